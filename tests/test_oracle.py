@@ -1,0 +1,299 @@
+"""Pins for the CPU oracle: each test checks it against something the paper or
+the mathematics fixes, not against itself.  No GPU needed."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2211_03339_amd import testmats as tm
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def res(A, V, W):
+    return np.linalg.norm(A @ V - V * W[None, :]) / np.linalg.norm(A)
+
+
+def orth(V):
+    return np.linalg.norm(V.T @ V - np.eye(V.shape[1]))
+
+
+# ---------------------------------------------------------------- 2x2 pins
+@pytest.mark.parametrize("a,d,b", [(1.0, 2.0, 0.5), (3.0, -1.0, 2.0), (0.0, 0.0, 1.0),
+                                   (1e-3, 1.0, -1e-9), (5.0, 5.0, -3.0), (-2.0, 7.0, 1e3)])
+def test_angle_closed_form(a, d, b):
+    """Lemma offa-jr: J^T A J has b_ij = 0 and b_ii^2 + b_jj^2 = a_ii^2 + a_jj^2 + 2a_ij^2;
+    the diagonal equals the closed-form 2x2 eigenvalues (a+d)/2 +- sqrt(((a-d)/2)^2 + b^2)."""
+    c, s, t = oracle.angle(a, d, b)
+    assert abs(c * c + s * s - 1) < 4e-16
+    assert abs(t - s / c) <= 4e-16 * abs(t) + 1e-300
+    assert abs(s) <= c + 1e-15            # |theta| <= pi/4: the smaller root
+    J = np.array([[c, s], [-s, c]])       # J(1,2;c,s) of the rotation definition
+    A = np.array([[a, b], [b, d]])
+    B = J.T @ A @ J
+    scale = abs(a) + abs(d) + abs(b)
+    assert abs(B[0, 1]) <= 8e-16 * scale
+    assert abs(B[0, 0] ** 2 + B[1, 1] ** 2 - (a * a + d * d + 2 * b * b)) <= 1e-14 * scale ** 2
+    r = np.sqrt(((a - d) / 2) ** 2 + b * b)
+    ev = sorted([(a + d) / 2 - r, (a + d) / 2 + r])
+    out = oracle.syev(A, tol=1e-300)
+    np.testing.assert_allclose(out.W, ev, rtol=0, atol=4e-16 * scale)
+
+
+def test_angle_zero_offdiag():
+    assert oracle.angle(1.0, 2.0, 0.0) == (1.0, 0.0, 0.0)
+
+
+def test_angle_huge_mu():
+    """mu beyond the overflow guard still yields t ~ 1/(2 mu)."""
+    c, s, t = oracle.angle(0.0, 1e200, 1e-200)
+    mu = 1e200 / 2e-200 if np.isfinite(1e200 / 2e-200) else np.inf
+    assert c == 1.0 and 0 < t < 1e-300 or (t == 0.0 and c == 1.0)
+
+
+# ---------------------------------------------------------------- full solves
+def test_toeplitz_tridiagonal():
+    """tridiag(1,0,1): lambda_k = 2cos(k pi/(n+1)), v_k(j) = sqrt(2/(n+1)) sin(j k pi/(n+1))."""
+    n = 40
+    A = np.diag(np.ones(n - 1), 1) + np.diag(np.ones(n - 1), -1)
+    r = oracle.syev(A)
+    k = np.arange(1, n + 1)
+    lam = np.sort(2 * np.cos(k * np.pi / (n + 1)))
+    np.testing.assert_allclose(r.W, lam, rtol=0, atol=1e-14)
+    j = np.arange(1, n + 1)
+    for col in range(n):
+        kk = n - col   # ascending order: the largest k has the smallest eigenvalue
+        v = np.sqrt(2.0 / (n + 1)) * np.sin(j * kk * np.pi / (n + 1))
+        assert min(np.linalg.norm(r.V[:, col] - v), np.linalg.norm(r.V[:, col] + v)) < 1e-13
+
+
+@pytest.mark.parametrize("order", ["row", "rr"])
+@pytest.mark.parametrize("kind", tm.SPECTRA)
+def test_known_spectrum(kind, order):
+    n = 96
+    A, lam = tm.sym_matrix(n, kind, seed=7)
+    r = oracle.syev(A, tol=1e-15, order=order)
+    assert r.info == 0
+    nrm2 = np.abs(lam).max()
+    assert np.abs(r.W - np.sort(lam)).max() <= 1e-13 * nrm2
+    assert res(A, r.V, r.W) <= 1e-14
+    assert orth(r.V) <= 1e-13
+    # invariants: trace and Frobenius norm are preserved by orthogonal similarity
+    assert abs(r.W.sum() - np.trace(A)) <= 1e-13 * np.abs(A).sum() / n
+    assert abs(np.sqrt((r.W ** 2).sum()) - np.linalg.norm(A)) <= 1e-14 * np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_brute_force_small(n):
+    """Tiny matrices against LAPACK's eigh (an independent library, run here)."""
+    g = tm.rng(1000 + n)
+    for _ in range(20):
+        G = g.standard_normal((n, n))
+        A = 0.5 * (G + G.T)
+        r = oracle.syev(A, tol=1e-16)
+        ref = np.linalg.eigh(A)[0]
+        np.testing.assert_allclose(r.W, ref, rtol=0, atol=1e-14 * max(1, np.abs(ref).max()))
+        assert res(A, r.V, r.W) < 1e-14 and orth(r.V) < 1e-14
+
+
+def test_empty_and_diagonal():
+    r = oracle.syev(np.zeros((0, 0)))
+    assert r.info == 0 and r.sweeps == 0
+    D = np.diag([3.0, -1.0, 2.0, 0.5])
+    r = oracle.syev(D)
+    assert r.sweeps == 0 and r.rotations == 0
+    np.testing.assert_array_equal(r.W, [-1.0, 0.5, 2.0, 3.0])
+    assert np.array_equal(np.abs(r.V), np.abs(np.eye(4)[:, [1, 3, 2, 0]]))
+
+
+def test_not_converged_flag():
+    A, _ = tm.sym_matrix(32, "uniform", seed=3)
+    r = oracle.syev(A, tol=1e-15, max_sweeps=1)
+    assert r.info == 1 and r.sweeps == 1
+
+
+def test_sweep_quadratic_shape():
+    """Section 3.3 (Theorem qc-de): once ||off|| < d/4 (d = smallest eigenvalue gap), one sweep
+    takes ||off|| to O(||off||^2 / d); checked on the relative off-norm history."""
+    A, lam = tm.sym_matrix(64, "uniform", seed=11)
+    r = oracle.syev(A, tol=1e-15)
+    nA = np.linalg.norm(A)
+    d = np.diff(np.sort(lam)).min() / nA
+    h = r.off_hist / nA
+    assert np.all(np.diff(h) < 0)
+    tail = [(h[i], h[i + 1]) for i in range(len(h) - 1) if 1e-13 < h[i] < d / 4]
+    assert tail, h
+    for a, b in tail:
+        assert b <= a * a / d + 1e-14
+
+
+# ---------------------------------------------------------------- ordering
+@pytest.mark.parametrize("n", [2, 4, 6, 8, 16, 34])
+def test_round_robin_schedule(n):
+    """Each step is a perfect matching; each pair appears exactly once per sweep."""
+    seen = set()
+    for r in range(n - 1):
+        p, q = oracle.round_robin(n, r)
+        assert np.all(p < q)
+        assert sorted(np.concatenate([p, q]).tolist()) == list(range(n))
+        for a, b in zip(p, q):
+            assert (a, b) not in seen
+            seen.add((int(a), int(b)))
+    assert len(seen) == n * (n - 1) // 2
+
+
+def test_parallel_step_properties():
+    """One step of disjoint rotations: each rotated pair is zeroed, entries outside the rotated
+    rows/columns keep their value (Lemma pqrk (i)), and a_pj^2 + a_qj^2 is preserved (iii)."""
+    n = 12
+    A, _ = tm.sym_matrix(n, "uniform", seed=5)
+    p, q = oracle.round_robin(n, 3)
+    p3, q3 = p[:3], q[:3]   # rotate only three pairs, the rest stay fixed
+    T, P, applied = oracle.parallel_step(A, np.eye(n), p3, q3, 0.0)
+    assert applied == 3
+    rot = set(np.concatenate([p3, q3]).tolist())
+    for a, b in zip(p3, q3):
+        assert T[a, b] == 0 and T[b, a] == 0
+    rest = [i for i in range(n) if i not in rot]
+    np.testing.assert_array_equal(T[np.ix_(rest, rest)], A[np.ix_(rest, rest)])
+    for a, b in zip(p3, q3):
+        for j in rest:
+            assert abs(T[a, j] ** 2 + T[b, j] ** 2 - A[a, j] ** 2 - A[b, j] ** 2) < 1e-15
+    np.testing.assert_allclose(P.T @ A @ P, T, atol=1e-14)
+    assert orth(P) < 1e-15
+
+
+def test_parallel_step_matches_sequential():
+    """Disjoint rotations commute: one parallel step equals applying them one at a time."""
+    n = 10
+    A, _ = tm.sym_matrix(n, "uniform", seed=6)
+    p, q = oracle.round_robin(n, 2)
+    T1, P1, _ = oracle.parallel_step(A, np.eye(n), p, q, 0.0)
+    T2, P2 = A.copy(), np.eye(n)
+    for a, b in zip(p[::-1], q[::-1]):
+        T2, P2, _ = oracle.parallel_step(T2, P2, [a], [b], 0.0)
+    np.testing.assert_allclose(T1, T2, atol=1e-15)
+    np.testing.assert_allclose(P1, P2, atol=1e-15)
+
+
+# ---------------------------------------------------------------- stages
+def test_mgs():
+    """MGS: Z = QR, Q^T Q = I, R upper triangular with positive diagonal; matches LAPACK QR
+    (sign-fixed) for a well-conditioned Z."""
+    g = tm.rng(9)
+    Z = g.standard_normal((50, 30))
+    Q, R, info = oracle.mgs(Z)
+    assert info == 0
+    np.testing.assert_allclose(Q @ R, Z, atol=1e-13)
+    assert np.linalg.norm(Q.T @ Q - np.eye(30)) < 1e-13
+    assert np.all(np.diag(R) > 0) and np.allclose(np.tril(R, -1), 0)
+    Qr, Rr = np.linalg.qr(Z)
+    sg = np.sign(np.diag(Rr))
+    np.testing.assert_allclose(Q, Qr * sg, atol=1e-13)
+
+
+def test_mgs_breakdown():
+    Z = np.ones((5, 3))
+    assert oracle.mgs(Z)[2] == 2
+
+
+def test_gemm_and_similarity():
+    g = tm.rng(10)
+    A = g.standard_normal((7, 5))
+    B = g.standard_normal((7, 4))
+    np.testing.assert_allclose(oracle.gemm(A, B, ta=True), A.T @ B, atol=1e-13)
+    np.testing.assert_allclose(oracle.gemm(B.T, A.T, tb=True), B.T @ A, atol=1e-13)
+    S, _ = tm.sym_matrix(9, "uniform", seed=1)
+    Q = tm.haar(9, g)
+    np.testing.assert_allclose(oracle.similarity(S, Q), Q.T @ S @ Q, atol=1e-14)
+
+
+def test_fp32_reference_accuracy():
+    """FP32 Jacobi: eigenvalues within a small multiple of n 2^-24 ||A||, eigenvectors
+    orthonormal to FP32 level (the Lemma symeig properties that Algorithm 4.1 relies on)."""
+    n = 64
+    A, lam = tm.sym_matrix(n, "uniform", seed=12)
+    r = oracle.syev_f32(A.astype(np.float32), tol=1e-6)
+    assert r.info == 0
+    nA = np.abs(lam).max()
+    assert np.abs(r.W.astype(np.float64) - np.sort(lam)).max() < 4 * n * oracle.U32 * nA
+    Z = r.V.astype(np.float64)
+    assert np.linalg.norm(Z.T @ Z - np.eye(n)) < 4 * n * oracle.U32
+
+
+@pytest.mark.parametrize("kind,max_sp", [("uniform", 3), ("geometric", 8)])
+def test_preconditioned_pipeline_bounds(kind, max_sp):
+    """Algorithm 4.1 steps 1-3 with the FP32 reference: ||Z - Q||_F = O(upsilon) (Lemma main),
+    ||off(Q^T A Q)||_F <= n ||A||_2 upsilon (Theorem evd-ubd with the Section 6 proxy bd), and
+    the FP64 sweeps then converge in a handful of sweeps to the known spectrum."""
+    n = 128
+    A, lam = tm.sym_matrix(n, kind, seed=13)
+    r32 = oracle.syev_f32(A.astype(np.float32), tol=1e-6)
+    Z = r32.V.astype(np.float64)
+    Q, R, info = oracle.mgs(Z)
+    assert info == 0
+    assert np.linalg.norm(Z - Q) < 4 * n * oracle.U32   # h1(n) upsilon, h1 modest in n
+    T0 = oracle.similarity(A, Q)
+    nrm2 = np.abs(lam).max()
+    assert oracle.off(T0) <= n * nrm2 * oracle.U32
+    out = oracle.jacobi_from(T0, Q, 1e-15, oracle.fro(A), order="rr")
+    assert out.info == 0 and out.sweeps <= max_sp
+    W = np.diag(out.T)
+    idx = np.argsort(W, kind="stable")
+    assert np.abs(W[idx] - np.sort(lam)).max() <= 1e-13 * nrm2
+    assert res(A, out.P[:, idx], W[idx]) < 1e-14
+    plain = oracle.syev(A, tol=1e-15, order="rr")
+    assert plain.sweeps > out.sweeps
+
+
+@pytest.mark.slow
+def test_table61_mode3():
+    """Table 6.1, Example 6.1 mode 3 (geometric), kappa = 1e3, n = 512: sweeps and applied
+    rotations of Algorithm 3.2 (plain) and Algorithm 4.1 (FP32 start) near the printed values;
+    residual and normalised orthogonality at the printed level."""
+    g = json.load(open(os.path.join(GOLDEN, "table61_n512.json")))
+    row = [r for r in g["rows"] if r["mode"] == 3][0]
+    n = g["n"]
+    N = n * (n - 1) / 2
+    A, lam = tm.example61(n, row["kappa"], 3, seed=61)
+    plain = oracle.syev(A)
+    assert abs(plain.sweeps - row["plain_sp"]) <= 1
+    assert abs(plain.rotations / N - row["plain_ju"]) <= 0.1 * row["plain_ju"]
+    assert res(A, plain.V, plain.W) < 2 * row["plain_res"]
+    assert orth(plain.V) / np.sqrt(n) < 2 * row["plain_orp"]
+    r32 = oracle.syev_f32(A.astype(np.float32), tol=1e-6)
+    Q, _, _ = oracle.mgs(r32.V.astype(np.float64))
+    out = oracle.jacobi_from(oracle.similarity(A, Q), Q, oracle.DEFAULT_TOL, oracle.fro(A),
+                             order="row")
+    assert abs(out.sweeps - row["pre_sp"]) <= 1
+    assert abs(out.rotations / N - row["pre_ju"]) <= 0.1 * row["pre_ju"]
+    W = np.diag(out.T)
+    assert res(A, out.P, W) < 2 * row["pre_res"]
+    assert orth(out.P) / np.sqrt(n) < 2 * row["pre_orp"]
+
+
+# ---------------------------------------------------------------- SVD
+def test_svd_known_singular_values():
+    """Algorithm 5.1: known sigma, U^T U = I, V^T V = I, A V = U Sigma (Lemma ortho-2c)."""
+    m, n = 60, 24
+    A, sig = tm.svd_case(m, n, decades=4.0, seed=21)
+    r = oracle.gesvd(A)
+    assert r.info == 0
+    np.testing.assert_allclose(r.S, sig, rtol=1e-12, atol=0)
+    assert np.linalg.norm(r.U.T @ r.U - np.eye(n)) < 1e-13
+    assert np.linalg.norm(r.V.T @ r.V - np.eye(n)) < 1e-13
+    assert np.linalg.norm(A @ r.V - r.U * r.S) / np.linalg.norm(A) < 1e-14
+    np.testing.assert_allclose(r.S, np.linalg.svd(A, compute_uv=False), rtol=1e-12)
+
+
+def test_svd_2col_rotation():
+    """Lemma ortho-2c on one pair: after the rotation the two columns are orthogonal and
+    ||b_i||^2 + ||b_j||^2 is preserved."""
+    g = tm.rng(22)
+    C = g.standard_normal((30, 2))
+    out = oracle.svd_onesided(C, np.eye(2), max_sweeps=1)
+    B = out.C
+    assert abs(B[:, 0] @ B[:, 1]) < 1e-14 * np.linalg.norm(C) ** 2
+    assert abs((B ** 2).sum() - (C ** 2).sum()) < 1e-13
