@@ -1,0 +1,155 @@
+/*
+ * jacobi.h -- C-ABI of libjacobi, an MI355X (gfx950) implementation of the
+ * mixed-precision preconditioned Jacobi method of Zhang & Bai, "A mixed
+ * precision preconditioned Jacobi method for the symmetric eigenvalue
+ * problem" (arXiv 2211.03339).
+ *
+ * Conventions (all entry points):
+ *  - Matrices are column-major FP64 (LAPACK layout): element (i,j) of X is
+ *    X[i + j*ldx].  Matrix/vector pointers are DEVICE pointers (hipMalloc'd or
+ *    a torch tensor's data pointer) unless an argument says "host".
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    Calls without the _batched suffix are synchronous: they return after the
+ *    results are written.
+ *  - Ownership: the caller owns every buffer it passes; the library never
+ *    frees or retains them.  The library allocates its own device workspace
+ *    (grow-only, kept until jac_release_workspace()).
+ *  - Return codes (LAPACK style): 0 success; -i the i-th argument is invalid
+ *    (counting from 1); +1 the iteration did not converge within max_sweeps
+ *    (outputs hold the last iterate); +2 the input contains NaN or Inf;
+ *    +3 modified Gram-Schmidt broke down (rank-deficient start);
+ *    +4 HIP/device error.  jac_last_error() describes the last failure.
+ *  - A (symmetric problems) must be exactly symmetric; both triangles are
+ *    read.  A is never written.
+ */
+#ifndef JACOBI_H
+#define JACOBI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Start of the FP64 Jacobi iteration (Algorithm 4.1 of the paper vs its
+ * Algorithm 3.2). */
+typedef enum {
+  JAC_PRECOND_NONE = 0, /* plain cyclic Jacobi from T = A, P = I (Algorithm 3.2) */
+  JAC_PRECOND_FP32 = 1, /* FP32 eigensolve -> FP64 MGS -> T = Q^T A Q (Algorithm 4.1) */
+  JAC_PRECOND_MLP = 2   /* learned warm start, FP32 solve as fallback */
+} jac_precond_t;
+
+/* How each sweep is carried out. */
+typedef enum {
+  JAC_VARIANT_AUTO = 0,
+  JAC_VARIANT_ELEMENT = 1, /* n/2 disjoint 2x2 rotations per parallel step */
+  JAC_VARIANT_BLOCKED = 2  /* 2b x 2b block rotations applied as GEMMs */
+} jac_variant_t;
+
+struct jac_mlp;
+
+typedef struct jac_opts {
+  int precond;         /* jac_precond_t; default (zeroed struct) = NONE */
+  int variant;         /* jac_variant_t */
+  int block_b;         /* block size b of the blocked variant; 0 = library choice */
+  int max_sweeps;      /* FP64 sweeps; <= 0 means 64 */
+  double fp32_tol;     /* FP32 stage stops at off(T32) <= fp32_tol ||A||_F; <= 0: default */
+  int fp32_max_sweeps; /* <= 0 means 30 */
+  const struct jac_mlp* mlp;  /* JAC_PRECOND_MLP: the network */
+  const float* theta;  /* JAC_PRECOND_MLP: device pointer to its input */
+  double fallback_tol; /* MLP start rejected if off(Q^T A Q)_F / ||A||_F > this; <= 0: 1e-2 */
+} jac_opts;
+
+#define JAC_HIST 65
+typedef struct jac_stats {
+  int sweeps;              /* FP64 sweeps executed (SP) */
+  int fp32_sweeps;         /* sweeps of the FP32 stage */
+  long long rotations;     /* FP64 rotations applied (JU = rotations / (n(n-1)/2)) */
+  long long fp32_rotations;
+  int used_fallback;       /* MLP start rejected, FP32 start used */
+  double nrmA;             /* ||A||_F */
+  double off0;             /* ||off(T_0)||_F before the first FP64 sweep */
+  double off_final;        /* ||off(T)||_F at return */
+  double off_hist[JAC_HIST]; /* ||off(T)||_F before sweep 1, after sweep 1, ... */
+  float stage_ms[8];       /* 0 low-precision start, 1 MGS, 2 Q^T A Q, 3 sweeps,
+                              4 output, 5 total, 6 norm/checks */
+  double step_ms;          /* HIP-event time of the FP64 sweep launches (rotation steps) */
+  long long step_launches; /* number of FP64 step launches timed in step_ms */
+  double fp32_step_ms;     /* same for the FP32 stage */
+  long long fp32_step_launches;
+} jac_stats;
+
+/* Symmetric eigendecomposition A = V diag(W) V^T by Algorithm 4.1
+ * (preconditioned, FP32 start) with the library's choice of sweep variant.
+ * A: n x n (lda >= max(1,n)), read only.  W: n eigenvalues, ascending.
+ * V: n x n (leading dimension n), column i pairs with W[i].
+ * tol: stop when ||off(T)||_F <= tol ||A||_F (tested before each sweep);
+ * tol <= 0 selects the paper's 20 * 2^-53.  sweeps_out (host, may be NULL):
+ * FP64 sweeps executed. */
+int syev_jacobi(const double* A, int n, int lda, double* W, double* V, double tol, int* sweeps_out);
+
+/* As syev_jacobi with explicit options, leading dimension of V, statistics
+ * (host pointer, may be NULL) and stream.  opts NULL = plain method. */
+int syev_jacobi_ex(const double* A, int n, int lda, double* W, double* V, int ldv, double tol,
+                   const jac_opts* opts, jac_stats* stats, void* stream);
+
+/* Resume / custom start (Algorithm 4.1 steps 2-4 from a given Q0): Q = MGS(Q0),
+ * T = Q^T A Q, sweeps.  Q0: n x n, ldq >= n, read only. */
+int syev_jacobi_warm(const double* A, int n, int lda, const double* Q0, int ldq, double* W, double* V,
+                     int ldv, double tol, const jac_opts* opts, jac_stats* stats, void* stream);
+
+/* ---- Stages of the path, callable on their own --------------------------- */
+
+/* Apply parallel round-robin steps r0 .. r0+nsteps-1 (Section 6.2 ordering,
+ * step r pairs the indices of ring positions i and ne-1-i, ne = n rounded up
+ * to even; see jac_round_robin_pairs) to the symmetric T (n x n, in place)
+ * and the columns of V (n x n, in place; may be NULL).  Angles follow Lemma
+ * offa-jr from T before each step; an entry with |t_pq| <= min(2^-53
+ * sqrt|t_pp t_qq|, skip_abs) is set to zero without a rotation (Remark dc).
+ * rotations (host, may be NULL) receives the number applied. */
+int jac_parallel_steps(double* T, int n, int ldt, double* V, int ldv, int r0, int nsteps,
+                       double skip_abs, long long* rotations, void* stream);
+
+/* Host: index pairs (p[i] < q[i], i < ne/2) of step r of the round-robin
+ * ordering for ne (even) indices. */
+int jac_round_robin_pairs(int ne, int r, int* p, int* q);
+
+/* FP64 modified Gram-Schmidt, in place: Q (m x n, m >= n, ldq >= m, m <= 8192)
+ * becomes orthonormal with the column order and signs of the input
+ * (Algorithm 4.1 step 2).  Returns +3 on a zero column. */
+int jac_mgs(double* Q, int m, int n, int ldq, void* stream);
+
+/* T = Q^T A Q (Algorithm 4.1 step 3), FP64: upper triangle computed, mirrored.
+ * A, Q, T: n x n. */
+int jac_similarity(const double* A, int n, int lda, const double* Q, int ldq, double* T, int ldt,
+                   void* stream);
+
+/* Low-precision step 1: FP32 eigenvectors of A (demoted to FP32), stored in
+ * FP64.  Z: n x n (ldz >= n); W (may be NULL): FP32 eigenvalues promoted,
+ * ascending, with Z's columns in the same order.  tol <= 0: default.
+ * sweeps (host, may be NULL). */
+int jac_eig_fp32(const double* A, int n, int lda, double* Z, int ldz, double* W, double tol,
+                 int max_sweeps, int* sweeps, void* stream);
+
+/* C = alpha op(A) op(B) + beta C on the matrix cores (FP64 / FP32). */
+int jac_gemm_f64(int transa, int transb, int m, int n, int k, double alpha, const double* A, int lda,
+                 const double* B, int ldb, double beta, double* C, int ldc, void* stream);
+int jac_gemm_f32(int transa, int transb, int m, int n, int k, float alpha, const float* A, int lda,
+                 const float* B, int ldb, float beta, float* C, int ldc, void* stream);
+
+/* ---- Housekeeping ---------------------------------------------------------- */
+
+/* Device workspace bytes a call of order n with these options would use. */
+size_t jac_workspace_bytes(int n, const jac_opts* opts);
+/* Free the library's device workspace (after all calls have returned). */
+void jac_release_workspace(void);
+/* Text of the last error in this thread ("" if none). */
+const char* jac_last_error(void);
+/* Library version string. */
+const char* jac_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JACOBI_H */

@@ -1,0 +1,660 @@
+// C-ABI entry points of libjacobi (declared in include/jacobi.h).
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "../../include/jacobi.h"
+#include "common.h"
+
+namespace jac {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+const char* last_error() { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ workspace
+struct Pool { void* ptr = nullptr; size_t bytes = 0; };
+static std::map<int, Pool> g_pools;
+static std::mutex g_pool_mu;
+
+void* workspace(size_t bytes) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  Pool& p = g_pools[dev];
+  if (bytes > p.bytes) {
+    if (p.ptr) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(p.ptr);
+      p.ptr = nullptr;
+      p.bytes = 0;
+    }
+    size_t want = align_up(bytes + bytes / 8, 1 << 20);
+    if (hipMalloc(&p.ptr, want) != hipSuccess) {
+      p.ptr = nullptr;
+      return nullptr;
+    }
+    p.bytes = want;
+  }
+  return p.ptr;
+}
+
+void release_workspace() {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : g_pools) {
+    if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    kv.second = Pool{};
+  }
+}
+
+static inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// ------------------------------------------------------------------ sizing
+constexpr int kMaxSweepsDefault = 64;
+constexpr int kRotSlots = 272;  // per-sweep rotation counters (>= max sweeps + 2)
+
+template <typename T>
+static size_t elem_bytes(int n) {
+  int ne = n + (n & 1), h = ne / 2;
+  long long nblk = (long long)h * (h + 1) / 2;
+  size_t b = 0;
+  b += 2 * align_up(nblk * sizeof(Blk<T>), 256);
+  b += 2 * align_up((size_t)h * sizeof(Ang<T>), 256);
+  return b;
+}
+
+static size_t syev_bytes(int n, int precond) {
+  size_t b = 0;
+  b += 4096 + 1024 * 8 + 2 * kRotSlots * 8 + align_up((size_t)n * 4, 256) + 256;
+  b += elem_bytes<double>(n);
+  b += align_up((size_t)n * n * 8, 256);           // Vw
+  b += align_up((size_t)n * 8, 256);               // d
+  if (precond != JAC_PRECOND_NONE) {
+    b += 2 * align_up((size_t)n * n * 8, 256);     // GEMM scratch W, T0
+    b += align_up(mgs_scratch_elems(n, n) * 8, 256);
+    b += elem_bytes<float>(n);
+    b += align_up((size_t)n * n * 4, 256);         // V32
+    b += align_up((size_t)n * n * 4, 256);         // A32
+    b += align_up((size_t)n * 4, 256);
+  }
+  return b + 64 * 256;
+}
+
+// Scalars block at the start of every workspace.
+struct Head {
+  double* scal;               // [0] off^2, [1] fro^2
+  double* partial;            // 1024 partial sums
+  unsigned long long* rot64;  // FP64 rotation counters
+  unsigned long long* rot32;  // FP32 rotation counters
+  int* flag;
+};
+
+static Head carve_head(Carve& c, int) {
+  Head h;
+  h.scal = c.take<double>(16);
+  h.partial = c.take<double>(1024);
+  h.rot64 = c.take<unsigned long long>(kRotSlots);
+  h.rot32 = c.take<unsigned long long>(kRotSlots);
+  h.flag = c.take<int>(16);
+  return h;
+}
+
+template <typename T>
+static void carve_elem(Carve& c, ElemState<T>& st, int n) {
+  st.n = n;
+  st.ne = n + (n & 1);
+  st.h = st.ne / 2;
+  st.nblk = (long long)st.h * (st.h + 1) / 2;
+  st.Tp[0] = c.take<Blk<T>>(st.nblk);
+  st.Tp[1] = c.take<Blk<T>>(st.nblk);
+  st.A[0] = c.take<Ang<T>>(st.h);
+  st.A[1] = c.take<Ang<T>>(st.h);
+  st.cur = 0;
+}
+
+// Run sweeps of the element-wise path until off <= tol*nrm or max_sweeps.
+// Returns 0 (converged), 1 (not converged), or an error code.  off history in
+// hist (host, may be NULL, length hist_len).
+template <typename T>
+static int elem_run(ElemState<T>& st, double tol, double nrm, int max_sweeps, hipStream_t s, int* sweeps_out,
+                    double* off_out, double* hist, int hist_len, long long* rot_out, double* step_ms = nullptr,
+                    long long* launches = nullptr) {
+  const int per = st.ne - 1;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (step_ms) {
+    JAC_HIP(hipEventCreate(&ea));
+    JAC_HIP(hipEventCreate(&eb));
+    *step_ms = 0;
+  }
+  JAC_HIP(hipMemsetAsync(st.rot, 0, kRotSlots * sizeof(unsigned long long), s));
+  int e = elem_init_angles<T>(st, 0, s);
+  if (e) return e;
+  double off2 = 0;
+  e = elem_offnorm2<T>(st, s);
+  if (e) return e;
+  JAC_HIP(hipMemcpyAsync(&off2, st.scalars, 8, hipMemcpyDeviceToHost, s));
+  JAC_HIP(hipStreamSynchronize(s));
+  double off = std::sqrt(off2);
+  if (hist && hist_len > 0) hist[0] = off;
+  int sweeps = 0;
+  if (max_sweeps > kRotSlots - 2) max_sweeps = kRotSlots - 2;
+  while (off > tol * nrm && sweeps < max_sweeps) {
+    if (ea) JAC_HIP(hipEventRecord(ea, s));
+    e = elem_steps<T>(st, (long long)sweeps * per, per, s);
+    if (e) return e;
+    if (eb) JAC_HIP(hipEventRecord(eb, s));
+    ++sweeps;
+    e = elem_offnorm2<T>(st, s);
+    if (e) return e;
+    JAC_HIP(hipMemcpyAsync(&off2, st.scalars, 8, hipMemcpyDeviceToHost, s));
+    JAC_HIP(hipStreamSynchronize(s));
+    if (ea) {
+      float ms = 0;
+      JAC_HIP(hipEventElapsedTime(&ms, ea, eb));
+      *step_ms += ms;
+    }
+    off = std::sqrt(off2);
+    if (hist && sweeps < hist_len) hist[sweeps] = off;
+    if (!(off == off)) break;
+  }
+  if (rot_out) {
+    std::vector<unsigned long long> cnt(kRotSlots);
+    JAC_HIP(hipMemcpyAsync(cnt.data(), st.rot, kRotSlots * 8, hipMemcpyDeviceToHost, s));
+    JAC_HIP(hipStreamSynchronize(s));
+    long long tot = 0;
+    for (int i = 0; i < sweeps; ++i) tot += (long long)cnt[i];
+    *rot_out = tot;
+  }
+  if (sweeps_out) *sweeps_out = sweeps;
+  if (off_out) *off_out = off;
+  if (launches) *launches = (long long)sweeps * per;
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+  return off > tol * nrm ? 1 : 0;
+}
+
+struct Timer {
+  hipEvent_t ev[8];
+  int used = 0;
+  hipStream_t s;
+  bool on;
+  Timer(hipStream_t st, bool enable) : s(st), on(enable) {
+    if (on)
+      for (int i = 0; i < 8; ++i) (void)hipEventCreate(&ev[i]);
+  }
+  ~Timer() {
+    if (on)
+      for (int i = 0; i < 8; ++i) (void)hipEventDestroy(ev[i]);
+  }
+  void mark(int i) {
+    if (on) (void)hipEventRecord(ev[i], s);
+  }
+  float ms(int a, int b) {
+    if (!on) return 0.f;
+    float t = 0;
+    (void)hipEventSynchronize(ev[b]);
+    (void)hipEventElapsedTime(&t, ev[a], ev[b]);
+    return t;
+  }
+};
+
+// FP32 stage (Algorithm 4.1 step 1): eigenvectors of fl32(A) by the FP32
+// element-wise round-robin Jacobi.  Z (FP64, n x n, ldz) receives them in
+// working (unsorted) order; d32 (device, may be NULL) the FP32 diagonal.
+static int fp32_stage(const double* A, int n, int lda, double nrmA, double tol32, int max32, double* Z, int ldz,
+                      float* d32, Carve& c, Head& hd, hipStream_t s, int* sweeps, long long* rots,
+                      double* step_ms = nullptr, long long* launches = nullptr) {
+  ElemState<float> st;
+  carve_elem(c, st, n);
+  float* A32 = c.take<float>((size_t)n * n);
+  float* V32 = c.take<float>((size_t)n * n);
+  st.V = V32;
+  st.ldv = n;
+  st.partial = hd.partial;
+  st.scalars = hd.scal;
+  st.rot = hd.rot32;
+  st.skip_abs = (float)(tol32 * nrmA / n);
+  int e = copy_convert<double, float>(A, n, n, lda, A32, n, s);
+  if (e) return e;
+  e = elem_pack_from<float>(st, A32, n, 0, s);
+  if (e) return e;
+  e = set_identity<float>(V32, n, n, s);
+  if (e) return e;
+  double off = 0;
+  e = elem_run<float>(st, tol32, nrmA, max32, s, sweeps, &off, nullptr, 0, rots, step_ms, launches);
+  if (e < 0 || e > 1) return e;
+  e = copy_convert<float, double>(V32, n, n, n, Z, ldz, s);
+  if (e) return e;
+  if (d32) {
+    e = elem_diag<float>(st, d32, s);
+    if (e) return e;
+  }
+  return 0;
+}
+
+// T = Q^T A Q with W = A Q, T = Q^T W, then T mirrored from its upper triangle.
+__global__ void mirror_upper_kernel(double* T, int n, int ldt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y;
+  if (i < n && i > j) T[i + (size_t)j * ldt] = T[j + (size_t)i * ldt];
+}
+
+static int similarity(const double* A, int n, int lda, const double* Q, int ldq, double* T, int ldt, double* W,
+                      hipStream_t s) {
+  int e = gemm<double>(false, false, n, n, n, 1.0, A, lda, Q, ldq, 0.0, W, n, s);
+  if (e) return e;
+  e = gemm<double>(true, false, n, n, n, 1.0, Q, ldq, W, n, 0.0, T, ldt, s);
+  if (e) return e;
+  hipLaunchKernelGGL(mirror_upper_kernel, dim3(cdiv(n, 256), n), dim3(256), 0, s, T, n, ldt);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
+static double default_tol(double tol) { return tol > 0 ? tol : 20.0 * 1.1102230246251565e-16; }
+
+// Shared driver of syev_jacobi_ex / syev_jacobi_warm.
+static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq, double* W, double* V, int ldv,
+                     double tol, const jac_opts* opts, jac_stats* stats, hipStream_t s) {
+  jac_opts o{};
+  if (opts) o = *opts;
+  if (Q0) o.precond = -1;  // custom start
+  const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : kMaxSweepsDefault;
+  tol = default_tol(tol);
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+  }
+  if (n == 0) return 0;
+  if (o.precond == JAC_PRECOND_MLP) {
+    set_error("syev_jacobi_ex: the learned start needs the MLP entry points");
+    return -8;
+  }
+  Timer tm(s, stats != nullptr);
+  tm.mark(0);
+  const int pre = o.precond;
+  void* ws = workspace(syev_bytes(n, pre == JAC_PRECOND_NONE ? 0 : 1));
+  if (!ws) {
+    set_error("syev_jacobi: workspace allocation failed");
+    return 4;
+  }
+  Carve c(ws);
+  Head hd = carve_head(c, n);
+  JAC_HIP(hipMemsetAsync(hd.flag, 0, 16 * sizeof(int), s));
+  int e = check_finite(A, n, n, lda, hd.flag, s);
+  if (e) return e;
+  e = fro2_f64(A, n, n, lda, hd.partial, hd.scal + 1, s);
+  if (e) return e;
+  double hs[2];
+  int hflag = 0;
+  JAC_HIP(hipMemcpyAsync(hs, hd.scal, 16, hipMemcpyDeviceToHost, s));
+  JAC_HIP(hipMemcpyAsync(&hflag, hd.flag, 4, hipMemcpyDeviceToHost, s));
+  JAC_HIP(hipStreamSynchronize(s));
+  if (hflag) {
+    set_error("syev_jacobi: A contains NaN or Inf");
+    return 2;
+  }
+  const double nrm = std::sqrt(hs[1]);
+  if (stats) stats->nrmA = nrm;
+  tm.mark(1);
+
+  ElemState<double> st;
+  carve_elem(c, st, n);
+  double* Vw = c.take<double>((size_t)n * n);
+  double* d = c.take<double>(n);
+  int* rank = c.take<int>(n);
+  st.V = Vw;
+  st.ldv = n;
+  st.partial = hd.partial;
+  st.scalars = hd.scal;
+  st.rot = hd.rot64;
+  st.skip_abs = tol * nrm / n;
+
+  float ms_pre = 0, ms_mgs = 0, ms_sim = 0;
+  if (pre == JAC_PRECOND_NONE || nrm == 0.0) {
+    e = elem_pack<double>(st, A, lda, 0, s);
+    if (e) return e;
+    e = set_identity<double>(Vw, n, n, s);
+    if (e) return e;
+    tm.mark(2);
+    tm.mark(3);
+    tm.mark(4);
+  } else {
+    double* Wg = c.take<double>((size_t)n * n);
+    double* T0 = c.take<double>((size_t)n * n);
+    double* mscr = c.take<double>(mgs_scratch_elems(n, n));
+    if (pre == JAC_PRECOND_FP32) {
+      double tol32 = o.fp32_tol > 0 ? o.fp32_tol : 1e-6;
+      int max32 = o.fp32_max_sweeps > 0 ? o.fp32_max_sweeps : 30;
+      int sw32 = 0;
+      long long r32 = 0;
+      double ms32 = 0;
+      long long l32 = 0;
+      e = fp32_stage(A, n, lda, nrm, tol32, max32, Vw, n, nullptr, c, hd, s, &sw32, &r32, stats ? &ms32 : nullptr,
+                     &l32);
+      if (e) return e;
+      if (stats) {
+        stats->fp32_sweeps = sw32;
+        stats->fp32_rotations = r32;
+        stats->fp32_step_ms = ms32;
+        stats->fp32_step_launches = l32;
+      }
+    } else {
+      e = copy_convert<double, double>(Q0, n, n, ldq, Vw, n, s);
+      if (e) return e;
+    }
+    tm.mark(2);
+    e = mgs_f64(Vw, n, n, n, mscr, hd.flag, s);
+    if (e) return e;
+    tm.mark(3);
+    e = similarity(A, n, lda, Vw, n, T0, n, Wg, s);
+    if (e) return e;
+    e = elem_pack<double>(st, T0, n, 0, s);
+    if (e) return e;
+    JAC_HIP(hipMemcpyAsync(&hflag, hd.flag, 4, hipMemcpyDeviceToHost, s));
+    JAC_HIP(hipStreamSynchronize(s));
+    if (hflag) {
+      set_error("syev_jacobi: modified Gram-Schmidt met a zero column");
+      return 3;
+    }
+    tm.mark(4);
+  }
+  int sweeps = 0;
+  double off = 0;
+  long long rots = 0;
+  double ms64 = 0;
+  long long l64 = 0;
+  int info = elem_run<double>(st, tol, nrm, max_sweeps, s, &sweeps, &off, stats ? stats->off_hist : nullptr,
+                              JAC_HIST, &rots, stats ? &ms64 : nullptr, &l64);
+  if (info < 0 || info > 1) return info;
+  tm.mark(5);
+  e = elem_diag<double>(st, d, s);
+  if (e) return e;
+  e = sort_eigs<double>(d, Vw, n, n, W, V, ldv, rank, s);
+  if (e) return e;
+  tm.mark(6);
+  JAC_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    stats->sweeps = sweeps;
+    stats->rotations = rots;
+    stats->step_ms = ms64;
+    stats->step_launches = l64;
+    stats->off0 = stats->off_hist[0];
+    stats->off_final = off;
+    stats->stage_ms[6] = tm.ms(0, 1);
+    stats->stage_ms[0] = tm.ms(1, 2);
+    stats->stage_ms[1] = tm.ms(2, 3);
+    stats->stage_ms[2] = tm.ms(3, 4);
+    stats->stage_ms[3] = tm.ms(4, 5);
+    stats->stage_ms[4] = tm.ms(5, 6);
+    stats->stage_ms[5] = tm.ms(0, 6);
+  }
+  (void)ms_pre; (void)ms_mgs; (void)ms_sim;
+  return info;
+}
+
+}  // namespace jac
+
+using namespace jac;
+
+static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+extern "C" {
+
+const char* jac_last_error(void) { return last_error(); }
+const char* jac_version(void) { return "libjacobi 0.1 (gfx950)"; }
+void jac_release_workspace(void) { release_workspace(); }
+
+size_t jac_workspace_bytes(int n, const jac_opts* opts) {
+  if (n <= 0) return 0;
+  int pre = opts ? opts->precond : 0;
+  return syev_bytes(n, pre);
+}
+
+int jac_round_robin_pairs(int ne, int r, int* p, int* q) {
+  if (ne < 2 || (ne & 1)) return -1;
+  if (r < 0) return -2;
+  if (!p) return -3;
+  if (!q) return -4;
+  RR rr(ne);
+  for (int k = 0; k < rr.h; ++k) {
+    int a = rr.index(k, r % (ne - 1)), b = rr.index(rr.h + k, r % (ne - 1));
+    p[k] = a < b ? a : b;
+    q[k] = a < b ? b : a;
+  }
+  return 0;
+}
+
+static int check_syev_args(const double* A, int n, int lda, double* W, double* V, int ldv, double tol) {
+  g_err.clear();
+  if (n < 0) { set_error("n < 0"); return -2; }
+  if (lda < (n > 1 ? n : 1)) { set_error("lda < max(1,n)"); return -3; }
+  if (n > 0 && !A) { set_error("A is NULL"); return -1; }
+  if (n > 0 && !W) { set_error("W is NULL"); return -4; }
+  if (n > 0 && !V) { set_error("V is NULL"); return -5; }
+  if (ldv < (n > 1 ? n : 1)) { set_error("ldv < max(1,n)"); return -6; }
+  if (tol != tol) { set_error("tol is NaN"); return -7; }
+  return 0;
+}
+
+int syev_jacobi_ex(const double* A, int n, int lda, double* W, double* V, int ldv, double tol,
+                   const jac_opts* opts, jac_stats* stats, void* stream) {
+  int e = check_syev_args(A, n, lda, W, V, ldv, tol);
+  if (e) return e;
+  return syev_impl(A, n, lda, nullptr, 0, W, V, ldv, tol, opts, stats, as_stream(stream));
+}
+
+int syev_jacobi(const double* A, int n, int lda, double* W, double* V, double tol, int* sweeps_out) {
+  jac_opts o{};
+  o.precond = JAC_PRECOND_FP32;
+  jac_stats st;
+  int e = check_syev_args(A, n, lda, W, V, n > 1 ? n : 1, tol);
+  if (e) return e;
+  e = syev_impl(A, n, lda, nullptr, 0, W, V, n > 1 ? n : 1, tol, &o, &st, nullptr);
+  if (sweeps_out) *sweeps_out = st.sweeps;
+  return e;
+}
+
+int syev_jacobi_warm(const double* A, int n, int lda, const double* Q0, int ldq, double* W, double* V, int ldv,
+                     double tol, const jac_opts* opts, jac_stats* stats, void* stream) {
+  g_err.clear();
+  if (n < 0) { set_error("n < 0"); return -2; }
+  if (lda < (n > 1 ? n : 1)) { set_error("lda < max(1,n)"); return -3; }
+  if (n > 0 && !A) { set_error("A is NULL"); return -1; }
+  if (n > 0 && !Q0) { set_error("Q0 is NULL"); return -4; }
+  if (ldq < (n > 1 ? n : 1)) { set_error("ldq < max(1,n)"); return -5; }
+  if (n > 0 && !W) { set_error("W is NULL"); return -6; }
+  if (n > 0 && !V) { set_error("V is NULL"); return -7; }
+  if (ldv < (n > 1 ? n : 1)) { set_error("ldv < max(1,n)"); return -8; }
+  if (tol != tol) { set_error("tol is NaN"); return -9; }
+  return syev_impl(A, n, lda, Q0, ldq, W, V, ldv, tol, opts, stats, as_stream(stream));
+}
+
+int jac_parallel_steps(double* T, int n, int ldt, double* V, int ldv, int r0, int nsteps, double skip_abs,
+                       long long* rotations, void* stream) {
+  g_err.clear();
+  if (!T && n > 0) { set_error("T is NULL"); return -1; }
+  if (n < 0) { set_error("n < 0"); return -2; }
+  if (ldt < (n > 1 ? n : 1)) { set_error("ldt < max(1,n)"); return -3; }
+  if (V && ldv < (n > 1 ? n : 1)) { set_error("ldv < max(1,n)"); return -5; }
+  if (r0 < 0) { set_error("r0 < 0"); return -6; }
+  if (nsteps < 0) { set_error("nsteps < 0"); return -7; }
+  if (!(skip_abs >= 0)) { set_error("skip_abs must be >= 0"); return -8; }
+  if (rotations) *rotations = 0;
+  if (n < 2 || nsteps == 0) return 0;
+  if ((long long)nsteps > (long long)(kRotSlots - 4) * (n + (n & 1) - 1)) {
+    set_error("nsteps too large for one call");
+    return -7;
+  }
+  hipStream_t s = as_stream(stream);
+  size_t need = 4096 + 1024 * 8 + 2 * kRotSlots * 8 + elem_bytes<double>(n) + 64 * 256 +
+                (V ? 0 : align_up((size_t)n * n * 8, 256));
+  void* ws = workspace(need);
+  if (!ws) { set_error("workspace allocation failed"); return 4; }
+  Carve c(ws);
+  Head hd = carve_head(c, n);
+  ElemState<double> st;
+  carve_elem(c, st, n);
+  double* Vd = V;
+  int ldvd = ldv;
+  if (!V) {
+    Vd = c.take<double>((size_t)n * n);
+    ldvd = n;
+    int e = set_identity<double>(Vd, n, n, s);
+    if (e) return e;
+  }
+  st.V = Vd;
+  st.ldv = ldvd;
+  st.partial = hd.partial;
+  st.scalars = hd.scal;
+  st.rot = hd.rot64;
+  st.skip_abs = skip_abs;
+  const int per = st.ne - 1;
+  const int r = r0 % per;
+  JAC_HIP(hipMemsetAsync(st.rot, 0, kRotSlots * 8, s));
+  int e = elem_pack<double>(st, T, ldt, r, s);
+  if (e) return e;
+  e = elem_init_angles<double>(st, r, s);
+  if (e) return e;
+  // Global step numbering starts at r, so the counters of the first sweep
+  // hold every step of this call as long as nsteps < kRotSlots * per.
+  e = elem_steps<double>(st, r, nsteps, s);
+  if (e) return e;
+  e = elem_unpack_dense<double>(st, (int)((r + (long long)nsteps) % per), T, ldt, s);
+  if (e) return e;
+  if (rotations) {
+    std::vector<unsigned long long> cnt(kRotSlots);
+    JAC_HIP(hipMemcpyAsync(cnt.data(), st.rot, kRotSlots * 8, hipMemcpyDeviceToHost, s));
+    JAC_HIP(hipStreamSynchronize(s));
+    // Count only the steps that were applied: angles of the step after the
+    // last one were computed but not used.
+    long long last = (long long)r + nsteps;  // global index of the unused step
+    long long tot = 0;
+    for (int i = 0; i < kRotSlots; ++i) tot += (long long)cnt[i];
+    // Recompute the unused step's count by running its angle kernel alone.
+    JAC_HIP(hipMemsetAsync(st.rot, 0, 8, s));
+    e = elem_init_angles<double>(st, (int)(last % per), s);
+    if (e) return e;
+    unsigned long long extra = 0;
+    JAC_HIP(hipMemcpyAsync(&extra, st.rot, 8, hipMemcpyDeviceToHost, s));
+    JAC_HIP(hipStreamSynchronize(s));
+    *rotations = tot - (long long)extra;
+  }
+  JAC_HIP(hipStreamSynchronize(s));
+  return 0;
+}
+
+int jac_mgs(double* Q, int m, int n, int ldq, void* stream) {
+  g_err.clear();
+  if (!Q && m > 0 && n > 0) { set_error("Q is NULL"); return -1; }
+  if (m < 0) { set_error("m < 0"); return -2; }
+  if (n < 0 || n > m) { set_error("need 0 <= n <= m"); return -3; }
+  if (ldq < (m > 1 ? m : 1)) { set_error("ldq < max(1,m)"); return -4; }
+  if (m > 8192) { set_error("m > 8192 is not supported"); return -2; }
+  if (n == 0) return 0;
+  hipStream_t s = as_stream(stream);
+  void* ws = workspace(align_up(mgs_scratch_elems(m, n) * 8, 256) + 4096);
+  if (!ws) { set_error("workspace allocation failed"); return 4; }
+  Carve c(ws);
+  int* flag = c.take<int>(16);
+  double* scr = c.take<double>(mgs_scratch_elems(m, n));
+  JAC_HIP(hipMemsetAsync(flag, 0, 64, s));
+  int e = mgs_f64(Q, m, n, ldq, scr, flag, s);
+  if (e) return e;
+  int hf = 0;
+  JAC_HIP(hipMemcpyAsync(&hf, flag, 4, hipMemcpyDeviceToHost, s));
+  JAC_HIP(hipStreamSynchronize(s));
+  if (hf) { set_error("modified Gram-Schmidt met a zero column"); return 3; }
+  return 0;
+}
+
+int jac_similarity(const double* A, int n, int lda, const double* Q, int ldq, double* T, int ldt, void* stream) {
+  g_err.clear();
+  if (!A && n > 0) { set_error("A is NULL"); return -1; }
+  if (n < 0) { set_error("n < 0"); return -2; }
+  if (lda < (n > 1 ? n : 1)) { set_error("lda < max(1,n)"); return -3; }
+  if (!Q && n > 0) { set_error("Q is NULL"); return -4; }
+  if (ldq < (n > 1 ? n : 1)) { set_error("ldq < max(1,n)"); return -5; }
+  if (!T && n > 0) { set_error("T is NULL"); return -6; }
+  if (ldt < (n > 1 ? n : 1)) { set_error("ldt < max(1,n)"); return -7; }
+  if (n == 0) return 0;
+  hipStream_t s = as_stream(stream);
+  void* ws = workspace(align_up((size_t)n * n * 8, 256) + 4096);
+  if (!ws) { set_error("workspace allocation failed"); return 4; }
+  Carve c(ws);
+  double* W = c.take<double>((size_t)n * n);
+  int e = similarity(A, n, lda, Q, ldq, T, ldt, W, s);
+  if (e) return e;
+  JAC_HIP(hipStreamSynchronize(s));
+  return 0;
+}
+
+int jac_eig_fp32(const double* A, int n, int lda, double* Z, int ldz, double* W, double tol, int max_sweeps,
+                 int* sweeps, void* stream) {
+  g_err.clear();
+  if (!A && n > 0) { set_error("A is NULL"); return -1; }
+  if (n < 0) { set_error("n < 0"); return -2; }
+  if (lda < (n > 1 ? n : 1)) { set_error("lda < max(1,n)"); return -3; }
+  if (!Z && n > 0) { set_error("Z is NULL"); return -4; }
+  if (ldz < (n > 1 ? n : 1)) { set_error("ldz < max(1,n)"); return -5; }
+  if (tol != tol) { set_error("tol is NaN"); return -7; }
+  if (sweeps) *sweeps = 0;
+  if (n == 0) return 0;
+  hipStream_t s = as_stream(stream);
+  size_t need = syev_bytes(n, 1) + align_up((size_t)n * n * 8, 256) + align_up((size_t)n * 8, 256);
+  void* ws = workspace(need);
+  if (!ws) { set_error("workspace allocation failed"); return 4; }
+  Carve c(ws);
+  Head hd = carve_head(c, n);
+  double* Zw = c.take<double>((size_t)n * n);
+  float* d32 = c.take<float>(n);
+  int* rank = c.take<int>(n);
+  int e = fro2_f64(A, n, n, lda, hd.partial, hd.scal + 1, s);
+  if (e) return e;
+  double f2 = 0;
+  JAC_HIP(hipMemcpyAsync(&f2, hd.scal + 1, 8, hipMemcpyDeviceToHost, s));
+  JAC_HIP(hipStreamSynchronize(s));
+  int sw = 0;
+  long long rots = 0;
+  e = fp32_stage(A, n, lda, std::sqrt(f2), tol > 0 ? tol : 1e-6, max_sweeps > 0 ? max_sweeps : 30, Zw, n, d32, c,
+                 hd, s, &sw, &rots);
+  if (e) return e;
+  if (W) {
+    // Z's columns in ascending order of the FP32 eigenvalues.
+    double* d64 = c.take<double>(n);
+    e = copy_convert<float, double>(d32, n, 1, n, d64, n, s);
+    if (e) return e;
+    e = sort_eigs<double>(d64, Zw, n, n, W, Z, ldz, rank, s);
+    if (e) return e;
+  } else {
+    e = copy_convert<double, double>(Zw, n, n, n, Z, ldz, s);
+    if (e) return e;
+  }
+  JAC_HIP(hipStreamSynchronize(s));
+  if (sweeps) *sweeps = sw;
+  return 0;
+}
+
+int jac_gemm_f64(int ta, int tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B,
+                 int ldb, double beta, double* C, int ldc, void* stream) {
+  g_err.clear();
+  if (m < 0 || n < 0 || k < 0) { set_error("negative size"); return -3; }
+  int e = gemm<double>(ta != 0, tb != 0, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, as_stream(stream));
+  if (e) return e;
+  JAC_HIP(hipStreamSynchronize(as_stream(stream)));
+  return 0;
+}
+
+int jac_gemm_f32(int ta, int tb, int m, int n, int k, float alpha, const float* A, int lda, const float* B,
+                 int ldb, float beta, float* C, int ldc, void* stream) {
+  g_err.clear();
+  if (m < 0 || n < 0 || k < 0) { set_error("negative size"); return -3; }
+  int e = gemm<float>(ta != 0, tb != 0, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, as_stream(stream));
+  if (e) return e;
+  JAC_HIP(hipStreamSynchronize(as_stream(stream)));
+  return 0;
+}
+
+}  // extern "C"

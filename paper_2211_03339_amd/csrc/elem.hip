@@ -1,0 +1,422 @@
+// Element-wise round-robin parallel Jacobi (Algorithm 3.2 / step 4 of
+// Algorithm 4.1 with the non-overlapping parallel ordering of Section 6.2).
+//
+// Data layout.  The working matrix T (symmetric, order ne = n rounded up to
+// even) is stored as the packed upper triangle of 2x2 "pair blocks" in
+// Brent-Luk slot order (see RR in common.h): block (k, l), k <= l, holds rows
+// (slot k, slot h+k) x columns (slot l, slot h+l), so every pair of the
+// current step is the diagonal block (k, k).  A step reads each stored block
+// once (32 B, coalesced), applies R_k^T B R_l (row pass with pair k, column
+// pass with pair l, tau form of the rotation; diagonal blocks use the t form of
+// Lemma offa-jr and get b_pq = 0), and scatters the four results to the slots
+// they occupy at the next step in the other ping-pong buffer.  Reads and
+// writes of T are therefore one pass over the stored triangle each, and the V
+// update (columns p, q of V in logical order, rotated in place) is one pass
+// over V: 8 n(n+1) + 16 n^2 bytes per step.
+//
+// One launch per step.  Its grid has three roles: (1) pair-block updates of T,
+// (2) "band" threads that recompute the few rotated entries feeding each new
+// diagonal block and produce the angles of the next step, (3) column-pair
+// updates of V with this step's angles.  No role reads what another writes in
+// the same launch, so the step is race-free without atomics on data.
+#include "common.h"
+
+namespace jac {
+
+template <typename T> __device__ __forceinline__ T fmaT(T a, T b, T c);
+template <> __device__ __forceinline__ double fmaT<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <> __device__ __forceinline__ float fmaT<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <typename T> __device__ __forceinline__ T sqrtT(T a);
+template <> __device__ __forceinline__ double sqrtT<double>(double a) { return __builtin_sqrt(a); }
+template <> __device__ __forceinline__ float sqrtT<float>(float a) { return __builtin_sqrtf(a); }
+template <typename T> __device__ __forceinline__ T absT(T a) { return a < T(0) ? -a : a; }
+
+// (x, y) <- (x - s (y + tau x), y + s (x - tau y)): columns (or rows) i, j of
+// J(i,j;c,s) applied from the right (left, transposed), tau = s / (1 + c).
+template <typename T>
+__device__ __forceinline__ void rot2(T& x, T& y, T s, T tau) {
+  T nx = fmaT(-s, fmaT(tau, x, y), x);
+  T ny = fmaT(s, fmaT(-tau, y, x), y);
+  x = nx;
+  y = ny;
+}
+
+template <typename T>
+__device__ __forceinline__ void rotate_block(Blk<T>& b, const Ang<T>& ak, const Ang<T>& al) {
+  rot2(b.tt, b.bt, ak.s, ak.tau);
+  rot2(b.tb, b.bb, ak.s, ak.tau);
+  rot2(b.tt, b.tb, al.s, al.tau);
+  rot2(b.bt, b.bb, al.s, al.tau);
+}
+
+template <typename T>
+__device__ __forceinline__ void rotate_diag(Blk<T>& b, const Ang<T>& a) {
+  T x = b.tb;
+  b.tt = fmaT(-a.t, x, b.tt);
+  b.bb = fmaT(a.t, x, b.bb);
+  b.tb = T(0);
+  b.bt = T(0);
+}
+
+// Angle of Lemma offa-jr for the pair whose top slot holds index ip and bottom
+// slot index iq, from the entries tt (top,top), bb (bottom,bottom), tb.  The
+// rotation is J(p, q) with p = min(ip, iq); the result is expressed in slot
+// roles (sign flipped when the top slot holds q).  Pairs with the padding
+// index, and negligible t_pq (Remark dc, capped by skip_abs), give the
+// identity.
+template <typename T>
+__device__ Ang<T> make_angle(T tt, T bb, T tb, int ip, int iq, int n, T skip_abs) {
+  Ang<T> a{T(0), T(0), T(0), T(0)};
+  if (ip >= n || iq >= n) return a;
+  bool flip = ip > iq;
+  T app = flip ? bb : tt, aqq = flip ? tt : bb, apq = tb;
+  if (apq == T(0)) return a;
+  T lim = Prec<T>::unit * sqrtT(absT(app * aqq));
+  if (skip_abs < lim) lim = skip_abs;
+  if (absT(apq) <= lim) return a;
+  T mu = (aqq - app) / (T(2) * apq);
+  T t;
+  if (absT(mu) > Prec<T>::bigmu) {
+    t = T(0.5) / mu;
+  } else if (mu >= T(0)) {
+    t = T(1) / (mu + sqrtT(T(1) + mu * mu));
+  } else {
+    t = T(1) / (mu - sqrtT(T(1) + mu * mu));
+  }
+  T c = T(1) / sqrtT(T(1) + t * t);
+  T s = t * c;
+  T tau = s / (T(1) + c);
+  if (flip) { s = -s; tau = -tau; t = -t; }
+  a.s = s; a.tau = tau; a.t = t; a.applied = T(1);
+  return a;
+}
+
+__device__ __forceinline__ void kl_from_g(long long g, int& k, int& l) {
+  double x = sqrt(8.0 * (double)g + 1.0);
+  long long L = (long long)((x - 1.0) * 0.5);
+  while (L * (L + 1) / 2 > g) --L;
+  while ((L + 1) * (L + 2) / 2 <= g) ++L;
+  l = (int)L;
+  k = (int)(g - L * (L + 1) / 2);
+}
+
+// Store the new value of the element at (slot a, slot b) of the next step.
+template <typename T>
+__device__ __forceinline__ void put(T* base, int h, int a, int b, T v) {
+  int ka = a < h ? a : a - h, ra = a < h ? 0 : 1;
+  int kb = b < h ? b : b - h, rb = b < h ? 0 : 1;
+  if (ka == kb) {
+    long long o = bidx(ka, ka) * 4;
+    if (ra == rb) {
+      base[o + (ra ? 3 : 0)] = v;
+    } else {
+      base[o + 1] = v;
+      base[o + 2] = v;
+    }
+  } else if (ka < kb) {
+    base[bidx(ka, kb) * 4 + ra * 2 + rb] = v;
+  } else {
+    base[bidx(kb, ka) * 4 + rb * 2 + ra] = v;
+  }
+}
+
+// Rotated value (this step) of the element at old slots (a, b).
+template <typename T>
+__device__ T rotated_old(const Blk<T>* __restrict__ Told, const Ang<T>* __restrict__ ang, int h,
+                         int a, int b) {
+  int ka = a < h ? a : a - h, ra = a < h ? 0 : 1;
+  int kb = b < h ? b : b - h, rb = b < h ? 0 : 1;
+  if (ka == kb) {
+    Blk<T> blk = Told[bidx(ka, ka)];
+    rotate_diag(blk, ang[ka]);
+    if (ra != rb) return T(0);
+    return ra ? blk.bb : blk.tt;
+  }
+  int k1 = ka < kb ? ka : kb, l1 = ka < kb ? kb : ka;
+  Blk<T> blk = Told[bidx(k1, l1)];
+  rotate_block(blk, ang[k1], ang[l1]);
+  int comp = ka < kb ? ra * 2 + rb : rb * 2 + ra;
+  return comp == 0 ? blk.tt : comp == 1 ? blk.tb : comp == 2 ? blk.bt : blk.bb;
+}
+
+constexpr int kThreads = 256;
+constexpr int kBPT = 2;    // pair blocks per thread
+constexpr int kRPT = 4;    // V rows per thread
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+elem_step_kernel(const Blk<T>* __restrict__ Told, Blk<T>* __restrict__ Tnew,
+                 const Ang<T>* __restrict__ ang, Ang<T>* __restrict__ ang_next,
+                 T* __restrict__ V, int ldv, int n, int ne, int r, long long gnext_sweep,
+                 long long nblk, int nwgT, int nwgB, int vchunks, T skip_abs,
+                 unsigned long long* __restrict__ rot) {
+  const RR rr(ne);
+  const int h = rr.h;
+  const int wg = blockIdx.x;
+  if (wg < nwgT) {
+    T* out = reinterpret_cast<T*>(Tnew);
+    long long g = (long long)wg * kThreads * kBPT + threadIdx.x;
+#pragma unroll
+    for (int it = 0; it < kBPT; ++it, g += kThreads) {
+      if (g >= nblk) break;
+      int k, l;
+      kl_from_g(g, k, l);
+      Blk<T> b = Told[g];
+      int nk = rr.newslot(k), nhk = rr.newslot(h + k);
+      if (k == l) {
+        rotate_diag(b, ang[k]);
+        put(out, h, nk, nk, b.tt);
+        put(out, h, nhk, nhk, b.bb);
+        put(out, h, nk, nhk, T(0));
+      } else {
+        rotate_block(b, ang[k], ang[l]);
+        int nl = rr.newslot(l), nhl = rr.newslot(h + l);
+        put(out, h, nk, nl, b.tt);
+        put(out, h, nk, nhl, b.tb);
+        put(out, h, nhk, nl, b.bt);
+        put(out, h, nhk, nhl, b.bb);
+      }
+    }
+  } else if (wg < nwgT + nwgB) {
+    int kp = (wg - nwgT) * kThreads + threadIdx.x;
+    bool applied = false;
+    if (kp < h) {
+      int a = rr.srcslot(kp), b = rr.srcslot(h + kp);
+      T tt = rotated_old(Told, ang, h, a, a);
+      T bb = rotated_old(Told, ang, h, b, b);
+      T tb = rotated_old(Told, ang, h, a, b);
+      int rn = (r + 1) % (ne - 1);
+      Ang<T> an = make_angle(tt, bb, tb, rr.index(kp, rn), rr.index(h + kp, rn), n, skip_abs);
+      ang_next[kp] = an;
+      applied = an.applied != T(0);
+    }
+    unsigned long long mask = __ballot(applied);
+    if ((threadIdx.x & 63) == 0 && mask) atomicAdd(&rot[gnext_sweep], (unsigned long long)__popcll(mask));
+  } else {
+    int w = wg - nwgT - nwgB;
+    int k = w / vchunks, chunk = w % vchunks;
+    Ang<T> a = ang[k];
+    if (a.applied == T(0)) return;
+    int ip = rr.index(k, r), iq = rr.index(h + k, r);
+    T* vp = V + (size_t)ip * ldv;
+    T* vq = V + (size_t)iq * ldv;
+    int i = chunk * kThreads * kRPT + threadIdx.x;
+#pragma unroll
+    for (int it = 0; it < kRPT; ++it, i += kThreads) {
+      if (i < n) {
+        T x = vp[i], y = vq[i];
+        rot2(x, y, a.s, a.tau);
+        vp[i] = x;
+        vq[i] = y;
+      }
+    }
+  }
+}
+
+// Angles of step r read straight from the packed T (no rotation pending).
+template <typename T>
+__global__ void elem_angles0_kernel(const Blk<T>* __restrict__ Tp, Ang<T>* __restrict__ ang, int n,
+                                    int ne, int r, T skip_abs, unsigned long long* __restrict__ rot) {
+  const RR rr(ne);
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  bool applied = false;
+  if (k < rr.h) {
+    Blk<T> b = Tp[bidx(k, k)];
+    Ang<T> a = make_angle(b.tt, b.bb, b.tb, rr.index(k, r), rr.index(rr.h + k, r), n, skip_abs);
+    ang[k] = a;
+    applied = a.applied != T(0);
+  }
+  unsigned long long mask = __ballot(applied);
+  if ((threadIdx.x & 63) == 0 && mask) atomicAdd(&rot[0], (unsigned long long)__popcll(mask));
+}
+
+// Pack a dense column-major matrix into the slot layout of step r.
+template <typename Tin, typename T>
+__global__ void elem_pack_kernel(const Tin* __restrict__ A, int lda, Blk<T>* __restrict__ Tp, int n,
+                                 int ne, int r, long long nblk) {
+  const RR rr(ne);
+  long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nblk) return;
+  int k, l;
+  kl_from_g(g, k, l);
+  int it = rr.index(k, r), ib = rr.index(rr.h + k, r);
+  int jt = rr.index(l, r), jb = rr.index(rr.h + l, r);
+  auto at = [&](int i, int j) -> T {
+    return (i < n && j < n) ? (T)A[i + (size_t)j * lda] : T(0);
+  };
+  Blk<T> b;
+  b.tt = at(it, jt);
+  b.tb = at(it, jb);
+  b.bt = at(ib, jt);
+  b.bb = at(ib, jb);
+  if (k == l) b.bt = b.tb;
+  Tp[g] = b;
+}
+
+// Off-norm: stored off-diagonal entries each stand for two entries of T.
+template <typename T>
+__global__ void elem_off_partial_kernel(const Blk<T>* __restrict__ Tp, long long nblk,
+                                        double* __restrict__ partial) {
+  __shared__ double red[kThreads / 64];
+  double acc = 0;
+  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < nblk;
+       g += (long long)gridDim.x * blockDim.x) {
+    int k, l;
+    kl_from_g(g, k, l);
+    Blk<T> b = Tp[g];
+    double tb = b.tb;
+    if (k == l) {
+      acc += 2.0 * tb * tb;
+    } else {
+      double tt = b.tt, bt = b.bt, bb = b.bb;
+      acc += 2.0 * (tt * tt + tb * tb + bt * bt + bb * bb);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+    partial[blockIdx.x] = s;
+  }
+}
+
+__global__ void sum_partials_kernel(const double* __restrict__ partial, int count,
+                                    double* __restrict__ out) {
+  __shared__ double red[1024 / 64];
+  double acc = 0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) acc += partial[i];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int w = 0; w < (int)(blockDim.x / 64); ++w) s += red[w];
+    *out = s;
+  }
+}
+
+template <typename T>
+__global__ void elem_unpack_kernel(const Blk<T>* __restrict__ Tp, int n, int ne, int r, long long nblk,
+                                   T* __restrict__ D, int ldd) {
+  const RR rr(ne);
+  long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nblk) return;
+  int k, l;
+  kl_from_g(g, k, l);
+  Blk<T> b = Tp[g];
+  int it = rr.index(k, r), ib = rr.index(rr.h + k, r);
+  int jt = rr.index(l, r), jb = rr.index(rr.h + l, r);
+  auto st = [&](int i, int j, T v) {
+    if (i < n && j < n) { D[i + (size_t)j * ldd] = v; D[j + (size_t)i * ldd] = v; }
+  };
+  st(it, jt, b.tt);
+  st(it, jb, b.tb);
+  st(ib, jt, k == l ? b.tb : b.bt);
+  st(ib, jb, b.bb);
+}
+
+template <typename T>
+__global__ void elem_diag_kernel(const Blk<T>* __restrict__ Tp, int n, int ne, T* __restrict__ d) {
+  const RR rr(ne);
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ne) return;
+  int k = s < rr.h ? s : s - rr.h;
+  Blk<T> b = Tp[bidx(k, k)];
+  int i = rr.index(s, 0);
+  if (i < n) d[i] = s < rr.h ? b.tt : b.bb;
+}
+
+// ------------------------------------------------------------------ host side
+static inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+template <typename T>
+int elem_pack(ElemState<T>& st, const double* A, int lda, int r, hipStream_t s) {
+  hipLaunchKernelGGL((elem_pack_kernel<double, T>), dim3(cdiv(st.nblk, 256)), dim3(256), 0, s, A, lda,
+                     st.Tp[st.cur], st.n, st.ne, r, st.nblk);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
+template <typename T>
+int elem_pack_from(ElemState<T>& st, const T* A, int lda, int r, hipStream_t s) {
+  hipLaunchKernelGGL((elem_pack_kernel<T, T>), dim3(cdiv(st.nblk, 256)), dim3(256), 0, s, A, lda,
+                     st.Tp[st.cur], st.n, st.ne, r, st.nblk);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
+template <typename T>
+int elem_init_angles(ElemState<T>& st, int r, hipStream_t s) {
+  hipLaunchKernelGGL((elem_angles0_kernel<T>), dim3(cdiv(st.h, 256)), dim3(256), 0, s, st.Tp[st.cur],
+                     st.A[st.cur], st.n, st.ne, r, st.skip_abs, st.rot);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
+// Run nsteps steps starting at global step gstep0 (step r = gstep0 mod (ne-1)
+// of sweep gstep0 / (ne-1)).  st.cur flips every step.
+template <typename T>
+int elem_steps(ElemState<T>& st, long long gstep0, int nsteps, hipStream_t s) {
+  const int per = st.ne - 1;
+  const int nwgT = cdiv(st.nblk, (long long)kThreads * kBPT);
+  const int nwgB = cdiv(st.h, kThreads);
+  const int vchunks = cdiv(st.n, kThreads * kRPT);
+  const int nwg = nwgT + nwgB + st.h * vchunks;
+  for (int i = 0; i < nsteps; ++i) {
+    long long g = gstep0 + i;
+    int r = (int)(g % per);
+    long long next_sweep = (g + 1) / per;
+    int c = st.cur;
+    hipLaunchKernelGGL((elem_step_kernel<T>), dim3(nwg), dim3(kThreads), 0, s, st.Tp[c], st.Tp[c ^ 1],
+                       st.A[c], st.A[c ^ 1], st.V, st.ldv, st.n, st.ne, r, next_sweep, st.nblk, nwgT,
+                       nwgB, vchunks, st.skip_abs, st.rot);
+    JAC_CHECK_LAUNCH();
+    st.cur = c ^ 1;
+  }
+  return 0;
+}
+
+template <typename T>
+int elem_offnorm2(ElemState<T>& st, hipStream_t s) {
+  int nwg = cdiv(st.nblk, kThreads);
+  if (nwg > 1024) nwg = 1024;
+  if (nwg < 1) nwg = 1;
+  hipLaunchKernelGGL((elem_off_partial_kernel<T>), dim3(nwg), dim3(kThreads), 0, s, st.Tp[st.cur],
+                     st.nblk, st.partial);
+  JAC_CHECK_LAUNCH();
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(1024), 0, s, st.partial, nwg, st.scalars);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
+template <typename T>
+int elem_unpack_dense(const ElemState<T>& st, int r, T* D, int ldd, hipStream_t s) {
+  hipLaunchKernelGGL((elem_unpack_kernel<T>), dim3(cdiv(st.nblk, 256)), dim3(256), 0, s, st.Tp[st.cur],
+                     st.n, st.ne, r, st.nblk, D, ldd);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
+template <typename T>
+int elem_diag(const ElemState<T>& st, T* d, hipStream_t s) {
+  hipLaunchKernelGGL((elem_diag_kernel<T>), dim3(cdiv(st.ne, 256)), dim3(256), 0, s, st.Tp[st.cur], st.n,
+                     st.ne, d);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
+#define INST(T)                                                                          \
+  template int elem_pack<T>(ElemState<T>&, const double*, int, int, hipStream_t);         \
+  template int elem_pack_from<T>(ElemState<T>&, const T*, int, int, hipStream_t);         \
+  template int elem_init_angles<T>(ElemState<T>&, int, hipStream_t);                      \
+  template int elem_steps<T>(ElemState<T>&, long long, int, hipStream_t);                 \
+  template int elem_offnorm2<T>(ElemState<T>&, hipStream_t);                              \
+  template int elem_unpack_dense<T>(const ElemState<T>&, int, T*, int, hipStream_t);      \
+  template int elem_diag<T>(const ElemState<T>&, T*, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace jac

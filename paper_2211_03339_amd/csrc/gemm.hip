@@ -1,0 +1,246 @@
+// Dense GEMM on the matrix cores: C = alpha op(A) op(B) + beta C, column-major.
+// FP64 uses v_mfma_f64_16x16x4f64, FP32 v_mfma_f32_16x16x4f32.  Both take one
+// A value (row i = lane % 16, k = lane / 16) and one B value (k = lane / 16,
+// column j = lane % 16) per lane and accumulate four C values per lane in
+// column lane % 16: accumulator r holds row 4 r + lane / 16 for FP64 and row
+// 4 (lane / 16) + r for FP32 (measured on gfx950).
+//
+// A workgroup of 4 waves (2 x 2) owns a BM x BN tile of C; each wave owns a
+// (BM/2) x (BN/2) sub-tile made of 16 x 16 MFMA tiles.  K advances in steps of
+// 16 through a double-buffered LDS stage (k-major, so the MFMA operand reads
+// are 16 consecutive elements per k).  Split-K (grid z) writes partial tiles
+// to a workspace that a second kernel sums in a fixed order.
+#include "common.h"
+
+namespace jac {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef f64x4 acc_t;
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<float> {
+  typedef f32x4 acc_t;
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int kBK = 16;
+constexpr int kPad = 4;
+
+template <typename T, int BM, int BN, bool TA, bool TB>
+__global__ void __launch_bounds__(256)
+gemm_kernel(int m, int n, int k, T alpha, const T* __restrict__ A, int lda, const T* __restrict__ B, int ldb,
+            T beta, T* __restrict__ C, int ldc, int kchunk, T* __restrict__ part) {
+  constexpr int WM = BM / 2, WN = BN / 2;        // wave tile
+  constexpr int TM = WM / 16, TN = WN / 16;      // MFMA tiles per wave
+  constexpr int LA = BM * kBK / 256;             // A elements loaded per thread
+  constexpr int LB = BN * kBK / 256;
+  __shared__ T As[2][kBK][BM + kPad];
+  __shared__ T Bs[2][kBK][BN + kPad];
+  typedef typename Mfma<T>::acc_t acc_t;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
+  const int kb = blockIdx.z * kchunk;
+  const int ke = min(k, kb + kchunk);
+
+  acc_t acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+  T ra[LA], rb[LB];
+  // op(A)[i][kk]: TA ? A[kk + i*lda] : A[i + kk*lda]
+  auto load_a = [&](int kt) {
+#pragma unroll
+    for (int e = 0; e < LA; ++e) {
+      int idx = tid + e * 256;
+      int ii, kk;
+      if (!TA) { ii = idx % BM; kk = idx / BM; } else { kk = idx % kBK; ii = idx / kBK; }
+      int gi = i0 + ii, gk = kt + kk;
+      ra[e] = (gi < m && gk < ke) ? (TA ? A[gk + (size_t)gi * lda] : A[gi + (size_t)gk * lda]) : T(0);
+    }
+  };
+  auto load_b = [&](int kt) {
+#pragma unroll
+    for (int e = 0; e < LB; ++e) {
+      int idx = tid + e * 256;
+      int jj, kk;
+      if (!TB) { kk = idx % kBK; jj = idx / kBK; } else { jj = idx % BN; kk = idx / BN; }
+      int gj = j0 + jj, gk = kt + kk;
+      rb[e] = (gj < n && gk < ke) ? (TB ? B[gj + (size_t)gk * ldb] : B[gk + (size_t)gj * ldb]) : T(0);
+    }
+  };
+  auto store_ab = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < LA; ++e) {
+      int idx = tid + e * 256;
+      int ii, kk;
+      if (!TA) { ii = idx % BM; kk = idx / BM; } else { kk = idx % kBK; ii = idx / kBK; }
+      As[buf][kk][ii] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < LB; ++e) {
+      int idx = tid + e * 256;
+      int jj, kk;
+      if (!TB) { kk = idx % kBK; jj = idx / kBK; } else { jj = idx % BN; kk = idx / BN; }
+      Bs[buf][kk][jj] = rb[e];
+    }
+  };
+
+  int buf = 0;
+  if (kb < ke) {
+    load_a(kb);
+    load_b(kb);
+    store_ab(0);
+  }
+  __syncthreads();
+  for (int kt = kb; kt < ke; kt += kBK) {
+    const bool more = kt + kBK < ke;
+    if (more) { load_a(kt + kBK); load_b(kt + kBK); }
+#pragma unroll
+    for (int kk = 0; kk < kBK; kk += 4) {
+      T av[TM], bv[TN];
+      const int kr = kk + (lane >> 4), cc = lane & 15;
+#pragma unroll
+      for (int a = 0; a < TM; ++a) av[a] = As[buf][kr][wm * WM + a * 16 + cc];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) bv[b] = Bs[buf][kr][wn * WN + b * 16 + cc];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = Mfma<T>::op(av[a], bv[b], acc[a][b]);
+    }
+    if (more) {
+      store_ab(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+  // Epilogue: accumulator r of a lane is row Mfma<T>::row(lane, r), column lane%16.
+  const int col = lane & 15;
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      int gj = j0 + wn * WN + b * 16 + col;
+      if (gj >= n) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int gi = i0 + wm * WM + a * 16 + Mfma<T>::row(lane, r);
+        if (gi >= m) continue;
+        T v = alpha * acc[a][b][r];
+        if (part) {
+          part[(size_t)blockIdx.z * m * n + gi + (size_t)gj * m] = v;
+        } else {
+          size_t o = gi + (size_t)gj * ldc;
+          C[o] = beta == T(0) ? v : v + beta * C[o];
+        }
+      }
+    }
+}
+
+template <typename T>
+__global__ void splitk_reduce_kernel(const T* __restrict__ part, int S, int m, int n, T beta, T* __restrict__ C,
+                                     int ldc) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y;
+  if (i >= m) return;
+  T acc = T(0);
+  for (int z = 0; z < S; ++z) acc += part[(size_t)z * m * n + i + (size_t)j * m];
+  size_t o = i + (size_t)j * ldc;
+  C[o] = beta == T(0) ? acc : acc + beta * C[o];
+}
+
+static inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+template <typename T, int BM, int BN>
+static void launch_cfg(bool ta, bool tb, dim3 grid, hipStream_t s, int m, int n, int k, T alpha, const T* A,
+                       int lda, const T* B, int ldb, T beta, T* C, int ldc, int kchunk, T* part) {
+#define L(TA_, TB_)                                                                                       \
+  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TA_, TB_>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, B, \
+                     ldb, beta, C, ldc, kchunk, part)
+  if (!ta && !tb) L(false, false);
+  else if (ta && !tb) L(true, false);
+  else if (!ta && tb) L(false, true);
+  else L(true, true);
+#undef L
+}
+
+// Scratch for split-K partial sums (library-owned, grow-only).
+static void* g_part = nullptr;
+static size_t g_part_bytes = 0;
+
+template <typename T>
+int gemm(bool ta, bool tb, int m, int n, int k, T alpha, const T* A, int lda, const T* B, int ldb, T beta,
+         T* C, int ldc, hipStream_t s) {
+  if (m <= 0 || n <= 0) return 0;
+  if (k <= 0) {
+    // C = beta C
+    if (beta == T(1)) return 0;
+    T* nul = nullptr;
+    hipLaunchKernelGGL((splitk_reduce_kernel<T>), dim3(cdiv(m, 256), n), dim3(256), 0, s, nul, 0, m, n, beta, C,
+                       ldc);
+    JAC_CHECK_LAUNCH();
+    return 0;
+  }
+  int cus = 256;
+  // Tile choice: large tiles for large outputs, small for skinny ones.
+  int BM = (m >= 1024 && n >= 1024) ? 128 : 64;
+  int BN = BM;
+  if (m <= 32) BM = 32;
+  if (n <= 32) BN = 32;
+  int tiles = cdiv(m, BM) * cdiv(n, BN);
+  int S = 1;
+  if (tiles < cus && k >= 512) {
+    S = cdiv(2 * cus, tiles);
+    int maxS = k / 256;
+    if (S > maxS) S = maxS;
+    if (S < 1) S = 1;
+  }
+  int kchunk = cdiv(cdiv(k, S), kBK) * kBK;
+  S = cdiv(k, kchunk);
+  T* part = nullptr;
+  if (S > 1) {
+    size_t need = (size_t)S * m * n * sizeof(T);
+    if (need > g_part_bytes) {
+      if (g_part) JAC_HIP(hipFree(g_part));
+      g_part = nullptr;
+      JAC_HIP(hipMalloc(&g_part, need));
+      g_part_bytes = need;
+    }
+    part = static_cast<T*>(g_part);
+  }
+  dim3 grid(cdiv(m, BM), cdiv(n, BN), S);
+  if (BM == 128 && BN == 128) launch_cfg<T, 128, 128>(ta, tb, grid, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
+  else if (BM == 64 && BN == 64) launch_cfg<T, 64, 64>(ta, tb, grid, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
+  else if (BM == 32 && BN == 64) launch_cfg<T, 32, 64>(ta, tb, grid, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
+  else if (BM == 64 && BN == 32) launch_cfg<T, 64, 32>(ta, tb, grid, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
+  else launch_cfg<T, 32, 32>(ta, tb, grid, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
+  JAC_CHECK_LAUNCH();
+  if (S > 1) {
+    hipLaunchKernelGGL((splitk_reduce_kernel<T>), dim3(cdiv(m, 256), n), dim3(256), 0, s, part, S, m, n, beta, C,
+                       ldc);
+    JAC_CHECK_LAUNCH();
+  }
+  return 0;
+}
+
+template int gemm<double>(bool, bool, int, int, int, double, const double*, int, const double*, int, double,
+                          double*, int, hipStream_t);
+template int gemm<float>(bool, bool, int, int, int, float, const float*, int, const float*, int, float, float*,
+                         int, hipStream_t);
+
+}  // namespace jac

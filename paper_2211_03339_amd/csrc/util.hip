@@ -1,0 +1,148 @@
+// Small device utilities: norms, conversions, identity, output ordering.
+#include "common.h"
+
+namespace jac {
+
+static inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// ||A||_F^2 partial sums, one per workgroup (deterministic: fixed grid, fixed
+// reduction tree), then a single-workgroup sum.
+__global__ void fro2_partial_kernel(const double* __restrict__ A, int m, int n, int lda,
+                                    double* __restrict__ partial) {
+  __shared__ double red[4];
+  double acc = 0;
+  long long total = (long long)m * n;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    int j = (int)(e / m), i = (int)(e % m);
+    double v = A[i + (size_t)j * lda];
+    acc += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void sum_partials_kernel2(const double* __restrict__ partial, int count,
+                                     double* __restrict__ out) {
+  __shared__ double red[16];
+  double acc = 0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) acc += partial[i];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int w = 0; w < (int)(blockDim.x / 64); ++w) s += red[w];
+    *out = s;
+  }
+}
+
+int fro2_f64(const double* A, int m, int n, int lda, double* partial, double* out, hipStream_t s) {
+  int nwg = cdiv((long long)m * n, 256);
+  if (nwg > 1024) nwg = 1024;
+  if (nwg < 1) nwg = 1;
+  hipLaunchKernelGGL(fro2_partial_kernel, dim3(nwg), dim3(256), 0, s, A, m, n, lda, partial);
+  JAC_CHECK_LAUNCH();
+  hipLaunchKernelGGL(sum_partials_kernel2, dim3(1), dim3(1024), 0, s, partial, nwg, out);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
+__global__ void finite_kernel(const double* __restrict__ A, int m, int n, int lda, int* flag) {
+  long long total = (long long)m * n;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    int j = (int)(e / m), i = (int)(e % m);
+    double v = A[i + (size_t)j * lda];
+    if (!(v - v == 0.0)) atomicOr(flag, 1);
+  }
+}
+
+int check_finite(const double* A, int m, int n, int lda, int* flag, hipStream_t s) {
+  int nwg = cdiv((long long)m * n, 256);
+  if (nwg > 1024) nwg = 1024;
+  if (nwg < 1) nwg = 1;
+  hipLaunchKernelGGL(finite_kernel, dim3(nwg), dim3(256), 0, s, A, m, n, lda, flag);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
+template <typename T>
+__global__ void identity_kernel(T* __restrict__ V, int n, int ldv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y;
+  if (i < n) V[i + (size_t)j * ldv] = i == j ? T(1) : T(0);
+}
+
+template <typename T>
+int set_identity(T* V, int n, int ldv, hipStream_t s) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL((identity_kernel<T>), dim3(cdiv(n, 256), n), dim3(256), 0, s, V, n, ldv);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
+template <typename Tin, typename Tout>
+__global__ void convert_kernel(const Tin* __restrict__ A, int m, int lda, Tout* __restrict__ B, int ldb) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y;
+  if (i < m) B[i + (size_t)j * ldb] = (Tout)A[i + (size_t)j * lda];
+}
+
+template <typename Tin, typename Tout>
+int copy_convert(const Tin* A, int m, int n, int lda, Tout* B, int ldb, hipStream_t s) {
+  if (m == 0 || n == 0) return 0;
+  hipLaunchKernelGGL((convert_kernel<Tin, Tout>), dim3(cdiv(m, 256), n), dim3(256), 0, s, A, m, lda, B, ldb);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
+// Ascending order with ties kept in index order: rank(i) = #{j : d_j < d_i or
+// (d_j == d_i and j < i)}.
+template <typename T>
+__global__ void rank_kernel(const T* __restrict__ d, int n, int* __restrict__ rank, double* __restrict__ W) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T di = d[i];
+  int r = 0;
+  for (int j = 0; j < n; ++j) {
+    T dj = d[j];
+    r += (dj < di) || (dj == di && j < i);
+  }
+  rank[i] = r;
+  W[r] = (double)di;
+}
+
+template <typename T>
+__global__ void permute_cols_kernel(const T* __restrict__ Vw, int ldw, const int* __restrict__ rank, int n,
+                                    double* __restrict__ Vout, int ldv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y;
+  if (i < n) Vout[i + (size_t)rank[j] * ldv] = (double)Vw[i + (size_t)j * ldw];
+}
+
+template <typename T>
+int sort_eigs(const T* d, const T* Vw, int n, int ldw, double* W, double* Vout, int ldv, int* rank,
+              hipStream_t s) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL((rank_kernel<T>), dim3(cdiv(n, 256)), dim3(256), 0, s, d, n, rank, W);
+  JAC_CHECK_LAUNCH();
+  if (Vout) {
+    hipLaunchKernelGGL((permute_cols_kernel<T>), dim3(cdiv(n, 256), n), dim3(256), 0, s, Vw, ldw, rank, n,
+                       Vout, ldv);
+    JAC_CHECK_LAUNCH();
+  }
+  return 0;
+}
+
+template int set_identity<double>(double*, int, int, hipStream_t);
+template int set_identity<float>(float*, int, int, hipStream_t);
+template int copy_convert<double, float>(const double*, int, int, int, float*, int, hipStream_t);
+template int copy_convert<float, double>(const float*, int, int, int, double*, int, hipStream_t);
+template int copy_convert<double, double>(const double*, int, int, int, double*, int, hipStream_t);
+template int sort_eigs<double>(const double*, const double*, int, int, double*, double*, int, int*, hipStream_t);
+template int sort_eigs<float>(const float*, const float*, int, int, double*, double*, int, int*, hipStream_t);
+
+}  // namespace jac

@@ -1,0 +1,282 @@
+"""Thin Python binding of libjacobi (include/jacobi.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Functions take and return torch tensors on the current HIP device;
+the current torch stream is passed to the library.  Matrices follow the usual
+torch (row-major) semantics at this level and are handed to the library in
+its column-major layout: a column-major M is stored as the row-major buffer of
+M^T, so symmetric inputs pass through unchanged and outputs are returned as
+transposed views.
+
+Importing this module never falls back to anything: if libjacobi.so is
+missing, load() raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjacobi.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "jacobi.h")
+
+PRECOND = {"none": 0, "fp32": 1, "mlp": 2}
+VARIANT = {"auto": 0, "element": 1, "blocked": 2}
+JAC_HIST = 65
+
+
+class JacOpts(ctypes.Structure):
+    _fields_ = [("precond", ctypes.c_int), ("variant", ctypes.c_int), ("block_b", ctypes.c_int),
+                ("max_sweeps", ctypes.c_int), ("fp32_tol", ctypes.c_double),
+                ("fp32_max_sweeps", ctypes.c_int), ("mlp", ctypes.c_void_p),
+                ("theta", ctypes.c_void_p), ("fallback_tol", ctypes.c_double)]
+
+
+class JacStats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int), ("fp32_sweeps", ctypes.c_int),
+                ("rotations", ctypes.c_longlong), ("fp32_rotations", ctypes.c_longlong),
+                ("used_fallback", ctypes.c_int), ("nrmA", ctypes.c_double),
+                ("off0", ctypes.c_double), ("off_final", ctypes.c_double),
+                ("off_hist", ctypes.c_double * JAC_HIST), ("stage_ms", ctypes.c_float * 8),
+                ("step_ms", ctypes.c_double), ("step_launches", ctypes.c_longlong),
+                ("fp32_step_ms", ctypes.c_double), ("fp32_step_launches", ctypes.c_longlong)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("off_hist", "stage_ms")}
+        d["off_hist"] = list(self.off_hist[: self.sweeps + 1])
+        d["stage_ms"] = dict(zip(["start", "mgs", "similarity", "sweeps", "output", "total", "checks"],
+                                 list(self.stage_ms)[:7]))
+        return d
+
+
+class JacobiError(RuntimeError):
+    def __init__(self, fn, code, msg):
+        super().__init__(f"{fn} returned {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+
+
+def load():
+    """Load libjacobi.so from the package directory (raises if it is absent)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "syev_jacobi": (_i, [_vp, _i, _i, _vp, _vp, _d, ctypes.POINTER(_i)]),
+        "syev_jacobi_ex": (_i, [_vp, _i, _i, _vp, _vp, _i, _d, ctypes.POINTER(JacOpts),
+                                ctypes.POINTER(JacStats), _vp]),
+        "syev_jacobi_warm": (_i, [_vp, _i, _i, _vp, _i, _vp, _vp, _i, _d, ctypes.POINTER(JacOpts),
+                                  ctypes.POINTER(JacStats), _vp]),
+        "jac_parallel_steps": (_i, [_vp, _i, _i, _vp, _i, _i, _i, _d,
+                                    ctypes.POINTER(ctypes.c_longlong), _vp]),
+        "jac_round_robin_pairs": (_i, [_i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+        "jac_mgs": (_i, [_vp, _i, _i, _i, _vp]),
+        "jac_similarity": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp]),
+        "jac_eig_fp32": (_i, [_vp, _i, _i, _vp, _i, _vp, _d, _i, ctypes.POINTER(_i), _vp]),
+        "jac_gemm_f64": (_i, [_i, _i, _i, _i, _i, _d, _vp, _i, _vp, _i, _d, _vp, _i, _vp]),
+        "jac_gemm_f32": (_i, [_i, _i, _i, _i, _i, ctypes.c_float, _vp, _i, _vp, _i, ctypes.c_float,
+                              _vp, _i, _vp]),
+        "jac_workspace_bytes": (ctypes.c_size_t, [_i, ctypes.POINTER(JacOpts)]),
+        "jac_release_workspace": (None, []),
+        "jac_last_error": (ctypes.c_char_p, []),
+        "jac_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def header_symbols():
+    """Function names declared in include/jacobi.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", txt)) - {"sizeof"})
+
+
+def last_error() -> str:
+    return load().jac_last_error().decode()
+
+
+def _check(fn, code, ok=(0,)):
+    if code not in ok:
+        raise JacobiError(fn, code, last_error())
+    return code
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(x: torch.Tensor, dtype=torch.float64):
+    if not x.is_cuda:
+        raise ValueError("expected a device tensor")
+    if x.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {x.dtype}")
+    return x
+
+
+def _colmajor(M: torch.Tensor) -> torch.Tensor:
+    """Buffer whose column-major reading is M (the row-major buffer of M^T)."""
+    return M.t().contiguous()
+
+
+def _opts(precond="fp32", variant="auto", block_b=0, max_sweeps=0, fp32_tol=0.0, fp32_max_sweeps=0,
+          fallback_tol=0.0):
+    o = JacOpts()
+    o.precond = PRECOND[precond] if isinstance(precond, str) else int(precond)
+    o.variant = VARIANT[variant] if isinstance(variant, str) else int(variant)
+    o.block_b = block_b
+    o.max_sweeps = max_sweeps
+    o.fp32_tol = fp32_tol
+    o.fp32_max_sweeps = fp32_max_sweeps
+    o.fallback_tol = fallback_tol
+    return o
+
+
+def syev_jacobi(A: torch.Tensor, tol: float = 0.0):
+    """Algorithm 4.1 (FP32 start), library's variant: returns (W, V, sweeps)."""
+    L = load()
+    A = _dev(A)
+    n = A.shape[0]
+    Ac = _colmajor(A)
+    W = torch.empty(n, dtype=torch.float64, device=A.device)
+    Vb = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    sw = ctypes.c_int(0)
+    torch.cuda.synchronize()
+    code = L.syev_jacobi(_vp(Ac.data_ptr()), n, max(n, 1), _vp(W.data_ptr()), _vp(Vb.data_ptr()), tol,
+                         ctypes.byref(sw))
+    _check("syev_jacobi", code, ok=(0, 1))
+    return W, Vb.t(), sw.value, code
+
+
+def syev_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", variant="auto", max_sweeps=0,
+                   fp32_tol=0.0, fp32_max_sweeps=0, block_b=0, allow_unconverged=False):
+    """Returns (W, V, stats dict, info)."""
+    L = load()
+    A = _dev(A)
+    n = A.shape[0]
+    Ac = _colmajor(A)
+    W = torch.empty(n, dtype=torch.float64, device=A.device)
+    Vb = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    o = _opts(precond, variant, block_b, max_sweeps, fp32_tol, fp32_max_sweeps)
+    st = JacStats()
+    code = L.syev_jacobi_ex(_vp(Ac.data_ptr()), n, max(n, 1), _vp(W.data_ptr()), _vp(Vb.data_ptr()),
+                            max(n, 1), tol, ctypes.byref(o), ctypes.byref(st), _stream())
+    _check("syev_jacobi_ex", code, ok=(0, 1) if allow_unconverged else (0,))
+    return W, Vb.t(), st.as_dict(), code
+
+
+def syev_jacobi_raw(A_ptr, n, lda, W_ptr, V_ptr, ldv, tol, opts: JacOpts, stats: JacStats | None = None,
+                    stream=None):
+    """Direct call with raw device pointers (used by the benchmark's timed loop)."""
+    L = load()
+    return L.syev_jacobi_ex(_vp(A_ptr), n, lda, _vp(W_ptr), _vp(V_ptr), ldv, tol, ctypes.byref(opts),
+                            ctypes.byref(stats) if stats is not None else None,
+                            stream if stream is not None else _stream())
+
+
+def syev_jacobi_warm(A: torch.Tensor, Q0: torch.Tensor, tol: float = 0.0, max_sweeps=0):
+    L = load()
+    A = _dev(A)
+    n = A.shape[0]
+    Ac = _colmajor(A)
+    Qc = _colmajor(_dev(Q0))
+    W = torch.empty(n, dtype=torch.float64, device=A.device)
+    Vb = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    o = _opts("fp32", "auto", 0, max_sweeps)
+    st = JacStats()
+    code = L.syev_jacobi_warm(_vp(Ac.data_ptr()), n, max(n, 1), _vp(Qc.data_ptr()), max(n, 1),
+                              _vp(W.data_ptr()), _vp(Vb.data_ptr()), max(n, 1), tol, ctypes.byref(o),
+                              ctypes.byref(st), _stream())
+    _check("syev_jacobi_warm", code)
+    return W, Vb.t(), st.as_dict(), code
+
+
+def jac_parallel_steps(T: torch.Tensor, V: torch.Tensor | None, r0: int, nsteps: int, skip_abs: float = 0.0):
+    """Apply round-robin steps r0.. to copies of T (symmetric) and V; returns (T, V, rotations)."""
+    L = load()
+    n = T.shape[0]
+    Tc = _colmajor(_dev(T))
+    Vc = None if V is None else _colmajor(_dev(V))
+    rot = ctypes.c_longlong(0)
+    code = L.jac_parallel_steps(_vp(Tc.data_ptr()), n, max(n, 1),
+                                None if Vc is None else _vp(Vc.data_ptr()), max(n, 1), r0, nsteps,
+                                skip_abs, ctypes.byref(rot), _stream())
+    _check("jac_parallel_steps", code)
+    return Tc.t(), None if Vc is None else Vc.t(), rot.value
+
+
+def jac_round_robin_pairs(ne: int, r: int):
+    L = load()
+    p = (ctypes.c_int * (ne // 2))()
+    q = (ctypes.c_int * (ne // 2))()
+    code = L.jac_round_robin_pairs(ne, r, p, q)
+    _check("jac_round_robin_pairs", code)
+    return list(p), list(q)
+
+
+def jac_mgs(Z: torch.Tensor):
+    """Modified Gram-Schmidt of the columns of Z (m x n); returns Q."""
+    L = load()
+    m, n = Z.shape
+    Qc = _colmajor(_dev(Z))
+    code = L.jac_mgs(_vp(Qc.data_ptr()), m, n, max(m, 1), _stream())
+    _check("jac_mgs", code)
+    return Qc.t()
+
+
+def jac_similarity(A: torch.Tensor, Q: torch.Tensor):
+    L = load()
+    n = A.shape[0]
+    Ac = _colmajor(_dev(A))
+    Qc = _colmajor(_dev(Q))
+    Tb = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    code = L.jac_similarity(_vp(Ac.data_ptr()), n, max(n, 1), _vp(Qc.data_ptr()), max(n, 1),
+                            _vp(Tb.data_ptr()), max(n, 1), _stream())
+    _check("jac_similarity", code)
+    return Tb.t()
+
+
+def jac_eig_fp32(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 0):
+    """FP32 step 1: returns (W ascending, Z with matching columns, sweeps)."""
+    L = load()
+    n = A.shape[0]
+    Ac = _colmajor(_dev(A))
+    W = torch.empty(n, dtype=torch.float64, device=A.device)
+    Zb = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    sw = ctypes.c_int(0)
+    code = L.jac_eig_fp32(_vp(Ac.data_ptr()), n, max(n, 1), _vp(Zb.data_ptr()), max(n, 1),
+                          _vp(W.data_ptr()), tol, max_sweeps, ctypes.byref(sw), _stream())
+    _check("jac_eig_fp32", code)
+    return W, Zb.t(), sw.value
+
+
+def jac_gemm(A: torch.Tensor, B: torch.Tensor, transa=False, transb=False):
+    """op(A) @ op(B) on the matrix cores (float64 or float32)."""
+    L = load()
+    dt = A.dtype
+    Ac = _colmajor(_dev(A, dt))
+    Bc = _colmajor(_dev(B, dt))
+    m = A.shape[1] if transa else A.shape[0]
+    k = A.shape[0] if transa else A.shape[1]
+    n = B.shape[0] if transb else B.shape[1]
+    Cb = torch.zeros((n, m), dtype=dt, device=A.device)
+    fn = L.jac_gemm_f64 if dt == torch.float64 else L.jac_gemm_f32
+    code = fn(int(transa), int(transb), m, n, k, 1.0, _vp(Ac.data_ptr()), max(A.shape[0], 1),
+              _vp(Bc.data_ptr()), max(B.shape[0], 1), 0.0, _vp(Cb.data_ptr()), max(m, 1), _stream())
+    _check("jac_gemm", code)
+    return Cb.t()
