@@ -1,0 +1,183 @@
+"""Benchmark: FP64 eigensolves/s of the preconditioned Jacobi pipeline at n = 2048.
+
+One step = one preconditioned solve (FP32 eigensolve -> FP64 MGS -> FP64 Q^T A Q -> FP64
+round-robin Jacobi sweeps) of each of three n = 2048 matrices A = Q diag(lambda) Q^T (Haar Q)
+with lambda ~ U[-1,1], a signed geometric spectrum 10^(-8 i/(n-1)), and ten clusters of width
+1e-6.  Inputs are resident in device memory before the timed region.  Printed beside it: plain
+FP64 Jacobi on the same matrices, sweep counts, residuals, the dominant kernel's roofline
+figure (HIP-event timed launches of the rotation-step kernel) and the CPU oracle timed on a
+bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 2048] [--variant auto]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP64 eigensolves/sec + Jacobi sweeps at n=2048: precond & MLP vs plain, resid<=1e-13"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def step_bytes(n: int, dtype_bytes: int) -> float:
+    """Algorithmic bytes of one element-wise parallel step: the symmetric T read and written
+    once (n(n+1)/2 entries each way) and V read and written once."""
+    return dtype_bytes * (n * (n + 1) + 2 * n * n)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--variant", default="auto")
+    ap.add_argument("--tol", type=float, default=0.0, help="<= 0: the paper's 20 * 2^-53")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-Jacobi comparison")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2211_03339_amd import jacobi
+    from paper_2211_03339_amd import testmats as tm
+
+    jacobi.load()
+    n = args.n
+    spectra = list(tm.SPECTRA)
+    log(f"[bench] generating {len(spectra)} matrices of order {n}")
+    mats = [tm.precond_case(n, k) for k in spectra]
+    dev = [torch.from_numpy(A).cuda() for A, _ in mats]   # symmetric: row/column-major agree
+    Ws = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in mats]
+    Vs = [torch.empty((n, n), dtype=torch.float64, device="cuda") for _ in mats]
+    stream = torch.cuda.current_stream()
+    sp = jacobi.ctypes.c_void_p(stream.cuda_stream)
+
+    def solve(i, precond, stats):
+        o = jacobi._opts(precond, args.variant)
+        code = jacobi.syev_jacobi_raw(dev[i].data_ptr(), n, n, Ws[i].data_ptr(), Vs[i].data_ptr(), n,
+                                      args.tol, o, stats, sp)
+        if code != 0:
+            raise RuntimeError(f"syev_jacobi_ex returned {code}: {jacobi.last_error()}")
+
+    stats = [jacobi.JacStats() for _ in mats]
+    for w in range(args.warmup):
+        for i in range(len(mats)):
+            solve(i, "fp32", stats[i])
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    agg = {"step_ms": 0.0, "launches": 0, "fp32_step_ms": 0.0, "fp32_launches": 0}
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        for i in range(len(mats)):
+            solve(i, "fp32", stats[i])
+            agg["step_ms"] += stats[i].step_ms
+            agg["launches"] += stats[i].step_launches
+            agg["fp32_step_ms"] += stats[i].fp32_step_ms
+            agg["fp32_launches"] += stats[i].fp32_step_launches
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s")
+    solves = args.steps * len(mats)
+    value = solves / elapsed
+
+    per_spec = {}
+    for i, (A, lam) in enumerate(mats):
+        W = Ws[i].cpu().numpy()
+        V = Vs[i].t().cpu().numpy()
+        res = float(np.linalg.norm(A @ V - V * W[None, :]) / np.linalg.norm(A))
+        orth = float(np.linalg.norm(V.T @ V - np.eye(n)))
+        lam_err = float(np.abs(W - np.sort(lam)).max() / np.abs(lam).max())
+        st = stats[i].as_dict()
+        per_spec[spectra[i]] = {"sweeps": st["sweeps"], "fp32_sweeps": st["fp32_sweeps"],
+                                "JU": round(st["rotations"] / (n * (n - 1) / 2), 3),
+                                "res": res, "orth": orth, "orth_over_sqrt_n": orth / np.sqrt(n),
+                                "lam_err_rel": lam_err,
+                                "stage_ms": {k2: round(v, 3) for k2, v in st["stage_ms"].items()}}
+    log(f"[bench] accuracy checked: {json.dumps({k: (v['res'], v['sweeps']) for k, v in per_spec.items()})}")
+
+    plain = None
+    if not args.no_plain:
+        pst = [jacobi.JacStats() for _ in mats]
+        solve(0, "none", pst[0])   # warm-up of the plain path
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(len(mats)):
+            solve(i, "none", pst[i])
+        torch.cuda.synchronize()
+        pt = time.perf_counter() - t1
+        plain = {"solves_per_s": len(mats) / pt,
+                 "sweeps": {spectra[i]: pst[i].sweeps for i in range(len(mats))},
+                 "speedup_precond_vs_plain": value / (len(mats) / pt)}
+        log(f"[bench] plain: {plain}")
+
+    # Roofline of the dominant kernel (rotation step, FP32 stage or FP64 sweeps).
+    if agg["fp32_step_ms"] >= agg["step_ms"] and agg["fp32_launches"] > 0:
+        ms, nl, db, kname = agg["fp32_step_ms"], agg["fp32_launches"], 4, "elem_step_kernel<float>"
+    else:
+        ms, nl, db, kname = agg["step_ms"], agg["launches"], 8, "elem_step_kernel<double>"
+    avg_s = ms / 1e3 / max(nl, 1)
+    bpl = step_bytes(n, db)
+    achieved = bpl / avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": kname, "avg_launch_us": round(avg_s * 1e6, 3),
+                "algorithmic_bytes_per_launch": bpl, "launches_timed": nl}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        ns = 512
+        A, lam = tm.precond_case(ns, "uniform")
+        log(f"[bench] CPU oracle sample: plain Jacobi, n={ns}")
+        tc = time.perf_counter()
+        r = oracle.syev(A, tol=args.tol if args.tol > 0 else oracle.DEFAULT_TOL)
+        dt = time.perf_counter() - tc
+        scale = (n / ns) ** 3
+        cpu = {"value": 1.0 / (dt * scale), "unit": "eigensolves/s", "cores": 1, "kind": "oracle",
+               "sample": f"one full oracle solve (cyclic Jacobi, FP64, 1 thread) of the {ns}x{ns} "
+                         f"U[-1,1] matrix of the same family: {dt:.2f} s, {r.sweeps} sweeps; "
+                         f"scaled by (n/{ns})^3 = {scale:.0f} to n={n}",
+               "cpu": _cpu_model()}
+
+    out = {"metric": METRIC, "value": round(value, 4), "unit": "eigensolves/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"preconditioned pipeline (FP32 eig -> FP64 MGS -> FP64 Q^T A Q -> "
+                                  f"FP64 round-robin Jacobi), n={n}, spectra U[-1,1] / signed geometric "
+                                  f"1e-8 / 10 clusters x 1e-6, one solve of each per step",
+                      "n": n, "solves_per_step": len(mats), "variant": args.variant,
+                      "tol": args.tol if args.tol > 0 else 20 * 2.0 ** -53},
+           "per_spectrum": per_spec, "plain": plain, "roofline": roofline, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip() + f" ({os.cpu_count()} logical CPUs)"
+    except OSError:
+        pass
+    return None
+
+
+if __name__ == "__main__":
+    main()

@@ -58,6 +58,7 @@ typedef struct jac_opts {
   const struct jac_mlp* mlp;  /* JAC_PRECOND_MLP: the network */
   const float* theta;  /* JAC_PRECOND_MLP: device pointer to its input */
   double fallback_tol; /* MLP start rejected if off(Q^T A Q)_F / ||A||_F > this; <= 0: 1e-2 */
+  int inner_sweeps;    /* blocked variant: cap on the sweeps of each 2b x 2b subproblem; <= 0: default */
 } jac_opts;
 
 #define JAC_HIST 65

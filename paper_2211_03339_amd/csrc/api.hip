@@ -67,8 +67,20 @@ static size_t elem_bytes(int n) {
   return b;
 }
 
+template <typename T>
+static size_t blk_bytes(int n) {
+  int np = blk_np(n), m = np / blk_b2();
+  size_t b = 0;
+  b += align_up((size_t)np * np * sizeof(T), 256);
+  b += align_up((size_t)n * np * sizeof(T), 256);
+  b += align_up((size_t)m * blk_b2() * blk_b2() * sizeof(T), 256);
+  b += align_up((size_t)m * sizeof(int), 256);
+  return b;
+}
+
 static size_t syev_bytes(int n, int precond) {
   size_t b = 0;
+  b += blk_bytes<double>(n) + (precond != JAC_PRECOND_NONE ? blk_bytes<float>(n) : 0);
   b += 4096 + 1024 * 8 + 2 * kRotSlots * 8 + align_up((size_t)n * 4, 256) + 256;
   b += elem_bytes<double>(n);
   b += align_up((size_t)n * n * 8, 256);           // Vw
@@ -177,6 +189,82 @@ static int elem_run(ElemState<T>& st, double tol, double nrm, int max_sweeps, hi
   return off > tol * nrm ? 1 : 0;
 }
 
+template <typename T>
+static void carve_blk(Carve& c, BlkState<T>& st, int n) {
+  st.n = n;
+  st.np = blk_np(n);
+  st.ldt = st.np;
+  st.Tm = c.take<T>((size_t)st.np * st.np);
+  st.nvr = n;
+  st.ldv = n > 1 ? n : 1;
+  st.V = c.take<T>((size_t)n * st.np);
+  st.W = c.take<T>((size_t)(st.np / blk_b2()) * blk_b2() * blk_b2());
+  st.ident = c.take<int>(st.np / blk_b2());
+}
+
+// Blocked sweeps until off <= tol*nrm or max_sweeps (same contract as elem_run).
+template <typename T>
+static int blk_run(BlkState<T>& st, double tol, double nrm, int max_sweeps, int max_inner, hipStream_t s,
+                   int* sweeps_out, double* off_out, double* hist, int hist_len, long long* rot_out,
+                   double* step_ms = nullptr, long long* launches = nullptr) {
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (step_ms) {
+    JAC_HIP(hipEventCreate(&ea));
+    JAC_HIP(hipEventCreate(&eb));
+    *step_ms = 0;
+  }
+  JAC_HIP(hipMemsetAsync(st.rot, 0, sizeof(unsigned long long), s));
+  double off2 = 0;
+  int e = blk_offnorm2<T>(st, s);
+  if (e) return e;
+  JAC_HIP(hipMemcpyAsync(&off2, st.scalars, 8, hipMemcpyDeviceToHost, s));
+  JAC_HIP(hipStreamSynchronize(s));
+  double off = std::sqrt(off2);
+  if (hist && hist_len > 0) hist[0] = off;
+  int sweeps = 0;
+  const int per = st.np / (blk_b2() / 2) - 1;
+  while (off > tol * nrm && sweeps < max_sweeps) {
+    if (ea) JAC_HIP(hipEventRecord(ea, s));
+    e = blk_sweep<T>(st, max_inner, s);
+    if (e) return e;
+    if (eb) JAC_HIP(hipEventRecord(eb, s));
+    ++sweeps;
+    e = blk_offnorm2<T>(st, s);
+    if (e) return e;
+    JAC_HIP(hipMemcpyAsync(&off2, st.scalars, 8, hipMemcpyDeviceToHost, s));
+    JAC_HIP(hipStreamSynchronize(s));
+    if (ea) {
+      float ms = 0;
+      JAC_HIP(hipEventElapsedTime(&ms, ea, eb));
+      *step_ms += ms;
+    }
+    off = std::sqrt(off2);
+    if (hist && sweeps < hist_len) hist[sweeps] = off;
+    if (!(off == off)) break;
+  }
+  if (rot_out) {
+    unsigned long long cnt = 0;
+    JAC_HIP(hipMemcpyAsync(&cnt, st.rot, 8, hipMemcpyDeviceToHost, s));
+    JAC_HIP(hipStreamSynchronize(s));
+    *rot_out = (long long)cnt;
+  }
+  if (sweeps_out) *sweeps_out = sweeps;
+  if (off_out) *off_out = off;
+  if (launches) *launches = (long long)sweeps * per * 2;
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+  return off > tol * nrm ? 1 : 0;
+}
+
+static bool use_blocked(int variant, int n) {
+  if (variant == JAC_VARIANT_ELEMENT) return false;
+  if (variant == JAC_VARIANT_BLOCKED) return true;
+  return n >= 2;
+}
+
+constexpr int kMaxInner64 = 4;
+constexpr int kMaxInner32 = 3;
+
 struct Timer {
   hipEvent_t ev[8];
   int used = 0;
@@ -207,7 +295,32 @@ struct Timer {
 // working (unsorted) order; d32 (device, may be NULL) the FP32 diagonal.
 static int fp32_stage(const double* A, int n, int lda, double nrmA, double tol32, int max32, double* Z, int ldz,
                       float* d32, Carve& c, Head& hd, hipStream_t s, int* sweeps, long long* rots,
-                      double* step_ms = nullptr, long long* launches = nullptr) {
+                      double* step_ms = nullptr, long long* launches = nullptr, int variant = 0,
+                      int inner = 0) {
+  if (use_blocked(variant, n)) {
+    BlkState<float> st;
+    carve_blk(c, st, n);
+    st.partial = hd.partial;
+    st.scalars = hd.scal;
+    st.rot = hd.rot32;
+    st.skip_abs = (float)(tol32 * nrmA / n);
+    int e = blk_load<float>(st, A, true, lda, s);
+    if (e) return e;
+    JAC_HIP(hipMemsetAsync(st.V, 0, (size_t)n * st.np * sizeof(float), s));
+    e = set_identity<float>(st.V, n, st.ldv, s);
+    if (e) return e;
+    double off = 0;
+    e = blk_run<float>(st, tol32, nrmA, max32, inner > 0 ? inner : kMaxInner32, s, sweeps, &off, nullptr, 0, rots,
+                       step_ms, launches);
+    if (e < 0 || e > 1) return e;
+    e = copy_convert<float, double>(st.V, n, n, st.ldv, Z, ldz, s);
+    if (e) return e;
+    if (d32) {
+      e = blk_diag<float>(st, d32, s);
+      if (e) return e;
+    }
+    return 0;
+  }
   ElemState<float> st;
   carve_elem(c, st, n);
   float* A32 = c.take<float>((size_t)n * n);
@@ -313,6 +426,7 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
   st.skip_abs = tol * nrm / n;
 
   float ms_pre = 0, ms_mgs = 0, ms_sim = 0;
+  double* T0p = nullptr;
   if (pre == JAC_PRECOND_NONE || nrm == 0.0) {
     e = elem_pack<double>(st, A, lda, 0, s);
     if (e) return e;
@@ -324,6 +438,7 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
   } else {
     double* Wg = c.take<double>((size_t)n * n);
     double* T0 = c.take<double>((size_t)n * n);
+    T0p = T0;
     double* mscr = c.take<double>(mgs_scratch_elems(n, n));
     if (pre == JAC_PRECOND_FP32) {
       double tol32 = o.fp32_tol > 0 ? o.fp32_tol : 1e-6;
@@ -333,7 +448,7 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
       double ms32 = 0;
       long long l32 = 0;
       e = fp32_stage(A, n, lda, nrm, tol32, max32, Vw, n, nullptr, c, hd, s, &sw32, &r32, stats ? &ms32 : nullptr,
-                     &l32);
+                     &l32, o.variant, o.inner_sweeps);
       if (e) return e;
       if (stats) {
         stats->fp32_sweeps = sw32;
@@ -366,13 +481,39 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
   long long rots = 0;
   double ms64 = 0;
   long long l64 = 0;
-  int info = elem_run<double>(st, tol, nrm, max_sweeps, s, &sweeps, &off, stats ? stats->off_hist : nullptr,
-                              JAC_HIST, &rots, stats ? &ms64 : nullptr, &l64);
+  int info;
+  const bool blocked = use_blocked(o.variant, n);
+  BlkState<double> bst;
+  if (blocked) {
+    carve_blk(c, bst, n);
+    bst.partial = hd.partial;
+    bst.scalars = hd.scal;
+    bst.rot = hd.rot64;
+    bst.skip_abs = tol * nrm / n;
+    const bool plain = (pre == JAC_PRECOND_NONE || nrm == 0.0);
+    e = blk_load<double>(bst, plain ? (const void*)A : (const void*)T0p, true, plain ? lda : n, s);
+    if (e) return e;
+    JAC_HIP(hipMemsetAsync(bst.V, 0, (size_t)n * bst.np * sizeof(double), s));
+    e = copy_convert<double, double>(Vw, n, n, n, bst.V, bst.ldv, s);
+    if (e) return e;
+    info = blk_run<double>(bst, tol, nrm, max_sweeps, o.inner_sweeps > 0 ? o.inner_sweeps : kMaxInner64, s,
+                           &sweeps, &off,
+                           stats ? stats->off_hist : nullptr, JAC_HIST, &rots, stats ? &ms64 : nullptr, &l64);
+  } else {
+    info = elem_run<double>(st, tol, nrm, max_sweeps, s, &sweeps, &off, stats ? stats->off_hist : nullptr,
+                            JAC_HIST, &rots, stats ? &ms64 : nullptr, &l64);
+  }
   if (info < 0 || info > 1) return info;
   tm.mark(5);
-  e = elem_diag<double>(st, d, s);
-  if (e) return e;
-  e = sort_eigs<double>(d, Vw, n, n, W, V, ldv, rank, s);
+  if (blocked) {
+    e = blk_diag<double>(bst, d, s);
+    if (e) return e;
+    e = sort_eigs<double>(d, bst.V, n, bst.ldv, W, V, ldv, rank, s);
+  } else {
+    e = elem_diag<double>(st, d, s);
+    if (e) return e;
+    e = sort_eigs<double>(d, Vw, n, n, W, V, ldv, rank, s);
+  }
   if (e) return e;
   tm.mark(6);
   JAC_HIP(hipStreamSynchronize(s));

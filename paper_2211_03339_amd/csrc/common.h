@@ -50,10 +50,12 @@ template <typename T> struct Prec;
 template <> struct Prec<double> {
   static constexpr double unit = 1.1102230246251565e-16;  // 2^-53
   static constexpr double bigmu = 1e150;
+  static constexpr double tiny = 1e-150;
 };
 template <> struct Prec<float> {
   static constexpr float unit = 5.9604644775390625e-08f;  // 2^-24
   static constexpr float bigmu = 1e18f;
+  static constexpr float tiny = 1e-18f;
 };
 
 // A 2x2 pair block: rows (top_k, bottom_k) x cols (top_l, bottom_l).
@@ -93,6 +95,95 @@ struct RR {
   }
 };
 
+// Matrix-core operations.  v_mfma_f64_16x16x4f64 and v_mfma_f32_16x16x4f32
+// take one A value (row lane % 16, k = lane / 16) and one B value (k = lane /
+// 16, column lane % 16) per lane and accumulate four C values per lane in
+// column lane % 16: accumulator r holds row 4 r + lane / 16 for FP64 and row
+// 4 (lane / 16) + r for FP32 (measured on gfx950).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef f64x4 acc_t;
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<float> {
+  typedef f32x4 acc_t;
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// Scalar helpers shared by the rotation kernels.
+template <typename T> __device__ __forceinline__ T fmaT(T a, T b, T c);
+template <> __device__ __forceinline__ double fmaT<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <> __device__ __forceinline__ float fmaT<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <typename T> __device__ __forceinline__ T sqrtT(T a);
+template <> __device__ __forceinline__ double sqrtT<double>(double a) { return __builtin_sqrt(a); }
+template <> __device__ __forceinline__ float sqrtT<float>(float a) { return __builtin_sqrtf(a); }
+template <typename T> __device__ __forceinline__ T absT(T a) { return a < T(0) ? -a : a; }
+
+// (x, y) <- (x - s (y + tau x), y + s (x - tau y)): columns (or rows) i, j of
+// J(i,j;c,s) applied from the right (left, transposed), tau = s / (1 + c).
+template <typename T>
+__device__ __forceinline__ void rot2(T& x, T& y, T s, T tau) {
+  T nx = fmaT(-s, fmaT(tau, x, y), x);
+  T ny = fmaT(s, fmaT(-tau, y, x), y);
+  x = nx;
+  y = ny;
+}
+
+// Angle of Lemma offa-jr for the pair whose "top" member holds index ip and
+// "bottom" member index iq, from the entries tt (top,top), bb (bottom,bottom),
+// tb.  The rotation is J(p, q) with p = min(ip, iq); the result is expressed in
+// top/bottom roles (sign flipped when the top member is q).  Pairs with an
+// index >= n (padding), and negligible t_pq (Remark dc: |t_pq| <= u
+// sqrt|t_pp t_qq|, capped by skip_abs), give the identity.
+template <typename T>
+__device__ __forceinline__ Ang<T> make_angle(T tt, T bb, T tb, int ip, int iq, int n, T skip_abs) {
+  Ang<T> a{T(0), T(0), T(0), T(0)};
+  if (ip >= n || iq >= n) return a;
+  bool flip = ip > iq;
+  T app = flip ? bb : tt, aqq = flip ? tt : bb, apq = tb;
+  if (apq == T(0)) return a;
+  // Remark dc, compared in squares: apq^2 <= min(u^2 |app aqq|, skip_abs^2).
+  T lim2 = Prec<T>::unit * Prec<T>::unit * absT(app * aqq);
+  T sk2 = skip_abs * skip_abs;
+  if (sk2 < lim2) lim2 = sk2;
+  if (apq * apq <= lim2) return a;
+  // Lemma offa-jr: t = sign(mu) / (|mu| + sqrt(1 + mu^2)), mu = d / (2 apq),
+  // d = aqq - app, written as t = sign(d) 2 apq / (|d| + sqrt(d^2 + 4 apq^2))
+  // (t = 1 when d = 0).  Then c = 1/r, s = t/r, tau = s/(1+c) = t/(1+r) with
+  // r = sqrt(1 + t^2).
+  T d = aqq - app, t;
+  T num = T(2) * apq;
+  const T ad = absT(d), an = absT(num);
+  if (d == T(0)) {
+    t = T(1);
+  } else if (ad > Prec<T>::bigmu || an > Prec<T>::bigmu || ad < Prec<T>::tiny || an < Prec<T>::tiny) {
+    // magnitudes where d^2 + 4 apq^2 could overflow or underflow: the mu form
+    T mu = d / num;
+    if (absT(mu) > Prec<T>::bigmu) t = T(0.5) / mu;
+    else t = mu >= T(0) ? T(1) / (mu + sqrtT(T(1) + mu * mu)) : T(1) / (mu - sqrtT(T(1) + mu * mu));
+  } else {
+    T rr = sqrtT(fmaT(d, d, num * num));
+    t = (d > T(0) ? num : -num) / (absT(d) + rr);
+  }
+  T r = sqrtT(fmaT(t, t, T(1)));
+  T c = T(1) / r;
+  T s = t / r;
+  T tau = t / (T(1) + r);
+  (void)c;
+  if (flip) { s = -s; tau = -tau; t = -t; }
+  a.s = s; a.tau = tau; a.t = t; a.applied = T(1);
+  return a;
+}
+
 // Packed upper triangle of pair blocks: block (k, l), k <= l.
 __host__ __device__ inline long long bidx(int k, int l) { return (long long)l * (l + 1) / 2 + k; }
 
@@ -128,6 +219,32 @@ template <typename T>
 int elem_unpack_dense(const ElemState<T>& st, int r, T* D, int ldd, hipStream_t s);
 template <typename T>
 int elem_diag(const ElemState<T>& st, T* d, hipStream_t s);  // logical-order diagonal
+
+// Blocked path (blocked.hip): in-place np x np T, blocks of b = blk_b2()/2.
+template <typename T>
+struct BlkState {
+  int n, np;
+  T* Tm;                // np x np, leading dimension ldt
+  int ldt;
+  T* V;                 // nvr x np, leading dimension ldv (pad columns zero)
+  int ldv, nvr;
+  T* W;                 // (np / blk_b2()) accumulated 2b x 2b rotations
+  int* ident;           // per pair: W is exactly I
+  T skip_abs;
+  double* partial;      // >= 1024
+  double* scalars;      // [0] off^2
+  unsigned long long* rot;  // applied rotations (cumulative)
+};
+int blk_np(int n);
+int blk_b2();
+template <typename T>
+int blk_load(BlkState<T>& st, const void* A, bool a_is_double, int lda, hipStream_t s);
+template <typename T>
+int blk_offnorm2(BlkState<T>& st, hipStream_t s);
+template <typename T>
+int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s);
+template <typename T>
+int blk_diag(const BlkState<T>& st, T* d, hipStream_t s);
 
 // Utilities (util.hip).
 int fro2_f64(const double* A, int m, int n, int lda, double* partial, double* out, hipStream_t s);

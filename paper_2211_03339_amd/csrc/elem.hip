@@ -23,24 +23,6 @@
 
 namespace jac {
 
-template <typename T> __device__ __forceinline__ T fmaT(T a, T b, T c);
-template <> __device__ __forceinline__ double fmaT<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
-template <> __device__ __forceinline__ float fmaT<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-template <typename T> __device__ __forceinline__ T sqrtT(T a);
-template <> __device__ __forceinline__ double sqrtT<double>(double a) { return __builtin_sqrt(a); }
-template <> __device__ __forceinline__ float sqrtT<float>(float a) { return __builtin_sqrtf(a); }
-template <typename T> __device__ __forceinline__ T absT(T a) { return a < T(0) ? -a : a; }
-
-// (x, y) <- (x - s (y + tau x), y + s (x - tau y)): columns (or rows) i, j of
-// J(i,j;c,s) applied from the right (left, transposed), tau = s / (1 + c).
-template <typename T>
-__device__ __forceinline__ void rot2(T& x, T& y, T s, T tau) {
-  T nx = fmaT(-s, fmaT(tau, x, y), x);
-  T ny = fmaT(s, fmaT(-tau, y, x), y);
-  x = nx;
-  y = ny;
-}
-
 template <typename T>
 __device__ __forceinline__ void rotate_block(Blk<T>& b, const Ang<T>& ak, const Ang<T>& al) {
   rot2(b.tt, b.bt, ak.s, ak.tau);
@@ -56,39 +38,6 @@ __device__ __forceinline__ void rotate_diag(Blk<T>& b, const Ang<T>& a) {
   b.bb = fmaT(a.t, x, b.bb);
   b.tb = T(0);
   b.bt = T(0);
-}
-
-// Angle of Lemma offa-jr for the pair whose top slot holds index ip and bottom
-// slot index iq, from the entries tt (top,top), bb (bottom,bottom), tb.  The
-// rotation is J(p, q) with p = min(ip, iq); the result is expressed in slot
-// roles (sign flipped when the top slot holds q).  Pairs with the padding
-// index, and negligible t_pq (Remark dc, capped by skip_abs), give the
-// identity.
-template <typename T>
-__device__ Ang<T> make_angle(T tt, T bb, T tb, int ip, int iq, int n, T skip_abs) {
-  Ang<T> a{T(0), T(0), T(0), T(0)};
-  if (ip >= n || iq >= n) return a;
-  bool flip = ip > iq;
-  T app = flip ? bb : tt, aqq = flip ? tt : bb, apq = tb;
-  if (apq == T(0)) return a;
-  T lim = Prec<T>::unit * sqrtT(absT(app * aqq));
-  if (skip_abs < lim) lim = skip_abs;
-  if (absT(apq) <= lim) return a;
-  T mu = (aqq - app) / (T(2) * apq);
-  T t;
-  if (absT(mu) > Prec<T>::bigmu) {
-    t = T(0.5) / mu;
-  } else if (mu >= T(0)) {
-    t = T(1) / (mu + sqrtT(T(1) + mu * mu));
-  } else {
-    t = T(1) / (mu - sqrtT(T(1) + mu * mu));
-  }
-  T c = T(1) / sqrtT(T(1) + t * t);
-  T s = t * c;
-  T tau = s / (T(1) + c);
-  if (flip) { s = -s; tau = -tau; t = -t; }
-  a.s = s; a.tau = tau; a.t = t; a.applied = T(1);
-  return a;
 }
 
 __device__ __forceinline__ void kl_from_g(long long g, int& k, int& l) {

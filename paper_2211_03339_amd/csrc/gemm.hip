@@ -14,25 +14,6 @@
 
 namespace jac {
 
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct Mfma;
-template <> struct Mfma<double> {
-  typedef f64x4 acc_t;
-  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
-  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-};
-template <> struct Mfma<float> {
-  typedef f32x4 acc_t;
-  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-};
-
 constexpr int kBK = 16;
 constexpr int kPad = 4;
 

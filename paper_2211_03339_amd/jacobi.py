@@ -32,7 +32,8 @@ class JacOpts(ctypes.Structure):
     _fields_ = [("precond", ctypes.c_int), ("variant", ctypes.c_int), ("block_b", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("fp32_tol", ctypes.c_double),
                 ("fp32_max_sweeps", ctypes.c_int), ("mlp", ctypes.c_void_p),
-                ("theta", ctypes.c_void_p), ("fallback_tol", ctypes.c_double)]
+                ("theta", ctypes.c_void_p), ("fallback_tol", ctypes.c_double),
+                ("inner_sweeps", ctypes.c_int)]
 
 
 class JacStats(ctypes.Structure):
@@ -135,7 +136,7 @@ def _colmajor(M: torch.Tensor) -> torch.Tensor:
 
 
 def _opts(precond="fp32", variant="auto", block_b=0, max_sweeps=0, fp32_tol=0.0, fp32_max_sweeps=0,
-          fallback_tol=0.0):
+          fallback_tol=0.0, inner_sweeps=0):
     o = JacOpts()
     o.precond = PRECOND[precond] if isinstance(precond, str) else int(precond)
     o.variant = VARIANT[variant] if isinstance(variant, str) else int(variant)
@@ -144,6 +145,7 @@ def _opts(precond="fp32", variant="auto", block_b=0, max_sweeps=0, fp32_tol=0.0,
     o.fp32_tol = fp32_tol
     o.fp32_max_sweeps = fp32_max_sweeps
     o.fallback_tol = fallback_tol
+    o.inner_sweeps = inner_sweeps
     return o
 
 
@@ -164,7 +166,7 @@ def syev_jacobi(A: torch.Tensor, tol: float = 0.0):
 
 
 def syev_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", variant="auto", max_sweeps=0,
-                   fp32_tol=0.0, fp32_max_sweeps=0, block_b=0, allow_unconverged=False):
+                   fp32_tol=0.0, fp32_max_sweeps=0, block_b=0, allow_unconverged=False, inner_sweeps=0):
     """Returns (W, V, stats dict, info)."""
     L = load()
     A = _dev(A)
@@ -172,7 +174,7 @@ def syev_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", variant="a
     Ac = _colmajor(A)
     W = torch.empty(n, dtype=torch.float64, device=A.device)
     Vb = torch.empty((n, n), dtype=torch.float64, device=A.device)
-    o = _opts(precond, variant, block_b, max_sweeps, fp32_tol, fp32_max_sweeps)
+    o = _opts(precond, variant, block_b, max_sweeps, fp32_tol, fp32_max_sweeps, inner_sweeps=inner_sweeps)
     st = JacStats()
     code = L.syev_jacobi_ex(_vp(Ac.data_ptr()), n, max(n, 1), _vp(W.data_ptr()), _vp(Vb.data_ptr()),
                             max(n, 1), tol, ctypes.byref(o), ctypes.byref(st), _stream())
