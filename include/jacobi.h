@@ -99,6 +99,23 @@ int syev_jacobi_ex(const double* A, int n, int lda, double* W, double* V, int ld
 int syev_jacobi_warm(const double* A, int n, int lda, const double* Q0, int ldq, double* W, double* V,
                      int ldv, double tol, const jac_opts* opts, jac_stats* stats, void* stream);
 
+/* Thin SVD A = U diag(S) V^T of an m x n matrix (m >= n, full column rank) by
+ * the preconditioned one-sided Jacobi method (Algorithm 5.2): FP32 right
+ * singular vectors (eigenvectors of the FP32 Gram A^T A), FP64 MGS, C = A Q,
+ * V = Q, then one-sided sweeps (Lemma ortho-2c) on column pairs of C and V
+ * until a sweep applies fewer than 2e-4 n(n-1)/2 rotations.  A pair is rotated
+ * only when |c_i.c_j| > m tol ||c_i|| ||c_j||; tol <= 0 selects 2^-53.
+ * A: m x n (lda >= m), read only.  S: n singular values, descending.
+ * U: m x n (ldu >= m), u_j = c_j / s_j.  V: n x n (ldv >= n).
+ * sweeps_out (host, may be NULL). */
+int gesvd_jacobi(const double* A, int m, int n, int lda, double* S, double* U, int ldu, double* V, int ldv,
+                 double tol, int* sweeps_out);
+
+/* As gesvd_jacobi with options (precond NONE = Algorithm 5.1 from C = A,
+ * V = I), statistics (off_hist[s] = rotations applied in sweep s) and stream. */
+int gesvd_jacobi_ex(const double* A, int m, int n, int lda, double* S, double* U, int ldu, double* V, int ldv,
+                    double tol, const jac_opts* opts, jac_stats* stats, void* stream);
+
 /* ---- Stages of the path, callable on their own --------------------------- */
 
 /* Apply parallel round-robin steps r0 .. r0+nsteps-1 (Section 6.2 ordering,

@@ -293,8 +293,8 @@ struct Timer {
 // FP32 stage (Algorithm 4.1 step 1): eigenvectors of fl32(A) by the FP32
 // element-wise round-robin Jacobi.  Z (FP64, n x n, ldz) receives them in
 // working (unsorted) order; d32 (device, may be NULL) the FP32 diagonal.
-static int fp32_stage(const double* A, int n, int lda, double nrmA, double tol32, int max32, double* Z, int ldz,
-                      float* d32, Carve& c, Head& hd, hipStream_t s, int* sweeps, long long* rots,
+static int fp32_stage(const void* A, bool a_dbl, int n, int lda, double nrmA, double tol32, int max32, double* Z,
+                      int ldz, float* d32, Carve& c, Head& hd, hipStream_t s, int* sweeps, long long* rots,
                       double* step_ms = nullptr, long long* launches = nullptr, int variant = 0,
                       int inner = 0) {
   if (use_blocked(variant, n)) {
@@ -304,7 +304,7 @@ static int fp32_stage(const double* A, int n, int lda, double nrmA, double tol32
     st.scalars = hd.scal;
     st.rot = hd.rot32;
     st.skip_abs = (float)(tol32 * nrmA / n);
-    int e = blk_load<float>(st, A, true, lda, s);
+    int e = blk_load<float>(st, A, a_dbl, lda, s);
     if (e) return e;
     JAC_HIP(hipMemsetAsync(st.V, 0, (size_t)n * st.np * sizeof(float), s));
     e = set_identity<float>(st.V, n, st.ldv, s);
@@ -331,7 +331,8 @@ static int fp32_stage(const double* A, int n, int lda, double nrmA, double tol32
   st.scalars = hd.scal;
   st.rot = hd.rot32;
   st.skip_abs = (float)(tol32 * nrmA / n);
-  int e = copy_convert<double, float>(A, n, n, lda, A32, n, s);
+  int e = a_dbl ? copy_convert<double, float>((const double*)A, n, n, lda, A32, n, s)
+                : copy_convert<float, float>((const float*)A, n, n, lda, A32, n, s);
   if (e) return e;
   e = elem_pack_from<float>(st, A32, n, 0, s);
   if (e) return e;
@@ -447,8 +448,8 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
       long long r32 = 0;
       double ms32 = 0;
       long long l32 = 0;
-      e = fp32_stage(A, n, lda, nrm, tol32, max32, Vw, n, nullptr, c, hd, s, &sw32, &r32, stats ? &ms32 : nullptr,
-                     &l32, o.variant, o.inner_sweeps);
+      e = fp32_stage(A, true, n, lda, nrm, tol32, max32, Vw, n, nullptr, c, hd, s, &sw32, &r32,
+                     stats ? &ms32 : nullptr, &l32, o.variant, o.inner_sweeps);
       if (e) return e;
       if (stats) {
         stats->fp32_sweeps = sw32;
@@ -536,6 +537,171 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
   return info;
 }
 
+
+// ------------------------------------------------------------------ one-sided SVD
+static int svd_gsplit(int m, int npair) {
+  int g = 512 / (npair > 0 ? npair : 1);
+  int gmax = m / 128 > 1 ? m / 128 : 1;
+  if (g > gmax) g = gmax;
+  if (g < 1) g = 1;
+  return g;
+}
+
+static size_t gesvd_bytes(int m, int n, int precond) {
+  int np = blk_np(n), npair = np / blk_b2();
+  int g = svd_gsplit(m, npair);
+  size_t b = 4096 + 1024 * 8 + 2 * kRotSlots * 8 + 64 * 256;
+  b += align_up((size_t)m * np * 8, 256);                       // C
+  b += align_up((size_t)n * np * 8, 256);                       // V work
+  b += align_up((size_t)npair * blk_b2() * blk_b2() * 8, 256);  // E
+  b += align_up((size_t)npair * 4, 256);
+  b += align_up((size_t)g * npair * blk_b2() * blk_b2() * 8, 256);  // Gram partials
+  b += 2 * align_up((size_t)n * 8, 256);
+  if (precond != JAC_PRECOND_NONE) {
+    b += align_up((size_t)m * n * 4, 256) + align_up((size_t)n * n * 4, 256);  // A32, G32
+    b += align_up((size_t)n * n * 8, 256);                                      // Z / Q
+    b += align_up(mgs_scratch_elems(n, n) * 8, 256);
+    b += syev_bytes(n, 1);                                                      // FP32 eig work
+  }
+  return b;
+}
+
+__global__ void zero_cols_kernel(double* C, int m, int ldc, int c0) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) C[i + (size_t)(c0 + blockIdx.y) * ldc] = 0.0;
+}
+
+static int gesvd_impl(const double* A, int m, int n, int lda, double* S, double* U, int ldu, double* V, int ldv,
+                      double tol, const jac_opts* opts, jac_stats* stats, hipStream_t s) {
+  jac_opts o{};
+  if (opts) o = *opts;
+  const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : kMaxSweepsDefault;
+  if (tol <= 0) tol = 1.1102230246251565e-16;  // epsilon = omega for the SVD (Section 6 setup)
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (n == 0) return 0;
+  Timer tm(s, stats != nullptr);
+  tm.mark(0);
+  const int pre = o.precond;
+  if (pre == JAC_PRECOND_MLP) { set_error("gesvd_jacobi: no learned start for the SVD"); return -10; }
+  void* ws = workspace(gesvd_bytes(m, n, pre));
+  if (!ws) { set_error("gesvd_jacobi: workspace allocation failed"); return 4; }
+  Carve c(ws);
+  Head hd = carve_head(c, n);
+  JAC_HIP(hipMemsetAsync(hd.flag, 0, 16 * sizeof(int), s));
+  int e = check_finite(A, m, n, lda, hd.flag, s);
+  if (e) return e;
+  e = fro2_f64(A, m, n, lda, hd.partial, hd.scal + 1, s);
+  if (e) return e;
+  double hs[2];
+  int hflag = 0;
+  JAC_HIP(hipMemcpyAsync(hs, hd.scal, 16, hipMemcpyDeviceToHost, s));
+  JAC_HIP(hipMemcpyAsync(&hflag, hd.flag, 4, hipMemcpyDeviceToHost, s));
+  JAC_HIP(hipStreamSynchronize(s));
+  if (hflag) { set_error("gesvd_jacobi: A contains NaN or Inf"); return 2; }
+  const double nrm = std::sqrt(hs[1]);
+  if (stats) stats->nrmA = nrm;
+  const int np = blk_np(n), npair = np / blk_b2();
+  const int gsplit = svd_gsplit(m, npair);
+  double* C = c.take<double>((size_t)m * np);
+  double* Vw = c.take<double>((size_t)n * np);
+  double* E = c.take<double>((size_t)npair * blk_b2() * blk_b2());
+  int* ident = c.take<int>(npair);
+  double* Gp = c.take<double>((size_t)gsplit * npair * blk_b2() * blk_b2());
+  double* sig = c.take<double>(n);
+  int* rank = c.take<int>(n);
+  JAC_HIP(hipMemsetAsync(Vw, 0, (size_t)n * np * 8, s));
+  tm.mark(1);
+  if (pre == JAC_PRECOND_NONE || nrm == 0.0) {
+    e = copy_convert<double, double>(A, m, n, lda, C, m, s);
+    if (e) return e;
+    e = set_identity<double>(Vw, n, n, s);
+    if (e) return e;
+    tm.mark(2);
+    tm.mark(3);
+  } else {
+    // Step 1 (reading of Algorithm 5.2): right singular vectors of fl32(A) as the
+    // FP32 eigenvectors of the FP32 Gram matrix A32^T A32.
+    float* A32 = c.take<float>((size_t)m * n);
+    float* G32 = c.take<float>((size_t)n * n);
+    double* Z = c.take<double>((size_t)n * n);
+    double* mscr = c.take<double>(mgs_scratch_elems(n, n));
+    e = copy_convert<double, float>(A, m, n, lda, A32, m, s);
+    if (e) return e;
+    e = gemm<float>(true, false, n, n, m, 1.0f, A32, m, A32, m, 0.0f, G32, n, s);
+    if (e) return e;
+    double tol32 = o.fp32_tol > 0 ? o.fp32_tol : 1e-6;
+    int max32 = o.fp32_max_sweeps > 0 ? o.fp32_max_sweeps : 30;
+    int sw32 = 0;
+    long long r32 = 0;
+    e = fp32_stage(G32, false, n, n, nrm * nrm, tol32, max32, Z, n, nullptr, c, hd, s, &sw32, &r32, nullptr,
+                   nullptr, o.variant, o.inner_sweeps);
+    if (e) return e;
+    if (stats) { stats->fp32_sweeps = sw32; stats->fp32_rotations = r32; }
+    tm.mark(2);
+    e = mgs_f64(Z, n, n, n, mscr, hd.flag, s);   // step 2
+    if (e) return e;
+    tm.mark(3);
+    e = gemm<double>(false, false, m, n, n, 1.0, A, lda, Z, n, 0.0, C, m, s);   // step 3: C = A Q
+    if (e) return e;
+    e = copy_convert<double, double>(Z, n, n, n, Vw, n, s);                        // V = Q
+    if (e) return e;
+    JAC_HIP(hipMemcpyAsync(&hflag, hd.flag, 4, hipMemcpyDeviceToHost, s));
+    JAC_HIP(hipStreamSynchronize(s));
+    if (hflag) { set_error("gesvd_jacobi: modified Gram-Schmidt met a zero column"); return 3; }
+  }
+  if (np > n) {
+    hipLaunchKernelGGL(zero_cols_kernel, dim3(cdiv(m, 256), np - n), dim3(256), 0, s, C, m, m, n);
+    JAC_CHECK_LAUNCH();
+  }
+  tm.mark(4);
+  // Step 4: one-sided sweeps until a sweep applies fewer than 2e-4 N rotations
+  // (Section 6 setup) or max_sweeps.  A pair is rotated only when its columns are
+  // not yet orthogonal to m * tol relative accuracy.
+  const double N = 0.5 * (double)n * (n - 1);
+  const double rel = (double)m * tol;
+  int sweeps = 0;
+  long long rots = 0;
+  double step_ms = 0;
+  int info = 1;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (stats) { JAC_HIP(hipEventCreate(&ea)); JAC_HIP(hipEventCreate(&eb)); }
+  while (sweeps < max_sweeps) {
+    JAC_HIP(hipMemsetAsync(hd.rot64, 0, 8, s));
+    if (ea) JAC_HIP(hipEventRecord(ea, s));
+    e = svd_sweep<double>(C, m, m, Vw, n, n, np, E, ident, Gp, gsplit, rel, kMaxInner64, hd.rot64, s);
+    if (e) return e;
+    if (eb) JAC_HIP(hipEventRecord(eb, s));
+    unsigned long long cnt = 0;
+    JAC_HIP(hipMemcpyAsync(&cnt, hd.rot64, 8, hipMemcpyDeviceToHost, s));
+    JAC_HIP(hipStreamSynchronize(s));
+    if (ea) { float ms = 0; JAC_HIP(hipEventElapsedTime(&ms, ea, eb)); step_ms += ms; }
+    ++sweeps;
+    rots += (long long)cnt;
+    if (stats && sweeps < JAC_HIST) stats->off_hist[sweeps] = (double)cnt;
+    if ((double)cnt < 2e-4 * N) { info = 0; break; }
+  }
+  if (ea) { (void)hipEventDestroy(ea); (void)hipEventDestroy(eb); }
+  tm.mark(5);
+  e = svd_finish(C, m, m, Vw, n, n, sig, rank, S, U, ldu, V, ldv, s);
+  if (e) return e;
+  tm.mark(6);
+  JAC_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    stats->sweeps = sweeps;
+    stats->rotations = rots;
+    stats->step_ms = step_ms;
+    stats->step_launches = (long long)sweeps * (2 * npair - 1) * 4;
+    stats->stage_ms[6] = tm.ms(0, 1);
+    stats->stage_ms[0] = tm.ms(1, 2);
+    stats->stage_ms[1] = tm.ms(2, 3);
+    stats->stage_ms[2] = tm.ms(3, 4);
+    stats->stage_ms[3] = tm.ms(4, 5);
+    stats->stage_ms[4] = tm.ms(5, 6);
+    stats->stage_ms[5] = tm.ms(0, 6);
+  }
+  return info;
+}
+
 }  // namespace jac
 
 using namespace jac;
@@ -611,6 +777,41 @@ int syev_jacobi_warm(const double* A, int n, int lda, const double* Q0, int ldq,
   if (ldv < (n > 1 ? n : 1)) { set_error("ldv < max(1,n)"); return -8; }
   if (tol != tol) { set_error("tol is NaN"); return -9; }
   return syev_impl(A, n, lda, Q0, ldq, W, V, ldv, tol, opts, stats, as_stream(stream));
+}
+
+static int check_svd_args(const double* A, int m, int n, int lda, double* S, double* U, int ldu, double* V, int ldv,
+                          double tol) {
+  g_err.clear();
+  if (n > 0 && !A) { set_error("A is NULL"); return -1; }
+  if (m < 0) { set_error("m < 0"); return -2; }
+  if (n < 0 || n > m) { set_error("need 0 <= n <= m"); return -3; }
+  if (lda < (m > 1 ? m : 1)) { set_error("lda < max(1,m)"); return -4; }
+  if (n > 0 && !S) { set_error("S is NULL"); return -5; }
+  if (n > 0 && !U) { set_error("U is NULL"); return -6; }
+  if (ldu < (m > 1 ? m : 1)) { set_error("ldu < max(1,m)"); return -7; }
+  if (n > 0 && !V) { set_error("V is NULL"); return -8; }
+  if (ldv < (n > 1 ? n : 1)) { set_error("ldv < max(1,n)"); return -9; }
+  if (tol != tol) { set_error("tol is NaN"); return -10; }
+  return 0;
+}
+
+int gesvd_jacobi(const double* A, int m, int n, int lda, double* S, double* U, int ldu, double* V, int ldv,
+                 double tol, int* sweeps_out) {
+  int e = check_svd_args(A, m, n, lda, S, U, ldu, V, ldv, tol);
+  if (e) return e;
+  jac_opts o{};
+  o.precond = JAC_PRECOND_FP32;
+  jac_stats st;
+  e = gesvd_impl(A, m, n, lda, S, U, ldu, V, ldv, tol, &o, &st, nullptr);
+  if (sweeps_out) *sweeps_out = st.sweeps;
+  return e;
+}
+
+int gesvd_jacobi_ex(const double* A, int m, int n, int lda, double* S, double* U, int ldu, double* V, int ldv,
+                    double tol, const jac_opts* opts, jac_stats* stats, void* stream) {
+  int e = check_svd_args(A, m, n, lda, S, U, ldu, V, ldv, tol);
+  if (e) return e;
+  return gesvd_impl(A, m, n, lda, S, U, ldu, V, ldv, tol, opts, stats, as_stream(stream));
 }
 
 int jac_parallel_steps(double* T, int n, int ldt, double* V, int ldv, int r0, int nsteps, double skip_abs,
@@ -759,8 +960,8 @@ int jac_eig_fp32(const double* A, int n, int lda, double* Z, int ldz, double* W,
   JAC_HIP(hipStreamSynchronize(s));
   int sw = 0;
   long long rots = 0;
-  e = fp32_stage(A, n, lda, std::sqrt(f2), tol > 0 ? tol : 1e-6, max_sweeps > 0 ? max_sweeps : 30, Zw, n, d32, c,
-                 hd, s, &sw, &rots);
+  e = fp32_stage(A, true, n, lda, std::sqrt(f2), tol > 0 ? tol : 1e-6, max_sweeps > 0 ? max_sweeps : 30, Zw, n, d32,
+                 c, hd, s, &sw, &rots);
   if (e) return e;
   if (W) {
     // Z's columns in ascending order of the FP32 eigenvalues.

@@ -96,10 +96,15 @@ constexpr int kPairBlocks = kH * (kH + 1) / 2;
 constexpr int kBlkPerLane = (kPairBlocks + kWork - 1) / kWork;
 constexpr int kRowsPerLane = kB2 / (kWork / kH);
 
+// Source of S: the diagonal tile T(P_k, P_k) (symmetric eigenproblem; the
+// diagonalised S is written back), or, when Gpart is given, the sum of the
+// gsplit partial Gram matrices of the one-sided SVD (rel > 0 selects its
+// negligibility rule; nothing is written back to T).
 template <typename T>
 __global__ void __launch_bounds__(kInnerThreads)
 blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restrict__ Eall, int* __restrict__ ident,
-                 T skip_abs, int max_inner, unsigned long long* __restrict__ rot) {
+                 T skip_abs, int max_inner, unsigned long long* __restrict__ rot, const T* __restrict__ Gpart,
+                 int gsplit, int npair, T rel) {
   __shared__ T S[2][kB2 * kLD];
   __shared__ T E[2][kB2 * kLD];      // E[a * kLD + slot]: row a = local index
   __shared__ Ang<T> ang[2][kH];
@@ -116,7 +121,16 @@ blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restric
   }
   for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
     int s1 = e % kB2, s2 = e / kB2;
-    S[0][s1 * kLD + s2] = Tm[gidx(ring_of(s1)) + (size_t)gidx(ring_of(s2)) * ldt];
+    T v;
+    if (Gpart) {
+      // partial Grams are indexed by local indices (a, c), column-major
+      const int a = ring_of(s1), c = ring_of(s2);
+      v = T(0);
+      for (int z = 0; z < gsplit; ++z) v += Gpart[((size_t)z * npair + k) * kB2 * kB2 + a + c * kB2];
+    } else {
+      v = Tm[gidx(ring_of(s1)) + (size_t)gidx(ring_of(s2)) * ldt];
+    }
+    S[0][s1 * kLD + s2] = v;
     E[0][s1 * kLD + s2] = T(0);
   }
   unsigned long long cnt = 0;
@@ -142,7 +156,7 @@ blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restric
   if (wave == 0 && lane < kH) {
     const T* Sc = S[0];
     ang[0][lane] = make_angle(Sc[lane * kLD + lane], Sc[(kH + lane) * kLD + kH + lane], Sc[lane * kLD + kH + lane],
-                              gsl[0][lane], gsl[0][kH + lane], n, skip_abs);
+                              gsl[0][lane], gsl[0][kH + lane], n, skip_abs, rel);
   }
   __syncthreads();
   int cur = 0;
@@ -150,13 +164,8 @@ blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restric
     bool big = false;
     for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
       int s1 = e % kB2, s2 = e / kB2;
-      if (s1 < s2 && gsl[cur][s1] < n && gsl[cur][s2] < n) {
-        T apq = S[cur][s1 * kLD + s2];
-        T lim2 = Prec<T>::unit * Prec<T>::unit * absT(S[cur][s1 * kLD + s1] * S[cur][s2 * kLD + s2]);
-        T sk2 = skip_abs * skip_abs;
-        if (sk2 < lim2) lim2 = sk2;
-        big |= apq != T(0) && apq * apq > lim2;
-      }
+      if (s1 < s2 && gsl[cur][s1] < n && gsl[cur][s2] < n)
+        big |= !negligible2(S[cur][s1 * kLD + s1], S[cur][s2 * kLD + s2], S[cur][s1 * kLD + s2], skip_abs, rel);
     }
     if (!__syncthreads_or(big)) break;
     for (int ri = 0; ri < kB2 - 1; ++ri) {
@@ -188,7 +197,7 @@ blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restric
             tabv = comp == 0 ? tt : comp == 1 ? tb : comp == 2 ? bt : bb;
           }
           const int gi = gsl[cur][ba], gj = gsl[cur][bb_];
-          ang[cur ^ 1][lane] = make_angle(ta, tbv, tabv, gi, gj, n, skip_abs);
+          ang[cur ^ 1][lane] = make_angle(ta, tbv, tabv, gi, gj, n, skip_abs, rel);
           gsl[cur ^ 1][lane] = gi;
           gsl[cur ^ 1][kH + lane] = gj;
           lsl[cur ^ 1][lane] = lsl[cur][ba];
@@ -252,9 +261,11 @@ blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restric
     }
   }
   // After whole sweeps the slots hold their initial indices again.
-  for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
-    int s1 = e % kB2, s2 = e / kB2;
-    Tm[gidx(ring_of(s1)) + (size_t)gidx(ring_of(s2)) * ldt] = S[cur][s1 * kLD + s2];
+  if (!Gpart) {
+    for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
+      int s1 = e % kB2, s2 = e / kB2;
+      Tm[gidx(ring_of(s1)) + (size_t)gidx(ring_of(s2)) * ldt] = S[cur][s1 * kLD + s2];
+    }
   }
   // E_k row-major: Eall[k][a * 2b + c] = E(a, c), c = local column index.
   T* Ek = Eall + (size_t)k * kB2 * kB2;
@@ -447,6 +458,120 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
   }
 }
 
+// ---------------------------------------------------------------- one-sided
+// Partial Gram of block pair k over the row range of split z:
+// G_z(a, c) = sum_rows C(row, P_k[a]) C(row, P_k[c]) (2b x 2b, column-major,
+// stored at Gpart[z][k]).  Rows are staged through LDS 16 at a time (k-major,
+// so the same array serves as the A = C^T and B = C operands).
+template <typename T>
+__global__ void __launch_bounds__(kNT)
+gram_partial_kernel(const T* __restrict__ C, int ldc, int mrows, int m2, int r, int krows, T* __restrict__ Gpart,
+                    int npair) {
+  constexpr int b = kB2 / 2;
+  __shared__ T Cs[2][16 * kLD];
+  __shared__ int gk[kB2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int k = blockIdx.x, z = blockIdx.y;
+  const RR rrb(m2);
+  if (tid < kB2) {
+    int Ik = rrb.index(k, r), Jk = rrb.index(rrb.h + k, r);
+    gk[tid] = tid < b ? Ik * b + tid : Jk * b + (tid - b);
+  }
+  const int r0 = z * krows, r1 = min(mrows, r0 + krows);
+  typename Mfma<T>::acc_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[a][c] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+  __syncthreads();
+  T ld[4];
+  auto load = [&](int rb) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int e = tid + q * kNT;      // 16 x 64 piece: row kk = e % 16, column i = e / 16
+      int kk = e & 15, i = e >> 4;
+      int row = rb + kk;
+      ld[q] = row < r1 ? C[row + (size_t)gk[i] * ldc] : T(0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int e = tid + q * kNT;
+      Cs[buf][(e & 15) * kLD + (e >> 4)] = ld[q];
+    }
+  };
+  int buf = 0;
+  if (r0 < r1) { load(r0); store(0); }
+  __syncthreads();
+  for (int rb = r0; rb < r1; rb += 16) {
+    const bool more = rb + 16 < r1;
+    if (more) load(rb + 16);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kr = q * 4 + (lane >> 4), cc = lane & 15;
+      T av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = Cs[buf][kr * kLD + wm * 32 + a * 16 + cc];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) bv[c] = Cs[buf][kr * kLD + wn * 32 + c * 16 + cc];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = Mfma<T>::op(av[a], bv[c], acc[a][c]);
+    }
+    if (more) {
+      store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+  T* G = Gpart + ((size_t)z * npair + k) * kB2 * kB2;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        int i = wm * 32 + a * 16 + Mfma<T>::row(lane, rr);
+        int j = wn * 32 + c * 16 + (lane & 15);
+        G[i + j * kB2] = acc[a][c][rr];
+      }
+}
+
+// One block sweep of the one-sided method (Algorithm 5.1 / step 4 of
+// Algorithm 5.2): for every block step, the Gram of each block pair, its
+// diagonalisation, and C(:, P_k) <- C(:, P_k)(I + E_k), V(:, P_k) likewise.
+template <typename T>
+int svd_sweep(T* C, int ldc, int mrows, T* V, int ldv, int n, int np, T* Ebuf, int* ident, T* Gpart, int gsplit,
+              T rel, int max_inner, unsigned long long* rot, hipStream_t s) {
+  const int m2 = np / (kB2 / 2), npair = m2 / 2;
+  const int krows = ((mrows + gsplit - 1) / gsplit + 15) / 16 * 16;
+  const int cch = (mrows + kB2 - 1) / kB2, vch = (n + kB2 - 1) / kB2;
+  for (int r = 0; r < m2 - 1; ++r) {
+    hipLaunchKernelGGL((gram_partial_kernel<T>), dim3(npair, gsplit), dim3(kNT), 0, s, C, ldc, mrows, m2, r, krows,
+                       Gpart, npair);
+    JAC_CHECK_LAUNCH();
+    hipLaunchKernelGGL((blk_inner_kernel<T>), dim3(npair), dim3(kInnerThreads), 0, s, (T*)nullptr, 0, n, m2, r, Ebuf,
+                       ident, T(0), max_inner, rot, (const T*)Gpart, gsplit, npair, rel);
+    JAC_CHECK_LAUNCH();
+    // column updates of C (mrows rows) and V (n rows): the chunk path of the update kernel
+    hipLaunchKernelGGL((blk_update_kernel<T>), dim3(npair * cch), dim3(kNT), 0, s, (T*)nullptr, 0, C, ldc, mrows, Ebuf,
+                       ident, m2, r, 0, cch);
+    JAC_CHECK_LAUNCH();
+    hipLaunchKernelGGL((blk_update_kernel<T>), dim3(npair * vch), dim3(kNT), 0, s, (T*)nullptr, 0, V, ldv, n, Ebuf,
+                       ident, m2, r, 0, vch);
+    JAC_CHECK_LAUNCH();
+  }
+  return 0;
+}
+
+template int svd_sweep<double>(double*, int, int, double*, int, int, int, double*, int*, double*, int, double, int,
+                               unsigned long long*, hipStream_t);
+template int svd_sweep<float>(float*, int, int, float*, int, int, int, float*, int*, float*, int, float, int,
+                              unsigned long long*, hipStream_t);
+
 // ||off(T)||^2 partial sums over the full np x np matrix.
 template <typename T>
 __global__ void offdiag2_partial_kernel(const T* __restrict__ Tm, int np, int ldt, double* __restrict__ partial) {
@@ -531,8 +656,7 @@ int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s) {
   const int nvchunk = cdiv(st.nvr, kB2);
   for (int r = 0; r < m2 - 1; ++r) {
     hipLaunchKernelGGL((blk_inner_kernel<T>), dim3(m), dim3(kInnerThreads), 0, s, st.Tm, st.ldt, st.n, m2, r, st.W,
-                       st.ident,
-                       st.skip_abs, max_inner, st.rot);
+                       st.ident, st.skip_abs, max_inner, st.rot, (const T*)nullptr, 0, m, T(0));
     JAC_CHECK_LAUNCH();
     int nwg = ntile + m * nvchunk;
     hipLaunchKernelGGL((blk_update_kernel<T>), dim3(nwg), dim3(kNT), 0, s, st.Tm, st.ldt, st.V, st.ldv, st.nvr, st.W,

@@ -144,18 +144,31 @@ __device__ __forceinline__ void rot2(T& x, T& y, T s, T tau) {
 // top/bottom roles (sign flipped when the top member is q).  Pairs with an
 // index >= n (padding), and negligible t_pq (Remark dc: |t_pq| <= u
 // sqrt|t_pp t_qq|, capped by skip_abs), give the identity.
+// Negligibility of a pair (squared comparison, no square root):
+//  symmetric problem (rel == 0): Remark dc, apq^2 <= min(u^2 |app aqq|, skip_abs^2);
+//  one-sided SVD (rel > 0): columns already orthogonal to rel, i.e.
+//  gamma^2 <= rel^2 alpha beta for the Gram entries (alpha, beta, gamma).
 template <typename T>
-__device__ __forceinline__ Ang<T> make_angle(T tt, T bb, T tb, int ip, int iq, int n, T skip_abs) {
+__device__ __forceinline__ bool negligible2(T app, T aqq, T apq, T skip_abs, T rel) {
+  if (apq == T(0)) return true;
+  T lim2;
+  if (rel > T(0)) {
+    lim2 = rel * rel * absT(app * aqq);
+  } else {
+    lim2 = Prec<T>::unit * Prec<T>::unit * absT(app * aqq);
+    T sk2 = skip_abs * skip_abs;
+    if (sk2 < lim2) lim2 = sk2;
+  }
+  return apq * apq <= lim2;
+}
+
+template <typename T>
+__device__ __forceinline__ Ang<T> make_angle(T tt, T bb, T tb, int ip, int iq, int n, T skip_abs, T rel = T(0)) {
   Ang<T> a{T(0), T(0), T(0), T(0)};
   if (ip >= n || iq >= n) return a;
   bool flip = ip > iq;
   T app = flip ? bb : tt, aqq = flip ? tt : bb, apq = tb;
-  if (apq == T(0)) return a;
-  // Remark dc, compared in squares: apq^2 <= min(u^2 |app aqq|, skip_abs^2).
-  T lim2 = Prec<T>::unit * Prec<T>::unit * absT(app * aqq);
-  T sk2 = skip_abs * skip_abs;
-  if (sk2 < lim2) lim2 = sk2;
-  if (apq * apq <= lim2) return a;
+  if (negligible2(app, aqq, apq, skip_abs, rel)) return a;
   // Lemma offa-jr: t = sign(mu) / (|mu| + sqrt(1 + mu^2)), mu = d / (2 apq),
   // d = aqq - app, written as t = sign(d) 2 apq / (|d| + sqrt(d^2 + 4 apq^2))
   // (t = 1 when d = 0).  Then c = 1/r, s = t/r, tau = s/(1+c) = t/(1+r) with
@@ -256,6 +269,13 @@ template <typename T>
 int sort_eigs(const T* d, const T* Vw, int n, int ldw, double* W, double* Vout, int ldv,
               int* rank, hipStream_t s);
 int check_finite(const double* A, int m, int n, int lda, int* flag, hipStream_t s);
+int svd_finish(const double* C, int m, int ldc, const double* Vw, int n, int ldvw, double* sig, int* rank,
+               double* S, double* U, int ldu, double* V, int ldv, hipStream_t s);
+
+// One-sided Jacobi sweep (blocked.hip).
+template <typename T>
+int svd_sweep(T* C, int ldc, int mrows, T* V, int ldv, int n, int np, T* Ebuf, int* ident, T* Gpart, int gsplit,
+              T rel, int max_inner, unsigned long long* rot, hipStream_t s);
 
 // GEMM (gemm.hip): C = alpha * op(A) * op(B) + beta * C, column-major.
 template <typename T>

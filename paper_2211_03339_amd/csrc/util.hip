@@ -137,11 +137,61 @@ int sort_eigs(const T* d, const T* Vw, int n, int ldw, double* W, double* Vout, 
   return 0;
 }
 
+// sigma_j = ||c_j|| (one workgroup per column, fixed reduction order).
+__global__ void colnorm2_kernel(const double* __restrict__ C, int m, int ldc, double* __restrict__ sig) {
+  __shared__ double red[4];
+  const double* c = C + (size_t)blockIdx.x * ldc;
+  double acc = 0;
+  for (int i = threadIdx.x; i < m; i += 256) acc = fma(c[i], c[i], acc);
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) sig[blockIdx.x] = sqrt(red[0] + red[1] + red[2] + red[3]);
+}
+
+// Descending order, ties by index.
+__global__ void rank_desc_kernel(const double* __restrict__ sig, int n, int* __restrict__ rank, double* __restrict__ S) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double v = sig[j];
+  int r = 0;
+  for (int i = 0; i < n; ++i) r += (sig[i] > v) || (sig[i] == v && i < j);
+  rank[j] = r;
+  S[r] = v;
+}
+
+// U(:, rank_j) = c_j / sigma_j (zero column if sigma_j = 0), V(:, rank_j) = v_j.
+__global__ void svd_finish_kernel(const double* __restrict__ C, int m, int ldc, const double* __restrict__ Vw, int n,
+                                  int ldvw, const double* __restrict__ sig, const int* __restrict__ rank,
+                                  double* __restrict__ U, int ldu, double* __restrict__ V, int ldv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y;
+  int rj = rank[j];
+  double sj = sig[j];
+  if (i < m) U[i + (size_t)rj * ldu] = sj > 0 ? C[i + (size_t)j * ldc] / sj : 0.0;
+  if (i < n) V[i + (size_t)rj * ldv] = Vw[i + (size_t)j * ldvw];
+}
+
+int svd_finish(const double* C, int m, int ldc, const double* Vw, int n, int ldvw, double* sig, int* rank,
+               double* S, double* U, int ldu, double* V, int ldv, hipStream_t s) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(colnorm2_kernel, dim3(n), dim3(256), 0, s, C, m, ldc, sig);
+  JAC_CHECK_LAUNCH();
+  hipLaunchKernelGGL(rank_desc_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, sig, n, rank, S);
+  JAC_CHECK_LAUNCH();
+  int rows = m > n ? m : n;
+  hipLaunchKernelGGL(svd_finish_kernel, dim3(cdiv(rows, 256), n), dim3(256), 0, s, C, m, ldc, Vw, n, ldvw, sig, rank,
+                     U, ldu, V, ldv);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
 template int set_identity<double>(double*, int, int, hipStream_t);
 template int set_identity<float>(float*, int, int, hipStream_t);
 template int copy_convert<double, float>(const double*, int, int, int, float*, int, hipStream_t);
 template int copy_convert<float, double>(const float*, int, int, int, double*, int, hipStream_t);
 template int copy_convert<double, double>(const double*, int, int, int, double*, int, hipStream_t);
+template int copy_convert<float, float>(const float*, int, int, int, float*, int, hipStream_t);
 template int sort_eigs<double>(const double*, const double*, int, int, double*, double*, int, int*, hipStream_t);
 template int sort_eigs<float>(const float*, const float*, int, int, double*, double*, int, int*, hipStream_t);
 

@@ -79,6 +79,9 @@ def load():
                                 ctypes.POINTER(JacStats), _vp]),
         "syev_jacobi_warm": (_i, [_vp, _i, _i, _vp, _i, _vp, _vp, _i, _d, ctypes.POINTER(JacOpts),
                                   ctypes.POINTER(JacStats), _vp]),
+        "gesvd_jacobi": (_i, [_vp, _i, _i, _i, _vp, _vp, _i, _vp, _i, _d, ctypes.POINTER(_i)]),
+        "gesvd_jacobi_ex": (_i, [_vp, _i, _i, _i, _vp, _vp, _i, _vp, _i, _d, ctypes.POINTER(JacOpts),
+                                 ctypes.POINTER(JacStats), _vp]),
         "jac_parallel_steps": (_i, [_vp, _i, _i, _vp, _i, _i, _i, _d,
                                     ctypes.POINTER(ctypes.c_longlong), _vp]),
         "jac_round_robin_pairs": (_i, [_i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
@@ -206,6 +209,28 @@ def syev_jacobi_warm(A: torch.Tensor, Q0: torch.Tensor, tol: float = 0.0, max_sw
                               ctypes.byref(st), _stream())
     _check("syev_jacobi_warm", code)
     return W, Vb.t(), st.as_dict(), code
+
+
+def gesvd_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", max_sweeps=0, variant="auto",
+                    allow_unconverged=False):
+    """Thin SVD A = U diag(S) V^T (m >= n): returns (S descending, U, V, stats, info)."""
+    L = load()
+    A = _dev(A)
+    m, n = A.shape
+    Ac = _colmajor(A)
+    S = torch.empty(n, dtype=torch.float64, device=A.device)
+    Ub = torch.empty((n, m), dtype=torch.float64, device=A.device)
+    Vb = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    o = _opts(precond, variant, 0, max_sweeps)
+    st = JacStats()
+    code = L.gesvd_jacobi_ex(_vp(Ac.data_ptr()), m, n, max(m, 1), _vp(S.data_ptr()), _vp(Ub.data_ptr()),
+                             max(m, 1), _vp(Vb.data_ptr()), max(n, 1), tol, ctypes.byref(o), ctypes.byref(st),
+                             _stream())
+    _check("gesvd_jacobi_ex", code, ok=(0, 1) if allow_unconverged else (0,))
+    d = st.as_dict()
+    d["rotations_per_sweep"] = list(st.off_hist[1: st.sweeps + 1])
+    d.pop("off_hist")
+    return S, Ub.t(), Vb.t(), d, code
 
 
 def jac_parallel_steps(T: torch.Tensor, V: torch.Tensor | None, r0: int, nsteps: int, skip_abs: float = 0.0):
