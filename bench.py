@@ -25,6 +25,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FP64 eigensolves/sec + Jacobi sweeps at n=2048: precond & MLP vs plain, resid<=1e-13"
 HBM_PEAK_GBS = 8000.0
+PEAK = {"fp64_mfma": 78.6, "fp32_mfma": 157.3, "fp64_valu": 78.6, "fp32_valu": 157.3}   # TFLOP/s
+TILE = 64   # 2b: block-pair size of the blocked variant
 
 
 def log(msg):
@@ -35,6 +37,42 @@ def step_bytes(n: int, dtype_bytes: int) -> float:
     """Algorithmic bytes of one element-wise parallel step: the symmetric T read and written
     once (n(n+1)/2 entries each way) and V read and written once."""
     return dtype_bytes * (n * (n + 1) + 2 * n * n)
+
+
+def roofline_for(cls: str, k: dict, n: int, rotations: int) -> dict:
+    """Roofline figure of one kernel class from its HIP-event launch times.
+    update*: algorithmic flops of the block rotations actually applied: each (2b)x(2b) tile
+    W_k^T T W_l costs 2 * 2(2b)^3, each 2b-row chunk of V W_k costs 2(2b)^3.
+    elem*: algorithmic bytes of a parallel step (step_bytes).
+    inner*: rotation flops (each rotation of a 2b x 2b subproblem updates two rows and two
+    columns of S and two columns of E: about 12 * 2b flops) on the vector units."""
+    ms, launches = k["ms"], max(k["launches"], 1)
+    avg_s = ms / 1e3 / launches
+    if cls.startswith("update"):
+        flops = k["tiles"] * 4 * TILE ** 3 + k["chunks"] * 2 * TILE ** 3
+        per_launch = flops / launches
+        peak = PEAK["fp64_mfma" if cls.endswith("64") else "fp32_mfma"]
+        ach = per_launch / avg_s / 1e12
+        return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 4), "traffic": None, "kernel": f"blk_update_kernel<{cls[-2:]}>",
+                "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_flops_per_launch": per_launch,
+                "launches_timed": k["launches"]}
+    if cls.startswith("elem"):
+        db = 8 if cls.endswith("64") else 4
+        bpl = step_bytes(n, db)
+        ach = bpl / avg_s / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": f"elem_step_kernel<{cls[-2:]}>",
+                "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_bytes_per_launch": bpl,
+                "launches_timed": k["launches"]}
+    flops = rotations * 12 * TILE
+    per_launch = flops / launches
+    peak = PEAK["fp64_valu" if cls.endswith("64") else "fp32_valu"]
+    ach = per_launch / avg_s / 1e12
+    return {"bound": "alu", "achieved": round(ach, 4), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(ach / peak, 6), "traffic": None, "kernel": f"blk_inner_kernel<{cls[-2:]}>",
+            "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_flops_per_launch": per_launch,
+            "launches_timed": k["launches"]}
 
 
 def main():
@@ -70,7 +108,7 @@ def main():
     sp = jacobi.ctypes.c_void_p(stream.cuda_stream)
 
     def solve(i, precond, stats):
-        o = jacobi._opts(precond, args.variant)
+        o = jacobi._opts(precond, args.variant, profile=1)
         code = jacobi.syev_jacobi_raw(dev[i].data_ptr(), n, n, Ws[i].data_ptr(), Vs[i].data_ptr(), n,
                                       args.tol, o, stats, sp)
         if code != 0:
@@ -82,15 +120,19 @@ def main():
             solve(i, "fp32", stats[i])
         log(f"[bench] warmup {w + 1}/{args.warmup} done")
     torch.cuda.synchronize()
-    agg = {"step_ms": 0.0, "launches": 0, "fp32_step_ms": 0.0, "fp32_launches": 0}
+    kern = {}
+    rot = {"64": 0, "32": 0}
     t0 = time.perf_counter()
     for k in range(args.steps):
         for i in range(len(mats)):
             solve(i, "fp32", stats[i])
-            agg["step_ms"] += stats[i].step_ms
-            agg["launches"] += stats[i].step_launches
-            agg["fp32_step_ms"] += stats[i].fp32_step_ms
-            agg["fp32_launches"] += stats[i].fp32_step_launches
+            d = stats[i].as_dict()
+            rot["64"] += d["rotations"]
+            rot["32"] += d["fp32_rotations"]
+            for name, kv in d["kernels"].items():
+                a = kern.setdefault(name, {"ms": 0.0, "launches": 0, "tiles": 0, "chunks": 0})
+                for f in a:
+                    a[f] += kv[f]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s")
@@ -127,18 +169,12 @@ def main():
                  "speedup_precond_vs_plain": value / (len(mats) / pt)}
         log(f"[bench] plain: {plain}")
 
-    # Roofline of the dominant kernel (rotation step, FP32 stage or FP64 sweeps).
-    if agg["fp32_step_ms"] >= agg["step_ms"] and agg["fp32_launches"] > 0:
-        ms, nl, db, kname = agg["fp32_step_ms"], agg["fp32_launches"], 4, "elem_step_kernel<float>"
-    else:
-        ms, nl, db, kname = agg["step_ms"], agg["launches"], 8, "elem_step_kernel<double>"
-    avg_s = ms / 1e3 / max(nl, 1)
-    bpl = step_bytes(n, db)
-    achieved = bpl / avg_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": kname, "avg_launch_us": round(avg_s * 1e6, 3),
-                "algorithmic_bytes_per_launch": bpl, "launches_timed": nl}
+    # Roofline of the dominant kernel (by measured launch time inside the timed region).
+    dom = max(kern, key=lambda c: kern[c]["ms"])
+    roofline = roofline_for(dom, kern[dom], n, rot[dom[-2:]])
+    kernels = {c: {"ms_total": round(v["ms"], 3), "launches": v["launches"],
+                   "share_of_timed": round(v["ms"] / (elapsed * 1e3), 4)} for c, v in kern.items()}
+    others = {c: roofline_for(c, kern[c], n, rot[c[-2:]]) for c in kern if c != dom}
 
     cpu = None
     if not args.no_cpu:
@@ -165,7 +201,8 @@ def main():
                                   f"1e-8 / 10 clusters x 1e-6, one solve of each per step",
                       "n": n, "solves_per_step": len(mats), "variant": args.variant,
                       "tol": args.tol if args.tol > 0 else 20 * 2.0 ** -53},
-           "per_spectrum": per_spec, "plain": plain, "roofline": roofline, "cpu_baseline": cpu}
+           "per_spectrum": per_spec, "plain": plain, "roofline": roofline, "cpu_baseline": cpu,
+           "kernels": kernels, "other_rooflines": others}
     print(json.dumps(out), flush=True)
 
 

@@ -59,6 +59,7 @@ typedef struct jac_opts {
   const float* theta;  /* JAC_PRECOND_MLP: device pointer to its input */
   double fallback_tol; /* MLP start rejected if off(Q^T A Q)_F / ||A||_F > this; <= 0: 1e-2 */
   int inner_sweeps;    /* blocked variant: cap on the sweeps of each 2b x 2b subproblem; <= 0: default */
+  int profile;         /* nonzero: time every sweep launch with HIP events into jac_stats.kern_* */
 } jac_opts;
 
 #define JAC_HIST 65
@@ -78,6 +79,15 @@ typedef struct jac_stats {
   long long step_launches; /* number of FP64 step launches timed in step_ms */
   double fp32_step_ms;     /* same for the FP32 stage */
   long long fp32_step_launches;
+  /* With opts.profile: per kernel class, summed HIP-event time, launch count and
+   * work done.  Classes: 0 FP64 inner solve, 1 FP64 block update, 2 FP32 inner
+   * solve, 3 FP32 block update, 4 FP64 element step, 5 FP32 element step.
+   * kern_work: update classes = 64x64 GEMM tiles + 64-row chunks computed
+   * (tiles in the high 32 bits, chunks in the low 32 bits); element classes =
+   * steps. */
+  double kern_ms[6];
+  long long kern_launches[6];
+  long long kern_work[6];
 } jac_stats;
 
 /* Symmetric eigendecomposition A = V diag(W) V^T by Algorithm 4.1
@@ -115,6 +125,32 @@ int gesvd_jacobi(const double* A, int m, int n, int lda, double* S, double* U, i
  * V = I), statistics (off_hist[s] = rotations applied in sweep s) and stream. */
 int gesvd_jacobi_ex(const double* A, int m, int n, int lda, double* S, double* U, int ldu, double* V, int ldv,
                     double tol, const jac_opts* opts, jac_stats* stats, void* stream);
+
+/* Batched symmetric eigendecompositions (plain FP64 Jacobi, blocked variant)
+ * of `batch` independent matrices of order n[i] in [1, 512].  Host arrays:
+ * n, A (device pointers to column-major n[i] x n[i] inputs, read only), lda,
+ * W (device pointers, n[i] eigenvalues ascending), V (device pointers,
+ * n[i] x n[i] eigenvectors, leading dimension ldv[i]).  Device arrays (may be
+ * NULL): sweeps[i] = sweeps until ||off(T)||_F <= tol ||A_i||_F first held,
+ * info[i] = 0 converged / 1 not converged within the tuned sweep count.
+ * tol <= 0 selects 20 * 2^-53.  Asynchronous: the whole solve is one graph
+ * launch on `stream` (the graph is built on the first call with these sizes
+ * and pointers and replayed afterwards).  Results are valid once the stream
+ * has completed.  Inputs must not change shape between calls that reuse it. */
+int syev_jacobi_batched(int batch, const int* n, const double* const* A, const int* lda, double* const* W,
+                        double* const* V, const int* ldv, double tol, int* sweeps, int* info, void* stream);
+
+/* Autotuner of the batched path: for every size class (order rounded up to 64)
+ * present in the batch, times the inner-sweep caps 1..4 on up to 16 of the
+ * given matrices and keeps the fastest one that converges, with its sweep
+ * count.  The table is used by later syev_jacobi_batched calls in this process
+ * and written to the file named by the environment variable JACOBI_TUNE_CACHE
+ * (read back at the first use in a later process).  Synchronous. */
+int jac_autotune_batched(int batch, const int* n, const double* const* A, const int* lda, double tol,
+                         void* stream);
+
+/* Host: the (inner-sweep cap, sweep count) the batched path uses for order n. */
+int jac_tune_entry(int n, int* inner_sweeps, int* sweeps);
 
 /* ---- Stages of the path, callable on their own --------------------------- */
 

@@ -53,6 +53,36 @@ void release_workspace() {
 
 static inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// ------------------------------------------------------------------ profiling
+int Prof::mark(hipStream_t s) {
+  if (!on) return -1;
+  if (used == (int)ev.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) { on = false; return -1; }
+    ev.push_back(e);
+  }
+  if (hipEventRecord(ev[used], s) != hipSuccess) { on = false; return -1; }
+  return used++;
+}
+
+int Prof::flush() {
+  if (!on) return 0;
+  for (const Iv& iv : ivs) {
+    float t = 0;
+    if (hipEventElapsedTime(&t, ev[iv.e0], ev[iv.e1]) == hipSuccess) {
+      ms[iv.cls] += t;
+      launches[iv.cls] += 1;
+    }
+  }
+  ivs.clear();
+  used = 0;
+  return 0;
+}
+
+Prof::~Prof() {
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+}
+
 // ------------------------------------------------------------------ sizing
 constexpr int kMaxSweepsDefault = 64;
 constexpr int kRotSlots = 272;  // per-sweep rotation counters (>= max sweeps + 2)
@@ -103,6 +133,7 @@ struct Head {
   unsigned long long* rot64;  // FP64 rotation counters
   unsigned long long* rot32;  // FP32 rotation counters
   int* flag;
+  unsigned long long* work;   // per kernel class work counters [8]
 };
 
 static Head carve_head(Carve& c, int) {
@@ -112,6 +143,7 @@ static Head carve_head(Carve& c, int) {
   h.rot64 = c.take<unsigned long long>(kRotSlots);
   h.rot32 = c.take<unsigned long long>(kRotSlots);
   h.flag = c.take<int>(16);
+  h.work = c.take<unsigned long long>(8);
   return h;
 }
 
@@ -164,6 +196,7 @@ static int elem_run(ElemState<T>& st, double tol, double nrm, int max_sweeps, hi
     if (e) return e;
     JAC_HIP(hipMemcpyAsync(&off2, st.scalars, 8, hipMemcpyDeviceToHost, s));
     JAC_HIP(hipStreamSynchronize(s));
+    if (st.prof) st.prof->flush();
     if (ea) {
       float ms = 0;
       JAC_HIP(hipEventElapsedTime(&ms, ea, eb));
@@ -233,6 +266,7 @@ static int blk_run(BlkState<T>& st, double tol, double nrm, int max_sweeps, int 
     if (e) return e;
     JAC_HIP(hipMemcpyAsync(&off2, st.scalars, 8, hipMemcpyDeviceToHost, s));
     JAC_HIP(hipStreamSynchronize(s));
+    if (st.prof) st.prof->flush();
     if (ea) {
       float ms = 0;
       JAC_HIP(hipEventElapsedTime(&ms, ea, eb));
@@ -296,10 +330,13 @@ struct Timer {
 static int fp32_stage(const void* A, bool a_dbl, int n, int lda, double nrmA, double tol32, int max32, double* Z,
                       int ldz, float* d32, Carve& c, Head& hd, hipStream_t s, int* sweeps, long long* rots,
                       double* step_ms = nullptr, long long* launches = nullptr, int variant = 0,
-                      int inner = 0) {
+                      int inner = 0, Prof* prof = nullptr) {
   if (use_blocked(variant, n)) {
     BlkState<float> st;
     carve_blk(c, st, n);
+    st.prof = prof;
+    st.cls_inner = 2;
+    st.cls_update = 3;
     st.partial = hd.partial;
     st.scalars = hd.scal;
     st.rot = hd.rot32;
@@ -323,6 +360,8 @@ static int fp32_stage(const void* A, bool a_dbl, int n, int lda, double nrmA, do
   }
   ElemState<float> st;
   carve_elem(c, st, n);
+  st.prof = prof;
+  st.cls = 5;
   float* A32 = c.take<float>((size_t)n * n);
   float* V32 = c.take<float>((size_t)n * n);
   st.V = V32;
@@ -396,7 +435,12 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
   }
   Carve c(ws);
   Head hd = carve_head(c, n);
+  Prof prof;
+  prof.on = stats != nullptr && o.profile != 0;
+  prof.work = hd.work;
+  Prof* pf = prof.on ? &prof : nullptr;
   JAC_HIP(hipMemsetAsync(hd.flag, 0, 16 * sizeof(int), s));
+  JAC_HIP(hipMemsetAsync(hd.work, 0, 8 * sizeof(unsigned long long), s));
   int e = check_finite(A, n, n, lda, hd.flag, s);
   if (e) return e;
   e = fro2_f64(A, n, n, lda, hd.partial, hd.scal + 1, s);
@@ -425,6 +469,8 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
   st.scalars = hd.scal;
   st.rot = hd.rot64;
   st.skip_abs = tol * nrm / n;
+  st.prof = pf;
+  st.cls = 4;
 
   float ms_pre = 0, ms_mgs = 0, ms_sim = 0;
   double* T0p = nullptr;
@@ -449,7 +495,7 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
       double ms32 = 0;
       long long l32 = 0;
       e = fp32_stage(A, true, n, lda, nrm, tol32, max32, Vw, n, nullptr, c, hd, s, &sw32, &r32,
-                     stats ? &ms32 : nullptr, &l32, o.variant, o.inner_sweeps);
+                     stats ? &ms32 : nullptr, &l32, o.variant, o.inner_sweeps, pf);
       if (e) return e;
       if (stats) {
         stats->fp32_sweeps = sw32;
@@ -491,6 +537,9 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
     bst.scalars = hd.scal;
     bst.rot = hd.rot64;
     bst.skip_abs = tol * nrm / n;
+    bst.prof = pf;
+    bst.cls_inner = 0;
+    bst.cls_update = 1;
     const bool plain = (pre == JAC_PRECOND_NONE || nrm == 0.0);
     e = blk_load<double>(bst, plain ? (const void*)A : (const void*)T0p, true, plain ? lda : n, s);
     if (e) return e;
@@ -532,6 +581,15 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
     stats->stage_ms[3] = tm.ms(4, 5);
     stats->stage_ms[4] = tm.ms(5, 6);
     stats->stage_ms[5] = tm.ms(0, 6);
+    if (prof.on) {
+      unsigned long long wk[8];
+      JAC_HIP(hipMemcpy(wk, hd.work, sizeof(wk), hipMemcpyDeviceToHost));
+      for (int i = 0; i < 6; ++i) {
+        stats->kern_ms[i] = prof.ms[i];
+        stats->kern_launches[i] = prof.launches[i];
+        stats->kern_work[i] = (long long)wk[i];
+      }
+    }
   }
   (void)ms_pre; (void)ms_mgs; (void)ms_sim;
   return info;

@@ -104,7 +104,12 @@ template <typename T>
 __global__ void __launch_bounds__(kInnerThreads)
 blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restrict__ Eall, int* __restrict__ ident,
                  T skip_abs, int max_inner, unsigned long long* __restrict__ rot, const T* __restrict__ Gpart,
-                 int gsplit, int npair, T rel) {
+                 int gsplit, int npair, T rel, const BDesc<T>* __restrict__ desc) {
+  if (desc) {   // batched: matrix blockIdx.y of a size class
+    const BDesc<T> d = desc[blockIdx.y];
+    Tm = d.Tm; ldt = d.ldt; n = d.n; Eall = d.E; ident = d.ident; rot = d.rot;
+    skip_abs = (T)(d.tol_n * sqrt(*d.nrm2));
+  }
   __shared__ T S[2][kB2 * kLD];
   __shared__ T E[2][kB2 * kLD];      // E[a * kLD + slot]: row a = local index
   __shared__ Ang<T> ang[2][kH];
@@ -367,7 +372,12 @@ __device__ __forceinline__ void acc_store(T* M, int wm, int wn, const typename M
 template <typename T>
 __global__ void __launch_bounds__(kNT)
 blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int nvr, const T* __restrict__ Eall,
-                  const int* __restrict__ ident, int m2, int r, int ntile, int nvchunk) {
+                  const int* __restrict__ ident, int m2, int r, int ntile, int nvchunk,
+                  unsigned long long* __restrict__ work, const BDesc<T>* __restrict__ desc = nullptr) {
+  if (desc) {   // batched: matrix blockIdx.y of a size class
+    const BDesc<T> d = desc[blockIdx.y];
+    Tm = d.Tm; ldt = d.ldt; V = d.V; ldv = d.ldv; nvr = d.n; Eall = d.E; ident = d.ident;
+  }
   constexpr int b = kB2 / 2;
   __shared__ T Bs[kB2 * kLD];
   __shared__ int gk[kB2], gl[kB2];
@@ -381,6 +391,7 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
     int k, l;
     stri_decode(w, k, l);
     if (ident[k] && ident[l]) return;
+    if (work && tid == 0) atomicAdd(work, 1ull << 32);
     const T* Ek = Eall + (size_t)k * kB2 * kB2;
     const T* El = Eall + (size_t)l * kB2 * kB2;
     load_efrag<T>(Ek, wm * 32, fa);   // A(i, kk) = E_k(kk, i)
@@ -431,6 +442,7 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
     int wv = w - ntile;
     int k = wv / nvchunk, chunk = wv % nvchunk;
     if (ident[k]) return;
+    if (work && tid == 0) atomicAdd(work, 1ull);
     const int row0 = chunk * kB2;
     const T* Ek = Eall + (size_t)k * kB2 * kB2;
     load_efrag<T>(Ek, wn * 32, fb);   // B(kk, j) = E_k(kk, j)
@@ -554,14 +566,14 @@ int svd_sweep(T* C, int ldc, int mrows, T* V, int ldv, int n, int np, T* Ebuf, i
                        Gpart, npair);
     JAC_CHECK_LAUNCH();
     hipLaunchKernelGGL((blk_inner_kernel<T>), dim3(npair), dim3(kInnerThreads), 0, s, (T*)nullptr, 0, n, m2, r, Ebuf,
-                       ident, T(0), max_inner, rot, (const T*)Gpart, gsplit, npair, rel);
+                       ident, T(0), max_inner, rot, (const T*)Gpart, gsplit, npair, rel, (const BDesc<T>*)nullptr);
     JAC_CHECK_LAUNCH();
     // column updates of C (mrows rows) and V (n rows): the chunk path of the update kernel
     hipLaunchKernelGGL((blk_update_kernel<T>), dim3(npair * cch), dim3(kNT), 0, s, (T*)nullptr, 0, C, ldc, mrows, Ebuf,
-                       ident, m2, r, 0, cch);
+                       ident, m2, r, 0, cch, (unsigned long long*)nullptr);
     JAC_CHECK_LAUNCH();
     hipLaunchKernelGGL((blk_update_kernel<T>), dim3(npair * vch), dim3(kNT), 0, s, (T*)nullptr, 0, V, ldv, n, Ebuf,
-                       ident, m2, r, 0, vch);
+                       ident, m2, r, 0, vch, (unsigned long long*)nullptr);
     JAC_CHECK_LAUNCH();
   }
   return 0;
@@ -654,14 +666,23 @@ int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s) {
   const int m2 = st.np / (kB2 / 2), m = m2 / 2;
   const int ntile = m * (m - 1) / 2;
   const int nvchunk = cdiv(st.nvr, kB2);
+  Prof* pf = st.prof;
+  unsigned long long* work = pf && pf->on ? pf->work + st.cls_update : nullptr;
+  int e_prev = pf ? pf->mark(s) : -1;
   for (int r = 0; r < m2 - 1; ++r) {
     hipLaunchKernelGGL((blk_inner_kernel<T>), dim3(m), dim3(kInnerThreads), 0, s, st.Tm, st.ldt, st.n, m2, r, st.W,
-                       st.ident, st.skip_abs, max_inner, st.rot, (const T*)nullptr, 0, m, T(0));
+                       st.ident, st.skip_abs, max_inner, st.rot, (const T*)nullptr, 0, m, T(0),
+                       (const BDesc<T>*)nullptr);
     JAC_CHECK_LAUNCH();
+    int e_mid = pf ? pf->mark(s) : -1;
+    if (pf) pf->interval(st.cls_inner, e_prev, e_mid);
     int nwg = ntile + m * nvchunk;
     hipLaunchKernelGGL((blk_update_kernel<T>), dim3(nwg), dim3(kNT), 0, s, st.Tm, st.ldt, st.V, st.ldv, st.nvr, st.W,
-                       st.ident, m2, r, ntile, nvchunk);
+                       st.ident, m2, r, ntile, nvchunk, work);
     JAC_CHECK_LAUNCH();
+    int e_end = pf ? pf->mark(s) : -1;
+    if (pf) pf->interval(st.cls_update, e_mid, e_end);
+    e_prev = e_end;
   }
   return 0;
 }
@@ -672,6 +693,143 @@ int blk_diag(const BlkState<T>& st, T* d, hipStream_t s) {
   JAC_CHECK_LAUNCH();
   return 0;
 }
+
+// ---------------------------------------------------------------- batched
+// All matrices of one size class (same np) advance through the block steps
+// together: grid.y runs over the class's matrices, each described by a BDesc.
+template <typename T>
+int blk_sweep_batched(const BDesc<T>* desc, int count, int np, int max_nvr, int max_inner, hipStream_t s) {
+  const int m2 = np / (kB2 / 2), m = m2 / 2;
+  const int ntile = m * (m - 1) / 2;
+  const int nvchunk = cdiv(max_nvr, kB2);
+  for (int r = 0; r < m2 - 1; ++r) {
+    hipLaunchKernelGGL((blk_inner_kernel<T>), dim3(m, count), dim3(kInnerThreads), 0, s, (T*)nullptr, 0, 0, m2, r,
+                       (T*)nullptr, (int*)nullptr, T(0), max_inner, (unsigned long long*)nullptr, (const T*)nullptr, 0,
+                       m, T(0), desc);
+    JAC_CHECK_LAUNCH();
+    hipLaunchKernelGGL((blk_update_kernel<T>), dim3(ntile + m * nvchunk, count), dim3(kNT), 0, s, (T*)nullptr, 0,
+                       (T*)nullptr, 0, 0, (const T*)nullptr, (const int*)nullptr, m2, r, ntile, nvchunk,
+                       (unsigned long long*)nullptr, desc);
+    JAC_CHECK_LAUNCH();
+  }
+  return 0;
+}
+
+// Per-matrix setup: T <- [A 0; 0 0] (np x np), V <- [I 0] (n x np), identity flags.
+template <typename T>
+__global__ void batched_init_kernel(const BDesc<T>* __restrict__ desc, const double* const* __restrict__ A,
+                                    const int* __restrict__ lda) {
+  const BDesc<T> d = desc[blockIdx.y];
+  const double* a = A[blockIdx.y];
+  const int la = lda[blockIdx.y];
+  const int np = d.ldt;
+  const long long total = (long long)np * np;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    int i = (int)(e % np), j = (int)(e / np);
+    d.Tm[i + (size_t)j * np] = (i < d.n && j < d.n) ? (T)a[i + (size_t)j * la] : T(0);
+    if (i < d.n) d.V[i + (size_t)j * d.ldv] = i == j ? T(1) : T(0);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *d.rot = 0;
+}
+
+// Per matrix: ||off(T)||_F^2 and ||T||_F^2 (one workgroup per matrix, fixed order).
+template <typename T>
+__global__ void batched_norms_kernel(const BDesc<T>* __restrict__ desc, double* __restrict__ out) {
+  __shared__ double red[2][4];
+  const BDesc<T> d = desc[blockIdx.x];
+  const int np = d.ldt;
+  double off = 0, all = 0;
+  for (long long e = threadIdx.x; e < (long long)np * np; e += blockDim.x) {
+    int i = (int)(e % np), j = (int)(e / np);
+    double v = d.Tm[i + (size_t)j * np];
+    all += v * v;
+    if (i != j) off += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) { off += __shfl_down(off, o, 64); all += __shfl_down(all, o, 64); }
+  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = off; red[1][threadIdx.x >> 6] = all; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    out[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+// Per matrix: W ascending with V's columns permuted alike, info (0 if
+// ||off(T)||_F <= tol ||A||_F after the last sweep, else 1) and the number of
+// sweeps until that test first held (norms[s] = (off^2, ||T||^2) after s sweeps).
+template <typename T>
+__global__ void batched_finish_kernel(const BDesc<T>* __restrict__ desc, double* const* __restrict__ W,
+                                      double* const* __restrict__ V, const int* __restrict__ ldv,
+                                      const double* __restrict__ norms, int stride, int nsweeps, double tol,
+                                      const int* __restrict__ orig, int* __restrict__ sweeps_out,
+                                      int* __restrict__ info) {
+  __shared__ int rank[512];
+  const BDesc<T> d = desc[blockIdx.x];
+  const int n = d.n;
+  double* w = W[blockIdx.x];
+  double* v = V[blockIdx.x];
+  const int lv = ldv[blockIdx.x];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    T di = d.Tm[i + (size_t)i * d.ldt];
+    int rk = 0;
+    for (int j = 0; j < n; ++j) {
+      T dj = d.Tm[j + (size_t)j * d.ldt];
+      rk += (dj < di) || (dj == di && j < i);
+    }
+    rank[i] = rk;
+    w[rk] = (double)di;
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const int rk = rank[j];
+    for (int row = threadIdx.x; row < n; row += blockDim.x)
+      v[row + (size_t)rk * lv] = (double)d.V[row + (size_t)j * d.ldv];
+  }
+  if (threadIdx.x == 0) {
+    const double nrm = sqrt(norms[2 * (size_t)blockIdx.x + 1]);
+    int first = -1;
+    for (int sw = 0; sw <= nsweeps; ++sw) {
+      double off = sqrt(norms[(size_t)sw * stride + 2 * (size_t)blockIdx.x]);
+      if (off <= tol * nrm) { first = sw; break; }
+    }
+    const int o = orig[blockIdx.x];
+    if (info) info[o] = first < 0 ? 1 : 0;
+    if (sweeps_out) sweeps_out[o] = first < 0 ? nsweeps : first;
+  }
+}
+
+template <typename T>
+int batched_init(const BDesc<T>* desc, int count, int maxnp, const double* const* A, const int* lda, hipStream_t s) {
+  int gx = cdiv((long long)maxnp * maxnp, 256);
+  if (gx > 64) gx = 64;
+  hipLaunchKernelGGL((batched_init_kernel<T>), dim3(gx, count), dim3(256), 0, s, desc, A, lda);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
+template <typename T>
+int batched_norms(const BDesc<T>* desc, int count, double* out, hipStream_t s) {
+  hipLaunchKernelGGL((batched_norms_kernel<T>), dim3(count), dim3(256), 0, s, desc, out);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
+template <typename T>
+int batched_finish(const BDesc<T>* desc, int count, double* const* W, double* const* V, const int* ldv,
+                   const double* norms, int stride, int nsweeps, double tol, const int* orig, int* sweeps_out,
+                   int* info, hipStream_t s) {
+  hipLaunchKernelGGL((batched_finish_kernel<T>), dim3(count), dim3(256), 0, s, desc, W, V, ldv, norms, stride,
+                     nsweeps, tol, orig, sweeps_out, info);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
+template int blk_sweep_batched<double>(const BDesc<double>*, int, int, int, int, hipStream_t);
+template int batched_init<double>(const BDesc<double>*, int, int, const double* const*, const int*, hipStream_t);
+template int batched_norms<double>(const BDesc<double>*, int, double*, hipStream_t);
+template int batched_finish<double>(const BDesc<double>*, int, double* const*, double* const*, const int*,
+                                    const double*, int, int, double, const int*, int*, int*, hipStream_t);
 
 #define INST(T)                                                                    \
   template int blk_load<T>(BlkState<T>&, const void*, bool, int, hipStream_t);     \

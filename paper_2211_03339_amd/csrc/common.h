@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 namespace jac {
 
@@ -24,6 +25,26 @@ const char* last_error();
   } while (0)
 
 #define JAC_CHECK_LAUNCH() JAC_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- profiling
+// Optional per-launch timing with HIP events recorded in the stream between
+// consecutive launches (classes as in jac_stats.kern_*).
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  int used = 0;
+  struct Iv { int cls, e0, e1; };
+  std::vector<Iv> ivs;
+  double ms[6] = {0, 0, 0, 0, 0, 0};
+  long long launches[6] = {0, 0, 0, 0, 0, 0};
+  unsigned long long* work = nullptr;   // device counters [6]
+  int mark(hipStream_t s);              // record an event, return its id (-1 if off)
+  void interval(int cls, int e0, int e1) {
+    if (on && e0 >= 0 && e1 >= 0) ivs.push_back({cls, e0, e1});
+  }
+  int flush();                          // after the stream is synchronised
+  ~Prof();
+};
 
 // ---------------------------------------------------------------- workspace
 // Grow-only device scratch owned by the library (one pool per device).
@@ -215,6 +236,8 @@ struct ElemState {
   double* scalars;      // [0] off^2 result, [1] fro^2 result
   unsigned long long* rot;  // per-sweep applied-rotation counters
   int cur;              // which Tp / A holds the current step
+  Prof* prof = nullptr;
+  int cls = 4;
 };
 
 // Pack / angles at the slot layout of step r (r = 0 at sweep boundaries).
@@ -233,6 +256,19 @@ int elem_unpack_dense(const ElemState<T>& st, int r, T* D, int ldd, hipStream_t 
 template <typename T>
 int elem_diag(const ElemState<T>& st, T* d, hipStream_t s);  // logical-order diagonal
 
+// Per-matrix descriptor of the batched path.
+template <typename T>
+struct BDesc {
+  T* Tm;                    // np x np, ldt = np
+  T* V;                     // n x np, leading dimension ldv
+  T* E;                     // (np / 64) pairs x 64 x 64
+  int* ident;               // per pair
+  unsigned long long* rot;  // applied rotations of this matrix
+  const double* nrm2;       // ||A||_F^2 of this matrix (written before the sweeps)
+  int n, ldt, ldv, pad;
+  double tol_n;             // tol / n: skip cap = tol_n * ||A||_F
+};
+
 // Blocked path (blocked.hip): in-place np x np T, blocks of b = blk_b2()/2.
 template <typename T>
 struct BlkState {
@@ -247,6 +283,8 @@ struct BlkState {
   double* partial;      // >= 1024
   double* scalars;      // [0] off^2
   unsigned long long* rot;  // applied rotations (cumulative)
+  Prof* prof = nullptr; // optional timing; classes cls_inner / cls_update
+  int cls_inner = 0, cls_update = 1;
 };
 int blk_np(int n);
 int blk_b2();
@@ -258,6 +296,16 @@ template <typename T>
 int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s);
 template <typename T>
 int blk_diag(const BlkState<T>& st, T* d, hipStream_t s);
+template <typename T>
+int blk_sweep_batched(const BDesc<T>* desc, int count, int np, int max_nvr, int max_inner, hipStream_t s);
+template <typename T>
+int batched_init(const BDesc<T>* desc, int count, int maxnp, const double* const* A, const int* lda, hipStream_t s);
+template <typename T>
+int batched_norms(const BDesc<T>* desc, int count, double* out, hipStream_t s);
+template <typename T>
+int batched_finish(const BDesc<T>* desc, int count, double* const* W, double* const* V, const int* ldv,
+                   const double* norms, int stride, int nsweeps, double tol, const int* orig, int* sweeps_out,
+                   int* info, hipStream_t s);
 
 // Utilities (util.hip).
 int fro2_f64(const double* A, int m, int n, int lda, double* partial, double* out, hipStream_t s);

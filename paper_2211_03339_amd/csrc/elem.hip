@@ -313,6 +313,8 @@ int elem_steps(ElemState<T>& st, long long gstep0, int nsteps, hipStream_t s) {
   const int nwgB = cdiv(st.h, kThreads);
   const int vchunks = cdiv(st.n, kThreads * kRPT);
   const int nwg = nwgT + nwgB + st.h * vchunks;
+  Prof* pf = st.prof;
+  int e_prev = pf ? pf->mark(s) : -1;
   for (int i = 0; i < nsteps; ++i) {
     long long g = gstep0 + i;
     int r = (int)(g % per);
@@ -322,6 +324,11 @@ int elem_steps(ElemState<T>& st, long long gstep0, int nsteps, hipStream_t s) {
                        st.A[c], st.A[c ^ 1], st.V, st.ldv, st.n, st.ne, r, next_sweep, st.nblk, nwgT,
                        nwgB, vchunks, st.skip_abs, st.rot);
     JAC_CHECK_LAUNCH();
+    if (pf) {
+      int e = pf->mark(s);
+      pf->interval(st.cls, e_prev, e);
+      e_prev = e;
+    }
     st.cur = c ^ 1;
   }
   return 0;

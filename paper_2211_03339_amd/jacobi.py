@@ -33,7 +33,7 @@ class JacOpts(ctypes.Structure):
                 ("max_sweeps", ctypes.c_int), ("fp32_tol", ctypes.c_double),
                 ("fp32_max_sweeps", ctypes.c_int), ("mlp", ctypes.c_void_p),
                 ("theta", ctypes.c_void_p), ("fallback_tol", ctypes.c_double),
-                ("inner_sweeps", ctypes.c_int)]
+                ("inner_sweeps", ctypes.c_int), ("profile", ctypes.c_int)]
 
 
 class JacStats(ctypes.Structure):
@@ -43,10 +43,18 @@ class JacStats(ctypes.Structure):
                 ("off0", ctypes.c_double), ("off_final", ctypes.c_double),
                 ("off_hist", ctypes.c_double * JAC_HIST), ("stage_ms", ctypes.c_float * 8),
                 ("step_ms", ctypes.c_double), ("step_launches", ctypes.c_longlong),
-                ("fp32_step_ms", ctypes.c_double), ("fp32_step_launches", ctypes.c_longlong)]
+                ("fp32_step_ms", ctypes.c_double), ("fp32_step_launches", ctypes.c_longlong),
+                ("kern_ms", ctypes.c_double * 6), ("kern_launches", ctypes.c_longlong * 6),
+                ("kern_work", ctypes.c_longlong * 6)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("off_hist", "stage_ms")}
+        d = {f: getattr(self, f) for f, _ in self._fields_
+             if f not in ("off_hist", "stage_ms", "kern_ms", "kern_launches", "kern_work")}
+        names = ["inner64", "update64", "inner32", "update32", "elem64", "elem32"]
+        d["kernels"] = {names[i]: {"ms": self.kern_ms[i], "launches": self.kern_launches[i],
+                                   "tiles": self.kern_work[i] >> 32 if i in (1, 3) else 0,
+                                   "chunks": self.kern_work[i] & 0xFFFFFFFF if i in (1, 3) else 0}
+                        for i in range(6) if self.kern_launches[i]}
         d["off_hist"] = list(self.off_hist[: self.sweeps + 1])
         d["stage_ms"] = dict(zip(["start", "mgs", "similarity", "sweeps", "output", "total", "checks"],
                                  list(self.stage_ms)[:7]))
@@ -82,6 +90,11 @@ def load():
         "gesvd_jacobi": (_i, [_vp, _i, _i, _i, _vp, _vp, _i, _vp, _i, _d, ctypes.POINTER(_i)]),
         "gesvd_jacobi_ex": (_i, [_vp, _i, _i, _i, _vp, _vp, _i, _vp, _i, _d, ctypes.POINTER(JacOpts),
                                  ctypes.POINTER(JacStats), _vp]),
+        "syev_jacobi_batched": (_i, [_i, ctypes.POINTER(_i), ctypes.POINTER(_vp), ctypes.POINTER(_i),
+                                     ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i), _d, _vp, _vp,
+                                     _vp]),
+        "jac_autotune_batched": (_i, [_i, ctypes.POINTER(_i), ctypes.POINTER(_vp), ctypes.POINTER(_i), _d, _vp]),
+        "jac_tune_entry": (_i, [_i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
         "jac_parallel_steps": (_i, [_vp, _i, _i, _vp, _i, _i, _i, _d,
                                     ctypes.POINTER(ctypes.c_longlong), _vp]),
         "jac_round_robin_pairs": (_i, [_i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
@@ -139,7 +152,7 @@ def _colmajor(M: torch.Tensor) -> torch.Tensor:
 
 
 def _opts(precond="fp32", variant="auto", block_b=0, max_sweeps=0, fp32_tol=0.0, fp32_max_sweeps=0,
-          fallback_tol=0.0, inner_sweeps=0):
+          fallback_tol=0.0, inner_sweeps=0, profile=0):
     o = JacOpts()
     o.precond = PRECOND[precond] if isinstance(precond, str) else int(precond)
     o.variant = VARIANT[variant] if isinstance(variant, str) else int(variant)
@@ -149,6 +162,7 @@ def _opts(precond="fp32", variant="auto", block_b=0, max_sweeps=0, fp32_tol=0.0,
     o.fp32_max_sweeps = fp32_max_sweeps
     o.fallback_tol = fallback_tol
     o.inner_sweeps = inner_sweeps
+    o.profile = profile
     return o
 
 
@@ -231,6 +245,48 @@ def gesvd_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", max_sweep
     d["rotations_per_sweep"] = list(st.off_hist[1: st.sweeps + 1])
     d.pop("off_hist")
     return S, Ub.t(), Vb.t(), d, code
+
+
+class Batch:
+    """Device buffers and pointer arrays for syev_jacobi_batched over a list of symmetric
+    matrices (kept alive so that repeated calls replay the same graph)."""
+
+    def __init__(self, mats):
+        self.A = [_dev(a).contiguous() for a in mats]    # symmetric: row/column-major agree
+        self.n = [a.shape[0] for a in self.A]
+        dev = self.A[0].device
+        self.W = [torch.empty(n, dtype=torch.float64, device=dev) for n in self.n]
+        self.V = [torch.empty((n, n), dtype=torch.float64, device=dev) for n in self.n]
+        b = len(self.A)
+        self.sweeps = torch.zeros(b, dtype=torch.int32, device=dev)
+        self.info = torch.zeros(b, dtype=torch.int32, device=dev)
+        self.c_n = (_i * b)(*self.n)
+        self.c_A = (_vp * b)(*[a.data_ptr() for a in self.A])
+        self.c_W = (_vp * b)(*[w.data_ptr() for w in self.W])
+        self.c_V = (_vp * b)(*[v.data_ptr() for v in self.V])
+        self.c_ld = (_i * b)(*self.n)
+
+    def run(self, tol: float = 0.0, stream=None):
+        L = load()
+        code = L.syev_jacobi_batched(len(self.A), self.c_n, self.c_A, self.c_ld, self.c_W, self.c_V, self.c_ld, tol,
+                                     _vp(self.sweeps.data_ptr()), _vp(self.info.data_ptr()),
+                                     stream if stream is not None else _stream())
+        _check("syev_jacobi_batched", code)
+
+    def autotune(self, tol: float = 0.0):
+        L = load()
+        code = L.jac_autotune_batched(len(self.A), self.c_n, self.c_A, self.c_ld, tol, _stream())
+        _check("jac_autotune_batched", code)
+
+    def results(self):
+        """(W list, V list (columns = eigenvectors), sweeps, info) after the stream completed."""
+        return self.W, [v.t() for v in self.V], self.sweeps.cpu().numpy(), self.info.cpu().numpy()
+
+
+def jac_tune_entry(n: int):
+    a, b = _i(0), _i(0)
+    load().jac_tune_entry(n, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
 
 
 def jac_parallel_steps(T: torch.Tensor, V: torch.Tensor | None, r0: int, nsteps: int, skip_abs: float = 0.0):
