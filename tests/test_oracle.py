@@ -297,3 +297,49 @@ def test_svd_2col_rotation():
     B = out.C
     assert abs(B[:, 0] @ B[:, 1]) < 1e-14 * np.linalg.norm(C) ** 2
     assert abs((B ** 2).sum() - (C ** 2).sum()) < 1e-13
+
+
+# ---------------------------------------------------------------- MLP reference
+def test_mlp_oracle_finite_differences():
+    """Backward pass of the reference network against central differences (rounding off)."""
+    from oracle import mlp
+    I, H, O, B = 3, 5, 4, 6
+    g = tm.rng(31)
+    npar = sum(int(np.prod(s)) for s in mlp.shapes(I, H, O))
+    p = g.standard_normal(npar) * 0.5
+    X = g.standard_normal((B, I))
+    T = g.standard_normal((B, O))
+    loss, grad = mlp.loss_and_grads(p, X, T, I, H, O, use_bf16=False)
+    h = 1e-6
+    for k in range(npar):
+        e = np.zeros(npar)
+        e[k] = h
+        lp, _ = mlp.loss_and_grads(p + e, X, T, I, H, O, use_bf16=False)
+        lm, _ = mlp.loss_and_grads(p - e, X, T, I, H, O, use_bf16=False)
+        assert abs((lp - lm) / (2 * h) - grad[k]) <= 1e-7 * max(1.0, abs(grad[k]))
+
+
+def test_mlp_oracle_bf16_rounding():
+    from oracle import mlp
+    x = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -9, -2.5, 0.0, 1e-40])
+    r = mlp.bf16(x)
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2.0 ** -7 and r[3] == -2.5 and r[4] == 0.0
+    # 8 significant bits: unit roundoff 2^-8
+    y = tm.rng(5).standard_normal(1000)
+    assert np.all(np.abs(mlp.bf16(y) - y) <= 2.0 ** -8 * np.abs(y))
+
+
+def test_mlp_oracle_adamw_closed_form():
+    """First AdamW step moves every parameter by lr * (sign(g) + wd p) (m_hat / sqrt(v_hat) = sign g)."""
+    from oracle import mlp
+    p = np.array([1.0, -2.0, 0.5])
+    gr = np.array([0.3, -0.1, 2.0])
+    p1, m, v = mlp.adamw(p, gr, np.zeros(3), np.zeros(3), 1, lr=0.01, wd=0.1, eps=0.0)
+    np.testing.assert_allclose(p1, p - 0.01 * (np.sign(gr) + 0.1 * p), rtol=1e-14)
+
+
+def test_canonical_signs():
+    from oracle import mlp
+    V = np.array([[0.6, -0.8], [-0.8, -0.6]])
+    C = mlp.canonical_signs(V)
+    np.testing.assert_array_equal(C, [[-0.6, 0.8], [0.8, 0.6]])
