@@ -88,6 +88,7 @@ typedef struct jac_stats {
   double kern_ms[6];
   long long kern_launches[6];
   long long kern_work[6];
+  double start_resid;      /* precond MLP: ||off(Q^T A Q)||_F / ||A||_F of the predicted start */
 } jac_stats;
 
 /* Symmetric eigendecomposition A = V diag(W) V^T by Algorithm 4.1
@@ -151,6 +152,71 @@ int jac_autotune_batched(int batch, const int* n, const double* const* A, const 
 
 /* Host: the (inner-sweep cap, sweep count) the batched path uses for order n. */
 int jac_tune_entry(int n, int* inner_sweeps, int* sweeps);
+
+/* ---- Learned warm start (a project addition; not in the paper) ------------
+ * A three-layer perceptron theta (n_in values) -> hidden -> ReLU -> hidden ->
+ * ReLU -> n^2 values, read as the column-major entries of an approximate
+ * eigenvector matrix Z of A(theta).  With opts.precond = JAC_PRECOND_MLP,
+ * syev_jacobi_ex uses Z in place of the FP32 eigensolve of Algorithm 4.1
+ * step 1: Q = MGS(Z), T = Q^T A Q; if ||off(T)||_F / ||A||_F exceeds
+ * opts.fallback_tol (default 1e-2) or MGS meets a zero column, the FP32 start
+ * is computed and used instead (jac_stats.used_fallback = 1).
+ * Every matrix product takes bfloat16 operands (round to nearest even from
+ * FP32) and accumulates in FP32; biases, activations, gradients, FP32 master
+ * weights and AdamW moments are FP32.  Parameters are packed row-major as
+ * [W1 (hidden x n_in), b1, W2 (hidden x hidden), b2, W3 (n^2 x hidden), b3].
+ * Activations are row-major (batch x features).  A handle owns its device
+ * memory (about 16 bytes per parameter plus activations for max_batch rows);
+ * calls that use one handle must not overlap (they share its buffers). */
+enum { JAC_MLP_PARAMS = 0, JAC_MLP_GRADS = 1, JAC_MLP_MOMENT1 = 2, JAC_MLP_MOMENT2 = 3 };
+
+/* New network on the current device: weights uniform in [-a, a] from
+ * SplitMix64(seed, index) (a = sqrt(6/n_in), sqrt(6/hidden), sqrt(3/hidden)
+ * per layer), biases and moments zero.  1 <= n_in <= 32, hidden a positive
+ * multiple of 32, n^2 a multiple of 32, max_batch >= 1.  Errors: -1..-4 for
+ * those arguments, -6 out NULL, 4 allocation failure. */
+int jac_mlp_create(int n_in, int hidden, int n, int max_batch, unsigned long long seed, struct jac_mlp** out);
+void jac_mlp_free(struct jac_mlp* net);
+long long jac_mlp_num_params(const struct jac_mlp* net);
+/* Shape and optimiser step count (host pointers, each may be NULL). */
+int jac_mlp_shape(const struct jac_mlp* net, int* n_in, int* hidden, int* n, int* max_batch, long long* steps);
+/* Copy one packed buffer (JAC_MLP_*) to / from host memory (num_params floats).
+ * Synchronises the device.  Setting the parameters refreshes the bfloat16
+ * weight copies; moments and step count are left as they are. */
+int jac_mlp_get(const struct jac_mlp* net, int which, float* host);
+int jac_mlp_set(struct jac_mlp* net, int which, const float* host);
+/* AdamW hyper-parameters (defaults 0.9, 0.999, 1e-8) and step count t. */
+int jac_mlp_set_adam(struct jac_mlp* net, float beta1, float beta2, float eps, long long steps);
+/* Y (device, batch x n^2 FP32, row stride ldy >= n^2) = network(theta)
+ * for theta (device, batch x n_in FP32, row-major), 0 <= batch <= max_batch. */
+int jac_mlp_forward(struct jac_mlp* net, const float* theta, int batch, float* Y, int ldy, void* stream);
+/* Z (device, column-major n x n FP64, ldz >= n) for one theta (device). */
+int jac_mlp_predict(const struct jac_mlp* net, const float* theta, double* Z, int ldz, void* stream);
+/* Mean squared error over batch x n^2 outputs against target (device,
+ * bfloat16 bits, row stride ldt >= n^2) and its gradient, left in the handle
+ * (JAC_MLP_GRADS).  loss: device float, may be NULL.  1 <= batch <= max_batch. */
+int jac_mlp_grads(struct jac_mlp* net, const float* theta, const unsigned short* target, long long ldt, int batch,
+                  float* loss, void* stream);
+/* One AdamW step (decoupled weight decay) with the gradient in the handle:
+ * t += 1, m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m/(1-b1^t) / (sqrt(v/(1-b2^t)) + eps) + weight_decay p). */
+int jac_mlp_adamw(struct jac_mlp* net, float lr, float weight_decay, void* stream);
+/* jac_mlp_grads followed by jac_mlp_adamw. */
+int jac_mlp_train_step(struct jac_mlp* net, const float* theta, const unsigned short* target, long long ldt,
+                       int batch, float lr, float weight_decay, float* loss, void* stream);
+/* Training targets from eigenvector matrices: for matrix c (device V +
+ * c stride_v, column-major n x n, ldv >= n) every column is multiplied by the
+ * sign of its entry of largest magnitude (the first one on ties) and its
+ * column-major entries are written, rounded to bfloat16 from FP32, to
+ * T + c ldt (device).  count <= 65535. */
+int jac_mlp_pack_targets(const double* V, int n, int ldv, long long stride_v, int count, unsigned short* T,
+                         long long ldt, void* stream);
+/* Weights, AdamW moments, step count and hyper-parameters to / from a file
+ * ("JACMLP01", int32 n_in, hidden, n, int64 t, float beta1, beta2, eps, then
+ * the weights, first and second moments as num_params floats each).  Loading
+ * checks the shape (6 on mismatch); 5 on an I/O error. */
+int jac_mlp_save(const struct jac_mlp* net, const char* path);
+int jac_mlp_load(struct jac_mlp* net, const char* path);
 
 /* ---- Stages of the path, callable on their own --------------------------- */
 

@@ -422,8 +422,14 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
   }
   if (n == 0) return 0;
   if (o.precond == JAC_PRECOND_MLP) {
-    set_error("syev_jacobi_ex: the learned start needs the MLP entry points");
-    return -8;
+    if (!o.mlp || !o.theta) {
+      set_error("syev_jacobi_ex: the learned start needs opts.mlp and opts.theta");
+      return -8;
+    }
+    if (mlp_order(o.mlp) != n) {
+      set_error("syev_jacobi_ex: the network predicts eigenvectors of another order");
+      return -8;
+    }
   }
   Timer tm(s, stats != nullptr);
   tm.mark(0);
@@ -487,7 +493,37 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
     double* T0 = c.take<double>((size_t)n * n);
     T0p = T0;
     double* mscr = c.take<double>(mgs_scratch_elems(n, n));
-    if (pre == JAC_PRECOND_FP32) {
+    bool accepted = false;
+    if (pre == JAC_PRECOND_MLP) {
+      // Learned start: Z -> MGS -> T = Q^T A Q; kept when ||off(T)||_F / ||A||_F <= fallback_tol
+      // and MGS met no zero column, else replaced by the FP32 start.
+      e = mlp_predict_f64(o.mlp, o.theta, Vw, n, s);
+      if (e) return e;
+      tm.mark(2);
+      e = mgs_f64(Vw, n, n, n, mscr, hd.flag, s);
+      if (e) return e;
+      tm.mark(3);
+      e = similarity(A, n, lda, Vw, n, T0, n, Wg, s);
+      if (e) return e;
+      e = off2_f64(T0, n, n, hd.partial, hd.scal + 2, s);
+      if (e) return e;
+      double off2 = 0;
+      JAC_HIP(hipMemcpyAsync(&off2, hd.scal + 2, 8, hipMemcpyDeviceToHost, s));
+      JAC_HIP(hipMemcpyAsync(&hflag, hd.flag, 4, hipMemcpyDeviceToHost, s));
+      JAC_HIP(hipStreamSynchronize(s));
+      const double r = hflag ? HUGE_VAL : std::sqrt(off2) / nrm;
+      const double ftol = o.fallback_tol > 0 ? o.fallback_tol : 1e-2;
+      if (stats) stats->start_resid = r;
+      if (r <= ftol) {
+        accepted = true;
+      } else {
+        if (stats) stats->used_fallback = 1;
+        JAC_HIP(hipMemsetAsync(hd.flag, 0, 16 * sizeof(int), s));
+      }
+    }
+    if (accepted) {
+      // T0 and Q already hold the accepted start.
+    } else if (pre == JAC_PRECOND_FP32 || pre == JAC_PRECOND_MLP) {
       double tol32 = o.fp32_tol > 0 ? o.fp32_tol : 1e-6;
       int max32 = o.fp32_max_sweeps > 0 ? o.fp32_max_sweeps : 30;
       int sw32 = 0;
@@ -507,12 +543,14 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
       e = copy_convert<double, double>(Q0, n, n, ldq, Vw, n, s);
       if (e) return e;
     }
-    tm.mark(2);
-    e = mgs_f64(Vw, n, n, n, mscr, hd.flag, s);
-    if (e) return e;
-    tm.mark(3);
-    e = similarity(A, n, lda, Vw, n, T0, n, Wg, s);
-    if (e) return e;
+    if (!accepted) {
+      tm.mark(2);
+      e = mgs_f64(Vw, n, n, n, mscr, hd.flag, s);
+      if (e) return e;
+      tm.mark(3);
+      e = similarity(A, n, lda, Vw, n, T0, n, Wg, s);
+      if (e) return e;
+    }
     e = elem_pack<double>(st, T0, n, 0, s);
     if (e) return e;
     JAC_HIP(hipMemcpyAsync(&hflag, hd.flag, 4, hipMemcpyDeviceToHost, s));

@@ -9,6 +9,8 @@
 #include <string>
 #include <vector>
 
+struct jac_mlp;
+
 namespace jac {
 
 // ---------------------------------------------------------------- errors
@@ -309,6 +311,11 @@ int batched_finish(const BDesc<T>* desc, int count, double* const* W, double* co
 
 // Utilities (util.hip).
 int fro2_f64(const double* A, int m, int n, int lda, double* partial, double* out, hipStream_t s);
+// ||off(T)||_F^2 of a full n x n matrix (diagonal excluded).
+int off2_f64(const double* T, int n, int ldt, double* partial, double* out, hipStream_t s);
+// Learned start: Z (column-major, ldz) for one theta (device); order n of the network.
+int mlp_predict_f64(const jac_mlp* net, const float* theta, double* Z, int ldz, hipStream_t s);
+int mlp_order(const jac_mlp* net);
 template <typename T>
 int set_identity(T* V, int n, int ldv, hipStream_t s);
 template <typename Tin, typename Tout>

@@ -50,6 +50,33 @@ int fro2_f64(const double* A, int m, int n, int lda, double* partial, double* ou
   return 0;
 }
 
+__global__ void off2_partial_kernel(const double* __restrict__ T, int n, int ldt, double* __restrict__ partial) {
+  __shared__ double red[4];
+  double acc = 0;
+  long long total = (long long)n * n;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    int j = (int)(e / n), i = (int)(e % n);
+    double v = i == j ? 0.0 : T[i + (size_t)j * ldt];
+    acc += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+int off2_f64(const double* T, int n, int ldt, double* partial, double* out, hipStream_t s) {
+  int nwg = cdiv((long long)n * n, 256);
+  if (nwg > 1024) nwg = 1024;
+  if (nwg < 1) nwg = 1;
+  hipLaunchKernelGGL(off2_partial_kernel, dim3(nwg), dim3(256), 0, s, T, n, ldt, partial);
+  JAC_CHECK_LAUNCH();
+  hipLaunchKernelGGL(sum_partials_kernel2, dim3(1), dim3(1024), 0, s, partial, nwg, out);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
 __global__ void finite_kernel(const double* __restrict__ A, int m, int n, int lda, int* flag) {
   long long total = (long long)m * n;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;

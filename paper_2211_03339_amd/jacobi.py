@@ -45,7 +45,7 @@ class JacStats(ctypes.Structure):
                 ("step_ms", ctypes.c_double), ("step_launches", ctypes.c_longlong),
                 ("fp32_step_ms", ctypes.c_double), ("fp32_step_launches", ctypes.c_longlong),
                 ("kern_ms", ctypes.c_double * 6), ("kern_launches", ctypes.c_longlong * 6),
-                ("kern_work", ctypes.c_longlong * 6)]
+                ("kern_work", ctypes.c_longlong * 6), ("start_resid", ctypes.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_
@@ -104,6 +104,23 @@ def load():
         "jac_gemm_f64": (_i, [_i, _i, _i, _i, _i, _d, _vp, _i, _vp, _i, _d, _vp, _i, _vp]),
         "jac_gemm_f32": (_i, [_i, _i, _i, _i, _i, ctypes.c_float, _vp, _i, _vp, _i, ctypes.c_float,
                               _vp, _i, _vp]),
+        "jac_mlp_create": (_i, [_i, _i, _i, _i, ctypes.c_ulonglong, ctypes.POINTER(_vp)]),
+        "jac_mlp_free": (None, [_vp]),
+        "jac_mlp_num_params": (ctypes.c_longlong, [_vp]),
+        "jac_mlp_shape": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i),
+                               ctypes.POINTER(ctypes.c_longlong)]),
+        "jac_mlp_get": (_i, [_vp, _i, _vp]),
+        "jac_mlp_set": (_i, [_vp, _i, _vp]),
+        "jac_mlp_set_adam": (_i, [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_longlong]),
+        "jac_mlp_forward": (_i, [_vp, _vp, _i, _vp, _i, _vp]),
+        "jac_mlp_predict": (_i, [_vp, _vp, _vp, _i, _vp]),
+        "jac_mlp_grads": (_i, [_vp, _vp, _vp, ctypes.c_longlong, _i, _vp, _vp]),
+        "jac_mlp_adamw": (_i, [_vp, ctypes.c_float, ctypes.c_float, _vp]),
+        "jac_mlp_train_step": (_i, [_vp, _vp, _vp, ctypes.c_longlong, _i, ctypes.c_float, ctypes.c_float, _vp,
+                                    _vp]),
+        "jac_mlp_pack_targets": (_i, [_vp, _i, _i, ctypes.c_longlong, _i, _vp, ctypes.c_longlong, _vp]),
+        "jac_mlp_save": (_i, [_vp, ctypes.c_char_p]),
+        "jac_mlp_load": (_i, [_vp, ctypes.c_char_p]),
         "jac_workspace_bytes": (ctypes.c_size_t, [_i, ctypes.POINTER(JacOpts)]),
         "jac_release_workspace": (None, []),
         "jac_last_error": (ctypes.c_char_p, []),
@@ -152,8 +169,12 @@ def _colmajor(M: torch.Tensor) -> torch.Tensor:
 
 
 def _opts(precond="fp32", variant="auto", block_b=0, max_sweeps=0, fp32_tol=0.0, fp32_max_sweeps=0,
-          fallback_tol=0.0, inner_sweeps=0, profile=0):
+          fallback_tol=0.0, inner_sweeps=0, profile=0, mlp=None, theta=None):
     o = JacOpts()
+    if mlp is not None:
+        o.mlp = mlp.h.value
+    if theta is not None:
+        o.theta = _dev(theta, torch.float32).data_ptr()
     o.precond = PRECOND[precond] if isinstance(precond, str) else int(precond)
     o.variant = VARIANT[variant] if isinstance(variant, str) else int(variant)
     o.block_b = block_b
@@ -183,15 +204,20 @@ def syev_jacobi(A: torch.Tensor, tol: float = 0.0):
 
 
 def syev_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", variant="auto", max_sweeps=0,
-                   fp32_tol=0.0, fp32_max_sweeps=0, block_b=0, allow_unconverged=False, inner_sweeps=0):
-    """Returns (W, V, stats dict, info)."""
+                   fp32_tol=0.0, fp32_max_sweeps=0, block_b=0, allow_unconverged=False, inner_sweeps=0,
+                   mlp=None, theta=None, fallback_tol=0.0, profile=0):
+    """Returns (W, V, stats dict, info).  precond="mlp" takes the network `mlp` (Mlp) and its
+    input `theta` (device float32 tensor of n_in values)."""
+    if theta is not None:
+        theta = _dev(theta, torch.float32).contiguous()
     L = load()
     A = _dev(A)
     n = A.shape[0]
     Ac = _colmajor(A)
     W = torch.empty(n, dtype=torch.float64, device=A.device)
     Vb = torch.empty((n, n), dtype=torch.float64, device=A.device)
-    o = _opts(precond, variant, block_b, max_sweeps, fp32_tol, fp32_max_sweeps, inner_sweeps=inner_sweeps)
+    o = _opts(precond, variant, block_b, max_sweeps, fp32_tol, fp32_max_sweeps, fallback_tol=fallback_tol,
+              inner_sweeps=inner_sweeps, profile=profile, mlp=mlp, theta=theta)
     st = JacStats()
     code = L.syev_jacobi_ex(_vp(Ac.data_ptr()), n, max(n, 1), _vp(W.data_ptr()), _vp(Vb.data_ptr()),
                             max(n, 1), tol, ctypes.byref(o), ctypes.byref(st), _stream())
@@ -363,3 +389,108 @@ def jac_gemm(A: torch.Tensor, B: torch.Tensor, transa=False, transb=False):
               _vp(Bc.data_ptr()), max(B.shape[0], 1), 0.0, _vp(Cb.data_ptr()), max(m, 1), _stream())
     _check("jac_gemm", code)
     return Cb.t()
+
+
+# ------------------------------------------------------------------ learned warm start
+MLP_PARAMS, MLP_GRADS, MLP_MOMENT1, MLP_MOMENT2 = 0, 1, 2, 3
+
+
+class Mlp:
+    """Handle of a jac_mlp network (theta -> n x n eigenvector guess).  Buffers are
+    exchanged as numpy float32 arrays (host); theta, targets and outputs as device tensors."""
+
+    def __init__(self, n_in: int, hidden: int, n: int, max_batch: int, seed: int = 0):
+        L = load()
+        h = _vp()
+        _check("jac_mlp_create", L.jac_mlp_create(n_in, hidden, n, max_batch, seed, ctypes.byref(h)))
+        self.h = h
+        self.n_in, self.hidden, self.n, self.max_batch = n_in, hidden, n, max_batch
+        self.P = int(L.jac_mlp_num_params(h))
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            load().jac_mlp_free(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shape(self):
+        a, b, c, d = _i(), _i(), _i(), _i()
+        t = ctypes.c_longlong()
+        _check("jac_mlp_shape", load().jac_mlp_shape(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                                      ctypes.byref(d), ctypes.byref(t)))
+        return a.value, b.value, c.value, d.value, t.value
+
+    def get(self, which: int = MLP_PARAMS):
+        import numpy as np
+        out = np.empty(self.P, dtype=np.float32)
+        _check("jac_mlp_get", load().jac_mlp_get(self.h, which, out.ctypes.data_as(_vp)))
+        return out
+
+    def set(self, values, which: int = MLP_PARAMS):
+        import numpy as np
+        v = np.ascontiguousarray(values, dtype=np.float32)
+        if v.size != self.P:
+            raise ValueError(f"expected {self.P} values, got {v.size}")
+        _check("jac_mlp_set", load().jac_mlp_set(self.h, which, v.ctypes.data_as(_vp)))
+
+    def set_adam(self, beta1=0.9, beta2=0.999, eps=1e-8, steps=0):
+        _check("jac_mlp_set_adam", load().jac_mlp_set_adam(self.h, beta1, beta2, eps, steps))
+
+    def forward(self, theta: torch.Tensor) -> torch.Tensor:
+        theta = _dev(theta, torch.float32).contiguous()
+        B = theta.shape[0]
+        Y = torch.empty((B, self.n * self.n), dtype=torch.float32, device=theta.device)
+        _check("jac_mlp_forward", load().jac_mlp_forward(self.h, _vp(theta.data_ptr()), B, _vp(Y.data_ptr()),
+                                                          self.n * self.n, _stream()))
+        return Y
+
+    def predict(self, theta: torch.Tensor) -> torch.Tensor:
+        """Z (n x n FP64) for one theta; columns are the predicted eigenvectors."""
+        theta = _dev(theta, torch.float32).contiguous()
+        Zc = torch.empty((self.n, self.n), dtype=torch.float64, device=theta.device)
+        _check("jac_mlp_predict", load().jac_mlp_predict(self.h, _vp(theta.data_ptr()), _vp(Zc.data_ptr()),
+                                                          self.n, _stream()))
+        return Zc.t()
+
+    def grads(self, theta: torch.Tensor, target: torch.Tensor, loss: torch.Tensor | None = None):
+        theta = _dev(theta, torch.float32).contiguous()
+        target = _dev(target, torch.int16)
+        _check("jac_mlp_grads", load().jac_mlp_grads(self.h, _vp(theta.data_ptr()), _vp(target.data_ptr()),
+                                                      target.stride(0), theta.shape[0],
+                                                      None if loss is None else _vp(loss.data_ptr()), _stream()))
+
+    def adamw(self, lr: float, weight_decay: float = 0.0):
+        _check("jac_mlp_adamw", load().jac_mlp_adamw(self.h, lr, weight_decay, _stream()))
+
+    def train_step(self, theta: torch.Tensor, target: torch.Tensor, lr: float, weight_decay: float = 0.0,
+                   loss: torch.Tensor | None = None):
+        """theta: (B, n_in) float32; target: (B, >= n^2) int16 holding bfloat16 bits (row stride
+        target.stride(0)); loss: optional device float32 scalar written with the batch loss."""
+        _check("jac_mlp_train_step", load().jac_mlp_train_step(
+            self.h, _vp(theta.data_ptr()), _vp(target.data_ptr()), target.stride(0), theta.shape[0], lr,
+            weight_decay, None if loss is None else _vp(loss.data_ptr()), _stream()))
+
+    def save(self, path: str):
+        _check("jac_mlp_save", load().jac_mlp_save(self.h, path.encode()))
+
+    def load_file(self, path: str):
+        _check("jac_mlp_load", load().jac_mlp_load(self.h, path.encode()))
+
+
+def jac_mlp_pack_targets(V: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Sign-canonicalised bfloat16 training targets of a stack of eigenvector matrices.
+    V: (count, n, n) FP64, V[c][:, j] = eigenvector j.  Returns (count, n*n) int16 bfloat16 bits,
+    row c = column-major entries of V[c] with every column's largest-|entry| made positive."""
+    V = _dev(V)
+    count, n, _ = V.shape
+    Vc = V.transpose(1, 2).contiguous()          # row-major buffer of V^T = column-major V
+    if out is None:
+        out = torch.empty((count, n * n), dtype=torch.int16, device=V.device)
+    _check("jac_mlp_pack_targets", load().jac_mlp_pack_targets(_vp(Vc.data_ptr()), n, n, n * n, count,
+                                                                _vp(out.data_ptr()), out.stride(0), _stream()))
+    return out

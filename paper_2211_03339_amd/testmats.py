@@ -165,6 +165,37 @@ def param_matrix(A0, B, theta) -> np.ndarray:
     return np.asfortranarray(0.5 * (A + A.T))
 
 
+# ---- learned warm start: network parameters, inputs and targets -----------------
+
+def mlp_params(I: int, H: int, O: int, seed: int = 6) -> np.ndarray:
+    """Packed float32 parameters [W1 (H x I), b1, W2 (H x H), b2, W3 (O x H), b3] drawn N(0, s^2)
+    with s = sqrt(2/fan_in) (W1, W2), sqrt(1/H) (W3), 0.1 (biases)."""
+    g = rng(seed)
+    parts = [g.standard_normal(H * I) * np.sqrt(2.0 / I), 0.1 * g.standard_normal(H),
+             g.standard_normal(H * H) * np.sqrt(2.0 / H), 0.1 * g.standard_normal(H),
+             g.standard_normal(O * H) * np.sqrt(1.0 / H), 0.1 * g.standard_normal(O)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_inputs(B: int, I: int, seed: int = 7) -> np.ndarray:
+    return rng(seed).uniform(-1.0, 1.0, (B, I)).astype(np.float32)
+
+
+def bf16_bits(shape, seed: int = 8, emin: int = 118, emax: int = 126) -> np.ndarray:
+    """Random bfloat16 bit patterns (int16): random sign and mantissa, biased exponent uniform in
+    [emin, emax] (magnitudes in [2^(emin-127), 2^(emax-126)))."""
+    g = rng(seed)
+    sign = g.integers(0, 2, shape, dtype=np.uint32)
+    exp = g.integers(emin, emax + 1, shape, dtype=np.uint32)
+    man = g.integers(0, 128, shape, dtype=np.uint32)
+    return ((sign << 15) | (exp << 7) | man).astype(np.uint16).view(np.int16)
+
+
+def bf16_value(bits: np.ndarray) -> np.ndarray:
+    """float64 value of bfloat16 bit patterns (exact)."""
+    return (np.asarray(bits).view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
 # ---- rectangular SVD inputs ---------------------------------------------------
 
 def svd_case(m: int, n: int, decades: float = 6.0, seed: int = 5_002_048):

@@ -1,0 +1,269 @@
+"""Learned warm start on the GPU (through the C-ABI) against the FP64 CPU reference in oracle/mlp.py.
+
+The GPU network rounds every product operand to bfloat16 and accumulates in FP32; the reference
+rounds the same operands the same way and accumulates in FP64.  The difference is the FP32
+accumulation error (about K 2^-24 relative to the sum of |terms| for a K-term product) plus the
+rare operand whose bfloat16 rounding flips because its FP32 and FP64 values straddle a rounding
+boundary, so forward outputs and gradients are compared at 1e-4 relative (Frobenius, per
+parameter block).  Target packing is byte work and is compared bit for bit.
+"""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as ref
+import oracle
+from paper_2211_03339_amd import jacobi
+from paper_2211_03339_amd import testmats as tm
+
+pytestmark = pytest.mark.gpu
+
+SMALL = (8, 96, 16)   # I, H, n: O = 256; H < 128 leaves ragged GEMM tiles
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def blocks(v, I, H, O):
+    return dict(zip(["W1", "b1", "W2", "b2", "W3", "b3"], ref.unpack(np.asarray(v, np.float64), I, H, O)))
+
+
+def make_net(I, H, n, B, seed=6):
+    net = jacobi.Mlp(I, H, n, B, seed=1)
+    p = tm.mlp_params(I, H, n * n, seed=seed)
+    net.set(p)
+    return net, p
+
+
+@pytest.mark.parametrize("B", [1, 5, 130])
+def test_forward_matches_reference(B):
+    I, H, n = SMALL
+    O = n * n
+    print(f"[mlp forward] I={I} H={H} n={n} B={B}", flush=True)
+    net, p = make_net(I, H, n, max(B, 4))
+    X = tm.mlp_inputs(B, I, seed=7 + B)
+    Y = net.forward(dev(X)).cpu().numpy().astype(np.float64)
+    Yr, _ = ref.forward(p.astype(np.float64), X.astype(np.float64), I, H, O, use_bf16=True)
+    err = np.linalg.norm(Y - Yr) / np.linalg.norm(Yr)
+    assert err <= 1e-5, err
+    # bf16 rounding of the operands matters at this tolerance: the unrounded network is farther off
+    Yf, _ = ref.forward(p.astype(np.float64), X.astype(np.float64), I, H, O, use_bf16=False)
+    assert np.linalg.norm(Yf - Yr) / np.linalg.norm(Yr) > 10 * err
+    net.close()
+
+
+def test_predict_layout_is_column_major():
+    I, H, n = SMALL
+    net, p = make_net(I, H, n, 2)
+    X = tm.mlp_inputs(1, I, seed=9)
+    Y = net.forward(dev(X)).cpu().numpy()[0]
+    Z = net.predict(dev(X[0])).cpu().numpy()
+    # Z[i, j] = Y[i + n j], converted to FP64 exactly
+    assert np.array_equal(Z, Y.reshape(n, n).T.astype(np.float64))
+    net.close()
+
+
+@pytest.mark.parametrize("B", [3, 37])
+def test_gradients_match_reference(B):
+    I, H, n = SMALL
+    O = n * n
+    print(f"[mlp grads] B={B}", flush=True)
+    net, p = make_net(I, H, n, 64)
+    X = tm.mlp_inputs(B, I, seed=11 + B)
+    Tb = tm.bf16_bits((B, O), seed=12 + B)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    net.grads(dev(X), dev(Tb), loss)
+    g = net.get(jacobi.MLP_GRADS)
+    lr_, gr = ref.loss_and_grads(p.astype(np.float64), X.astype(np.float64), tm.bf16_value(Tb), I, H, O, True)
+    assert abs(loss.item() - lr_) <= 1e-5 * lr_, (loss.item(), lr_)
+    gb, rb = blocks(g, I, H, O), blocks(gr, I, H, O)
+    for k in gb:
+        err = np.linalg.norm(gb[k] - rb[k]) / np.linalg.norm(rb[k])
+        print(f"  {k}: rel err {err:.2e}", flush=True)
+        assert err <= 1e-4, (k, err)
+    net.close()
+
+
+def test_gradients_at_full_size():
+    """theta (8) -> 1024 -> 1024 -> 256^2: split-K products over K = 65536 and 512 output tiles."""
+    I, H, n, B = 8, 1024, 256, 3
+    O = n * n
+    net, p = make_net(I, H, n, B, seed=21)
+    X = tm.mlp_inputs(B, I, seed=22)
+    Tb = tm.bf16_bits((B, O), seed=23)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    net.grads(dev(X), dev(Tb), loss)
+    g = net.get(jacobi.MLP_GRADS)
+    Y = net.forward(dev(X)).cpu().numpy().astype(np.float64)
+    p64 = p.astype(np.float64)
+    Yr, _ = ref.forward(p64, X.astype(np.float64), I, H, O, True)
+    assert np.linalg.norm(Y - Yr) / np.linalg.norm(Yr) <= 1e-5
+    lr_, gr = ref.loss_and_grads(p64, X.astype(np.float64), tm.bf16_value(Tb), I, H, O, True)
+    assert abs(loss.item() - lr_) <= 1e-5 * lr_
+    gb, rb = blocks(g, I, H, O), blocks(gr, I, H, O)
+    for k in gb:
+        err = np.linalg.norm(gb[k] - rb[k]) / np.linalg.norm(rb[k])
+        print(f"  {k}: rel err {err:.2e}", flush=True)
+        assert err <= 1e-4, (k, err)
+    net.close()
+
+
+def test_adamw_step_matches_reference():
+    """One step with eps = 1 (the update is then nearly linear in the gradient, so FP32 gradient
+    differences stay small in the update) and the moments, which depend on g alone."""
+    I, H, n = SMALL
+    O = n * n
+    B = 9
+    net, p = make_net(I, H, n, 16)
+    net.set_adam(0.9, 0.999, 1.0, 0)
+    X = tm.mlp_inputs(B, I, seed=31)
+    Tb = tm.bf16_bits((B, O), seed=32)
+    lr, wd = 1e-2, 0.1
+    net.train_step(dev(X), dev(Tb), lr, wd)
+    p1 = net.get(jacobi.MLP_PARAMS).astype(np.float64)
+    m1 = net.get(jacobi.MLP_MOMENT1).astype(np.float64)
+    v1 = net.get(jacobi.MLP_MOMENT2).astype(np.float64)
+    assert net.shape()[4] == 1
+    _, gr = ref.loss_and_grads(p.astype(np.float64), X.astype(np.float64), tm.bf16_value(Tb), I, H, O, True)
+    z = np.zeros_like(gr)
+    pr, mr, vr = ref.adamw(p.astype(np.float64), gr, z, z, 1, lr, wd, eps=1.0)
+    dp, dr = p1 - p.astype(np.float64), pr - p.astype(np.float64)
+    assert np.linalg.norm(dp - dr) / np.linalg.norm(dr) <= 1e-4
+    assert np.linalg.norm(m1 - mr) / np.linalg.norm(mr) <= 1e-4
+    assert np.linalg.norm(v1 - vr) / np.linalg.norm(vr) <= 2e-4
+    net.close()
+
+
+def test_training_reduces_loss_on_a_fixed_batch():
+    I, H, n = SMALL
+    O = n * n
+    B = 32
+    net, _ = make_net(I, H, n, B)
+    X = dev(tm.mlp_inputs(B, I, seed=41))
+    Tb = dev(tm.bf16_bits((B, O), seed=42, emin=119, emax=122))
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    hist = []
+    for it in range(60):
+        net.train_step(X, Tb, 2e-3, 0.0, loss)
+        hist.append(loss.item())
+    print(f"[mlp train] loss {hist[0]:.4e} -> {hist[-1]:.4e}", flush=True)
+    assert hist[-1] < 0.3 * hist[0]
+    net.close()
+
+
+def test_pack_targets_bit_exact():
+    n, count = 24, 3
+    g = tm.rng(51)
+    V = g.standard_normal((count, n, n))
+    V[0, 3, 5], V[0, 7, 5] = -5.0, 5.0      # tie on |.|: the first (negative) one decides
+    V[1, 0, 2], V[1, 9, 2] = 6.0, -6.0
+    V[2, :, 4] = 0.0                         # zero column: sign +1
+    T = jacobi.jac_mlp_pack_targets(dev(V)).cpu().numpy()
+    for c in range(count):
+        Vc = ref.canonical_signs(V[c])
+        want = ref.bf16(Vc.T.ravel())            # column-major entries
+        got = tm.bf16_value(T[c])
+        assert np.array_equal(got, want), c
+    assert np.all(tm.bf16_value(T[0])[5 * n:6 * n][[3, 7]] == [5.0, -5.0])
+
+
+def test_save_load_roundtrip_and_shape_check():
+    I, H, n = SMALL
+    O = n * n
+    net, _ = make_net(I, H, n, 8)
+    X = dev(tm.mlp_inputs(4, I, seed=61))
+    Tb = dev(tm.bf16_bits((4, O), seed=62))
+    net.train_step(X, Tb, 1e-3, 0.01)
+    net.train_step(X, Tb, 1e-3, 0.01)
+    with tempfile.TemporaryDirectory() as d:
+        f = os.path.join(d, "net.bin")
+        net.save(f)
+        other = jacobi.Mlp(I, H, n, 8, seed=99)
+        other.load_file(f)
+        for w in (jacobi.MLP_PARAMS, jacobi.MLP_MOMENT1, jacobi.MLP_MOMENT2):
+            assert np.array_equal(net.get(w), other.get(w))
+        assert other.shape()[4] == 2
+        # the next step continues identically
+        net.train_step(X, Tb, 1e-3, 0.01)
+        other.train_step(X, Tb, 1e-3, 0.01)
+        assert np.array_equal(net.get(), other.get())
+        wrong = jacobi.Mlp(I, H + 32, n, 8)
+        with pytest.raises(jacobi.JacobiError) as e:
+            wrong.load_file(f)
+        assert e.value.code == 6
+        other.close()
+        wrong.close()
+    net.close()
+
+
+def test_create_rejects_bad_shapes():
+    with pytest.raises(jacobi.JacobiError):
+        jacobi.Mlp(8, 100, 16, 4)          # hidden not a multiple of 32
+    with pytest.raises(jacobi.JacobiError):
+        jacobi.Mlp(8, 64, 6, 4)            # n^2 = 36 not a multiple of 32
+    with pytest.raises(jacobi.JacobiError):
+        jacobi.Mlp(40, 64, 16, 4)          # more than 32 inputs
+
+
+# ------------------------------------------------------------------ learned start inside syev
+def _bias_only_net(n, b3, I=8, H=64):
+    """A network whose output is b3 for every theta (all weights zero)."""
+    net = jacobi.Mlp(I, H, n, 1)
+    p = np.zeros(net.P, np.float32)
+    p[-n * n:] = b3
+    net.set(p)
+    return net
+
+
+def _check_solution(A, W, V, lam):
+    n = A.shape[0]
+    nA = np.linalg.norm(A)
+    assert np.linalg.norm(A @ V - V * W[None, :]) / nA <= 1e-13
+    assert np.linalg.norm(V.T @ V - np.eye(n)) <= 1e-13
+    assert np.abs(W - np.sort(lam)).max() <= 1e-12 * np.abs(lam).max()
+
+
+@pytest.mark.parametrize("kind", ["exact", "random", "zero"])
+def test_syev_learned_start_accept_and_fallback(kind):
+    n = 64
+    A, lam = tm.sym_matrix(n, "uniform", seed=71)
+    ref_eig = oracle.syev(A)
+    if kind == "exact":       # FP32 copy of the oracle's eigenvectors: residual ~ 1e-7, accepted
+        b3 = ref_eig.V.T.ravel().astype(np.float32)
+    elif kind == "random":    # unrelated orthogonal-ish columns: rejected
+        b3 = tm.rng(72).standard_normal(n * n).astype(np.float32)
+    else:                     # Z = 0: MGS meets a zero column, rejected
+        b3 = np.zeros(n * n, np.float32)
+    net = _bias_only_net(n, b3)
+    theta = dev(tm.mlp_inputs(1, 8, seed=73)[0])
+    W, V, st, _ = jacobi.syev_jacobi_ex(dev(A), precond="mlp", mlp=net, theta=theta)
+    W, V = W.cpu().numpy(), V.cpu().numpy()
+    print(f"[syev mlp {kind}] start_resid={st['start_resid']:.3e} fallback={st['used_fallback']} "
+          f"sweeps={st['sweeps']} fp32_sweeps={st['fp32_sweeps']}", flush=True)
+    _check_solution(A, W, V, lam)
+    if kind == "exact":
+        assert st["used_fallback"] == 0 and st["fp32_sweeps"] == 0
+        assert st["start_resid"] <= 1e-5
+        assert st["sweeps"] <= 3
+    else:
+        assert st["used_fallback"] == 1 and st["fp32_sweeps"] > 0
+        assert st["start_resid"] > 1e-2
+    net.close()
+
+
+def test_syev_learned_start_argument_errors():
+    n = 32
+    A, _ = tm.sym_matrix(n, "uniform", seed=74)
+    net = _bias_only_net(16, np.zeros(256, np.float32))
+    theta = dev(np.zeros(8, np.float32))
+    with pytest.raises(jacobi.JacobiError) as e:
+        jacobi.syev_jacobi_ex(dev(A), precond="mlp", mlp=net, theta=theta)   # network of order 16
+    assert e.value.code == -8
+    with pytest.raises(jacobi.JacobiError) as e:
+        jacobi.syev_jacobi_ex(dev(A), precond="mlp")                          # no network
+    assert e.value.code == -8
+    net.close()
