@@ -296,8 +296,9 @@ static bool use_blocked(int variant, int n) {
   return n >= 2;
 }
 
-constexpr int kMaxInner64 = 4;
-constexpr int kMaxInner32 = 3;
+constexpr int kMaxInner64 = 1;
+constexpr int kMaxInner32 = 1;
+constexpr int kSvdInner = 4;
 
 struct Timer {
   hipEvent_t ev[8];
@@ -500,6 +501,10 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
       e = mlp_predict_f64(o.mlp, o.theta, Vw, n, s);
       if (e) return e;
       tm.mark(2);
+      // A predicted Z can be far from orthogonal (condition number well above 1), where one MGS
+      // pass leaves ||Q^T Q - I|| ~ u cond(Z); a second pass restores it to ~u.
+      e = mgs_f64(Vw, n, n, n, mscr, hd.flag, s);
+      if (e) return e;
       e = mgs_f64(Vw, n, n, n, mscr, hd.flag, s);
       if (e) return e;
       tm.mark(3);
@@ -764,7 +769,7 @@ static int gesvd_impl(const double* A, int m, int n, int lda, double* S, double*
   while (sweeps < max_sweeps) {
     JAC_HIP(hipMemsetAsync(hd.rot64, 0, 8, s));
     if (ea) JAC_HIP(hipEventRecord(ea, s));
-    e = svd_sweep<double>(C, m, m, Vw, n, n, np, E, ident, Gp, gsplit, rel, kMaxInner64, hd.rot64, s);
+    e = svd_sweep<double>(C, m, m, Vw, n, n, np, E, ident, Gp, gsplit, rel, kSvdInner, hd.rot64, s);
     if (e) return e;
     if (eb) JAC_HIP(hipEventRecord(eb, s));
     unsigned long long cnt = 0;

@@ -33,7 +33,9 @@ def test_batched_uneven_sizes():
         assert np.linalg.norm(A @ v - v * w) <= 1e-13 * np.linalg.norm(A)
         assert np.linalg.norm(v.T @ v - np.eye(n)) <= 1e-13 * max(1.0, np.sqrt(n / 256))
         if n <= 64 and n > 1:
-            assert abs(s - oracle.syev(A, tol=1e-15).sweeps) <= 3
+            # one 2b x 2b subproblem: an outer sweep runs up to the tuned number of inner sweeps,
+            # so it needs no more sweeps than the cyclic oracle (plus one for the final check)
+            assert 1 <= s <= oracle.syev(A, tol=1e-15).sweeps + 1, (n, s)
     # replay of the cached graph gives bitwise the same results
     W1 = [w.clone() for w in W]
     V1 = [v.clone() for v in V]
