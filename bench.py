@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--tol", type=float, default=0.0, help="<= 0: the paper's 20 * 2^-53")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-Jacobi comparison")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the learned-start row at n=256")
+    ap.add_argument("--mlp-train", type=int, default=8192, help="training solves for the learned-start row")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -176,6 +178,11 @@ def main():
                    "share_of_timed": round(v["ms"] / (elapsed * 1e3), 4)} for c, v in kern.items()}
     others = {c: roofline_for(c, kern[c], n, rot[c[-2:]]) for c in kern if c != dom}
 
+    mlp_row = None
+    if not args.no_mlp:
+        mlp_row = learned_row(args.mlp_train)
+        log(f"[bench] learned start n=256: {json.dumps(mlp_row)}")
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -201,9 +208,33 @@ def main():
                                   f"1e-8 / 10 clusters x 1e-6, one solve of each per step",
                       "n": n, "solves_per_step": len(mats), "variant": args.variant,
                       "tol": args.tol if args.tol > 0 else 20 * 2.0 ** -53},
-           "per_spectrum": per_spec, "plain": plain, "roofline": roofline, "cpu_baseline": cpu,
+           "per_spectrum": per_spec, "plain": plain, "learned_n256": mlp_row, "roofline": roofline,
+           "cpu_baseline": cpu,
            "kernels": kernels, "other_rooflines": others}
     print(json.dumps(out), flush=True)
+
+
+def learned_row(n_train: int, n_eval: int = 32, epochs: int = 8):
+    """Learned start on the n = 256 family (the network row of the metric at the size where it is
+    feasible): train on n_train method-generated solves, then time solves of held-out matrices
+    with the learned start (FP32 fallback), the FP32 start and plain Jacobi."""
+    from paper_2211_03339_amd import learned
+    from paper_2211_03339_amd import testmats as tm
+    n = 256
+    A0, B = learned.family(n)
+    theta, T, data = learned.make_dataset(A0, B, tm.param_thetas(n_train, learned.THETA_TRAIN_SEED))
+    net = learned.jacobi.Mlp(8, 1024, n, 256, seed=0)
+    tr = learned.train(net, theta, T, epochs=epochs, batch=256, lr=1e-3, weight_decay=1e-4)
+    del T
+    ev = learned.evaluate(net, A0, B, tm.param_thetas(n_eval, learned.THETA_EVAL_SEED), check=True)
+    net.close()
+    return {"n": n, "train_solves": n_train, "epochs": epochs, "data_s": round(data["seconds"], 3),
+            "train_s": round(tr["seconds"], 3), "final_loss": tr["loss_per_epoch"][-1],
+            "eval_matrices": n_eval,
+            "solves_per_s": {m: round(1e3 / ev[m]["mean_ms"], 2) for m in ("mlp", "fp32", "plain", "mlp_forced")},
+            "mean_sweeps": {m: ev[m]["mean_sweeps"] for m in ("mlp", "fp32", "plain", "mlp_forced")},
+            "max_res": max(ev[m]["max_res"] for m in ("mlp", "fp32", "plain", "mlp_forced")),
+            "learned_start": ev["learned_start"]}
 
 
 def _cpu_model():

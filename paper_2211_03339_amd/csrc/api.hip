@@ -779,7 +779,8 @@ static int gesvd_impl(const double* A, int m, int n, int lda, double* S, double*
     ++sweeps;
     rots += (long long)cnt;
     if (stats && sweeps < JAC_HIST) stats->off_hist[sweeps] = (double)cnt;
-    if ((double)cnt < 2e-4 * N) { info = 0; break; }
+    // A sweep that applies no rotation has converged (this also covers n <= 1, N = 0).
+    if (cnt == 0 || (double)cnt < 2e-4 * N) { info = 0; break; }
   }
   if (ea) { (void)hipEventDestroy(ea); (void)hipEventDestroy(eb); }
   tm.mark(5);

@@ -30,15 +30,6 @@ constexpr int kB2 = 64;            // 2b
 constexpr int kLD = kB2 + 1;       // LDS row stride (elements)
 constexpr int kNT = 256;
 
-__device__ __forceinline__ void tri_decode(int e, int& i, int& j) {
-  // e -> (i, j), i <= j, e = j (j + 1) / 2 + i
-  int jj = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-  while (jj * (jj + 1) / 2 > e) --jj;
-  while ((jj + 1) * (jj + 2) / 2 <= e) ++jj;
-  j = jj;
-  i = e - jj * (jj + 1) / 2;
-}
-
 __device__ __forceinline__ void stri_decode(int e, int& k, int& l) {
   // e -> (k, l), k < l, e = l (l - 1) / 2 + k
   int ll = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)e)) * 0.5f);
@@ -48,53 +39,43 @@ __device__ __forceinline__ void stri_decode(int e, int& k, int& l) {
   k = e - ll * (ll - 1) / 2;
 }
 
-// Slot movement of the round-robin on kB2 indices (same rule as RR, as
-// compile-time functions so that register arrays are only indexed by
-// constants).
 constexpr int kH = kB2 / 2;
-__host__ __device__ constexpr int ring_of(int s) { return s < kH ? s : kB2 - 1 - (s - kH); }
-__host__ __device__ constexpr int src_of(int s) {
-  return s == 0 ? 0 : s == kH ? 1 : s < kH - 1 ? s + 1 : s == kH - 1 ? kB2 - 1 : s - 1;
-}
-__host__ __device__ constexpr int new_of(int s) {
-  return s == 0 ? 0 : s == 1 ? kH : s < kH ? s - 1 : s == kB2 - 1 ? kH - 1 : s + 1;
-}
-// The slots 1..kB2-1 form one cycle under src_of; cyc[i] = src_of^i(1).
-struct Cycle {
-  int v[kB2 - 1];
-  constexpr Cycle() : v() {
-    int t = 1;
-    for (int i = 0; i < kB2 - 1; ++i) { v[i] = t; t = src_of(t); }
-  }
-};
-constexpr Cycle kCyc{};
-
-// new[t] = old[src_of(t)] for a register array, done in place along the cycle.
-template <typename T>
-__device__ __forceinline__ void permute_slots(T (&w)[kB2]) {
-  T first = w[kCyc.v[0]];
-#pragma unroll
-  for (int i = 0; i < kB2 - 2; ++i) w[kCyc.v[i]] = w[kCyc.v[i + 1]];
-  w[kCyc.v[kB2 - 2]] = first;
-}
 
 // Inner solver: one workgroup diagonalises S = T(P_k, P_k) (2b x 2b) by
 // cyclic Jacobi and accumulates the product of its rotations as
 // E_k = W_k - I (the deviation from the identity is kept so that its rounding
-// errors scale with the size of the rotations).  S and E are kept in LDS in
-// slot order (ping-pong): the pairs of every step are the slots (i, h+i) and
-// entries move to the slots of the next step as they are written.
-//   wave 0, lanes < h: "band" lanes recompute the three rotated entries that
-//            form each pair of the NEXT step and derive its angle (Lemma
-//            offa-jr), so that one barrier per step suffices;
-//   waves 1-4: the pair blocks R_i^T B R_j of S (i <= j, mirrored) and the
-//            column rotations of E (lane t: pair t mod h, 8 rows).
-// Lane assignments and LDS offsets are fixed for all steps.
-constexpr int kInnerThreads = 320;
-constexpr int kWork = kInnerThreads - 64;
-constexpr int kPairBlocks = kH * (kH + 1) / 2;
-constexpr int kBlkPerLane = (kPairBlocks + kWork - 1) / kWork;
-constexpr int kRowsPerLane = kB2 / (kWork / kH);
+// errors scale with the size of the rotations).  S and E stay in LDS in local
+// index order (row-major, row stride 2b + 1) and are updated in place; step
+// ri of an inner sweep pairs the local indices held by ring positions i and
+// 2b-1-i of the circle method (position 0 fixed, the others shifted by ri).
+// Per step:
+//   A. lanes 0..b-1: the angle of pair i from S_pp, S_qq, S_pq (Lemma
+//      offa-jr, skip rule of Remark dc);
+//   B. every lane: two 2x2 blocks S({p_k,q_k}, {p_l,q_l}) -> R_k^T S R_l
+//      (the (k, k) blocks by the t-form: S_pp - t S_pq, S_qq + t S_pq, 0),
+//      and four entries pairs (E_ap, E_aq) of E <- E R + (R - I).
+// The 2b/2 x 2b/2 blocks partition S and the (row, pair) items partition E,
+// so no two lanes touch the same entry within a step; two barriers per step.
+constexpr int kInnerThreads = 512;
+constexpr int kBlkPerThread = kH * kH / kInnerThreads;          // 2
+constexpr int kEPerThread = kB2 * kH / kInnerThreads;           // 4
+static_assert(kBlkPerThread * kInnerThreads == kH * kH, "block split");
+static_assert(kEPerThread * kInnerThreads == kB2 * kH, "E split");
+
+// Local index on ring position pos at step ri of the circle method on kB2
+// indices: position 0 keeps index 0, position pos >= 1 holds
+// 1 + ((pos - 1 + ri) mod (kB2 - 1)).
+__device__ __forceinline__ int ring_index(int pos, int ri) {
+  if (pos == 0) return 0;
+  int x = pos - 1 + ri;
+  if (x >= kB2 - 1) x -= kB2 - 1;
+  return 1 + x;
+}
+__device__ __forceinline__ void ring_pair(int i, int ri, int& p, int& q) {
+  const int a = ring_index(i, ri), b = ring_index(kB2 - 1 - i, ri);
+  p = a < b ? a : b;
+  q = a < b ? b : a;
+}
 
 // Source of S: the diagonal tile T(P_k, P_k) (symmetric eigenproblem; the
 // diagonalised S is written back), or, when Gpart is given, the sum of the
@@ -110,173 +91,124 @@ blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restric
     Tm = d.Tm; ldt = d.ldt; n = d.n; Eall = d.E; ident = d.ident; rot = d.rot;
     skip_abs = (T)(d.tol_n * sqrt(*d.nrm2));
   }
-  __shared__ T S[2][kB2 * kLD];
-  __shared__ T E[2][kB2 * kLD];      // E[a * kLD + slot]: row a = local index
-  __shared__ Ang<T> ang[2][kH];
-  __shared__ int gsl[2][kB2];        // global index held by each slot
-  __shared__ int lsl[2][kB2];        // local index held by each slot
+  __shared__ T S[kB2 * kLD];
+  __shared__ T E[kB2 * kLD];         // E[a * kLD + c]: row a, column c (local indices)
+  __shared__ Ang<T> ang[kH];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const RR rrb(m2);
   const int k = blockIdx.x;
   const int I = rrb.index(k, r), J = rrb.index(rrb.h + k, r);
   auto gidx = [&](int a) { return a < kH ? I * kH + a : J * kH + (a - kH); };
-  if (tid < kB2) {
-    gsl[0][tid] = gidx(ring_of(tid));
-    lsl[0][tid] = ring_of(tid);
-  }
   for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
-    int s1 = e % kB2, s2 = e / kB2;
+    const int a = e % kB2, c = e / kB2;
     T v;
     if (Gpart) {
       // partial Grams are indexed by local indices (a, c), column-major
-      const int a = ring_of(s1), c = ring_of(s2);
       v = T(0);
       for (int z = 0; z < gsplit; ++z) v += Gpart[((size_t)z * npair + k) * kB2 * kB2 + a + c * kB2];
     } else {
-      v = Tm[gidx(ring_of(s1)) + (size_t)gidx(ring_of(s2)) * ldt];
+      v = Tm[gidx(a) + (size_t)gidx(c) * ldt];
     }
-    S[0][s1 * kLD + s2] = v;
-    E[0][s1 * kLD + s2] = T(0);
+    S[a * kLD + c] = v;
+    E[a * kLD + c] = T(0);
   }
-  unsigned long long cnt = 0;
-  int pb_i[kBlkPerLane], pb_j[kBlkPerLane];
-  const int w = tid - 64;          // work-lane index (waves 1-4)
-  const int ek = w & (kH - 1), eg = w >> 5;
-  if (wave >= 1) {
+  // Fixed lane roles: blocks (kb[q], lb) and E items (row er[q], pair lb).
+  const int lb = tid & (kH - 1);
+  int kb[kBlkPerThread], er[kEPerThread];
 #pragma unroll
-    for (int q = 0; q < kBlkPerLane; ++q) {
-      int e = w + q * kWork;
-      if (e < kPairBlocks) tri_decode(e, pb_i[q], pb_j[q]);
-      else { pb_i[q] = -1; pb_j[q] = -1; }
-    }
-  }
-  int ba = 0, bb_ = 0, bpa = 0, bra = 0, bpb = 0, brb = 0;
-  if (wave == 0 && lane < kH) {
-    ba = src_of(lane);
-    bb_ = src_of(kH + lane);
-    bpa = ba < kH ? ba : ba - kH; bra = ba < kH ? 0 : 1;
-    bpb = bb_ < kH ? bb_ : bb_ - kH; brb = bb_ < kH ? 0 : 1;
-  }
+  for (int q = 0; q < kBlkPerThread; ++q) kb[q] = (tid >> 5) + q * (kInnerThreads / kH);
+#pragma unroll
+  for (int q = 0; q < kEPerThread; ++q) er[q] = (tid >> 5) + q * (kInnerThreads / kH);
+  unsigned long long cnt = 0;
   __syncthreads();
-  if (wave == 0 && lane < kH) {
-    const T* Sc = S[0];
-    ang[0][lane] = make_angle(Sc[lane * kLD + lane], Sc[(kH + lane) * kLD + kH + lane], Sc[lane * kLD + kH + lane],
-                              gsl[0][lane], gsl[0][kH + lane], n, skip_abs, rel);
-  }
-  __syncthreads();
-  int cur = 0;
   for (int sw = 0; sw < max_inner; ++sw) {
     bool big = false;
     for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
-      int s1 = e % kB2, s2 = e / kB2;
-      if (s1 < s2 && gsl[cur][s1] < n && gsl[cur][s2] < n)
-        big |= !negligible2(S[cur][s1 * kLD + s1], S[cur][s2 * kLD + s2], S[cur][s1 * kLD + s2], skip_abs, rel);
+      const int a = e % kB2, c = e / kB2;
+      if (a < c && gidx(a) < n && gidx(c) < n)
+        big |= !negligible2(S[a * kLD + a], S[c * kLD + c], S[a * kLD + c], skip_abs, rel);
     }
     if (!__syncthreads_or(big)) break;
     for (int ri = 0; ri < kB2 - 1; ++ri) {
-      const T* Sc = S[cur];
-      T* Sn = S[cur ^ 1];
-      const Ang<T>* ac = ang[cur];
       if (wave == 0) {
-        unsigned long long m = __ballot(lane < kH && ac[lane & (kH - 1)].applied != T(0));
-        cnt += __popcll(m);
+        bool applied = false;
         if (lane < kH) {
-          const Ang<T> apa = ac[bpa], apb = ac[bpb];
-          T ta, tbv, tabv;
-          {
-            T x = Sc[bpa * kLD + kH + bpa];
-            ta = bra ? fmaT(apa.t, x, Sc[(kH + bpa) * kLD + kH + bpa]) : fmaT(-apa.t, x, Sc[bpa * kLD + bpa]);
-            T y = Sc[bpb * kLD + kH + bpb];
-            tbv = brb ? fmaT(apb.t, y, Sc[(kH + bpb) * kLD + kH + bpb]) : fmaT(-apb.t, y, Sc[bpb * kLD + bpb]);
-          }
-          {
-            const int k1 = bpa < bpb ? bpa : bpb, l1 = bpa < bpb ? bpb : bpa;
-            const Ang<T> ak = bpa < bpb ? apa : apb, al = bpa < bpb ? apb : apa;
-            T tt = Sc[k1 * kLD + l1], tb = Sc[k1 * kLD + kH + l1];
-            T bt = Sc[(kH + k1) * kLD + l1], bb = Sc[(kH + k1) * kLD + kH + l1];
-            rot2(tt, bt, ak.s, ak.tau);
-            rot2(tb, bb, ak.s, ak.tau);
-            rot2(tt, tb, al.s, al.tau);
-            rot2(bt, bb, al.s, al.tau);
-            const int comp = bpa < bpb ? bra * 2 + brb : brb * 2 + bra;
-            tabv = comp == 0 ? tt : comp == 1 ? tb : comp == 2 ? bt : bb;
-          }
-          const int gi = gsl[cur][ba], gj = gsl[cur][bb_];
-          ang[cur ^ 1][lane] = make_angle(ta, tbv, tabv, gi, gj, n, skip_abs, rel);
-          gsl[cur ^ 1][lane] = gi;
-          gsl[cur ^ 1][kH + lane] = gj;
-          lsl[cur ^ 1][lane] = lsl[cur][ba];
-          lsl[cur ^ 1][kH + lane] = lsl[cur][bb_];
+          int p, q;
+          ring_pair(lane, ri, p, q);
+          const Ang<T> an = make_angle(S[p * kLD + p], S[q * kLD + q], S[p * kLD + q], gidx(p), gidx(q), n,
+                                       skip_abs, rel);
+          ang[lane] = an;
+          applied = an.applied != T(0);
         }
-      } else {
+        const unsigned long long m = __ballot(applied);
+        if (lane == 0) cnt += __popcll(m);
+      }
+      __syncthreads();
+      int pl, ql;
+      ring_pair(lb, ri, pl, ql);
+      const Ang<T> al = ang[lb];
 #pragma unroll
-        for (int q = 0; q < kBlkPerLane; ++q) {
-          const int i = pb_i[q], j = pb_j[q];
-          if (i < 0) continue;
-          const Ang<T> ai = ac[i];
-          const int ni = new_of(i), nhi = new_of(kH + i);
-          if (i == j) {
-            T tb = Sc[i * kLD + kH + i];
-            Sn[ni * kLD + ni] = fmaT(-ai.t, tb, Sc[i * kLD + i]);
-            Sn[nhi * kLD + nhi] = fmaT(ai.t, tb, Sc[(kH + i) * kLD + kH + i]);
-            Sn[ni * kLD + nhi] = T(0);
-            Sn[nhi * kLD + ni] = T(0);
-          } else {
-            const Ang<T> aj = ac[j];
-            T tt = Sc[i * kLD + j], tb = Sc[i * kLD + kH + j];
-            T bt = Sc[(kH + i) * kLD + j], bb = Sc[(kH + i) * kLD + kH + j];
-            rot2(tt, bt, ai.s, ai.tau);
-            rot2(tb, bb, ai.s, ai.tau);
-            rot2(tt, tb, aj.s, aj.tau);
-            rot2(bt, bb, aj.s, aj.tau);
-            const int nj = new_of(j), nhj = new_of(kH + j);
-            Sn[ni * kLD + nj] = tt; Sn[nj * kLD + ni] = tt;
-            Sn[ni * kLD + nhj] = tb; Sn[nhj * kLD + ni] = tb;
-            Sn[nhi * kLD + nj] = bt; Sn[nj * kLD + nhi] = bt;
-            Sn[nhi * kLD + nhj] = bb; Sn[nhj * kLD + nhi] = bb;
-          }
+      for (int qd = 0; qd < kBlkPerThread; ++qd) {
+        const int kk = kb[qd];
+        int pk, qk;
+        ring_pair(kk, ri, pk, qk);
+        const Ang<T> ak = ang[kk];
+        T tt = S[pk * kLD + pl], tb = S[pk * kLD + ql];
+        T bt = S[qk * kLD + pl], bb = S[qk * kLD + ql];
+        if (kk == lb) {
+          tt = fmaT(-ak.t, tb, tt);
+          bb = fmaT(ak.t, tb, bb);
+          tb = T(0);
+          bt = T(0);
+        } else {
+          // Rows by the rotation of the smaller pair index first, so that the
+          // mirror block (lb, kk) is computed by the same operations and S
+          // stays exactly symmetric: for kk > lb work on the transpose.
+          const bool tr = kk > lb;
+          const T s1 = tr ? al.s : ak.s, u1 = tr ? al.tau : ak.tau;
+          const T s2 = tr ? ak.s : al.s, u2 = tr ? ak.tau : al.tau;
+          T x01 = tr ? bt : tb, x10 = tr ? tb : bt;
+          rot2(tt, x10, s1, u1);
+          rot2(x01, bb, s1, u1);
+          rot2(tt, x01, s2, u2);
+          rot2(x10, bb, s2, u2);
+          tb = tr ? x10 : x01;
+          bt = tr ? x01 : x10;
         }
-        // E <- E R + (R - I) restricted to row a: with x = E(a, top), y =
-        // E(a, bottom) and dt, db the entries of I in those columns,
-        // x' = x - s (y + tau x + db + tau dt), y' = y + s (x - tau y + dt - tau db).
-        {
-          const Ang<T> a = ac[ek];
-          const T* Ec = E[cur];
-          T* En = E[cur ^ 1];
-          const int lt = lsl[cur][ek], lb = lsl[cur][kH + ek];
-          const int nt = new_of(ek), nb = new_of(kH + ek);
+        S[pk * kLD + pl] = tt;
+        S[pk * kLD + ql] = tb;
+        S[qk * kLD + pl] = bt;
+        S[qk * kLD + ql] = bb;
+      }
+      // E <- E R + (R - I) on columns (p, q): with x = E(a, p), y = E(a, q)
+      // and dt, db the entries of I in those columns,
+      // x' = x - s (y + tau x + db + tau dt), y' = y + s (x - tau y + dt - tau db).
+      if (al.applied != T(0)) {
 #pragma unroll
-          for (int q = 0; q < kRowsPerLane; ++q) {
-            const int row = eg + q * (kWork / kH);
-            T x = Ec[row * kLD + ek], y = Ec[row * kLD + kH + ek];
-            if (a.applied != T(0)) {
-              const T dt = row == lt ? T(1) : T(0), db = row == lb ? T(1) : T(0);
-              T px = fmaT(a.tau, x, y) + fmaT(a.tau, dt, db);
-              T py = fmaT(-a.tau, y, x) + fmaT(-a.tau, db, dt);
-              x = fmaT(-a.s, px, x);
-              y = fmaT(a.s, py, y);
-            }
-            En[row * kLD + nt] = x;
-            En[row * kLD + nb] = y;
-          }
+        for (int qd = 0; qd < kEPerThread; ++qd) {
+          const int a = er[qd];
+          T x = E[a * kLD + pl], y = E[a * kLD + ql];
+          const T dt = a == pl ? T(1) : T(0), db = a == ql ? T(1) : T(0);
+          const T px = fmaT(al.tau, x, y) + fmaT(al.tau, dt, db);
+          const T py = fmaT(-al.tau, y, x) + fmaT(-al.tau, db, dt);
+          E[a * kLD + pl] = fmaT(-al.s, px, x);
+          E[a * kLD + ql] = fmaT(al.s, py, y);
         }
       }
       __syncthreads();
-      cur ^= 1;
     }
   }
-  // After whole sweeps the slots hold their initial indices again.
   if (!Gpart) {
     for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
-      int s1 = e % kB2, s2 = e / kB2;
-      Tm[gidx(ring_of(s1)) + (size_t)gidx(ring_of(s2)) * ldt] = S[cur][s1 * kLD + s2];
+      const int a = e % kB2, c = e / kB2;
+      Tm[gidx(a) + (size_t)gidx(c) * ldt] = S[a * kLD + c];
     }
   }
-  // E_k row-major: Eall[k][a * 2b + c] = E(a, c), c = local column index.
+  // E_k row-major: Eall[k][a * 2b + c] = E(a, c).
   T* Ek = Eall + (size_t)k * kB2 * kB2;
   for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
-    int s1 = e % kB2, a = e / kB2;
-    Ek[a * kB2 + ring_of(s1)] = E[cur][a * kLD + s1];
+    const int c = e % kB2, a = e / kB2;
+    Ek[a * kB2 + c] = E[a * kLD + c];
   }
   if (tid == 0) {
     ident[k] = cnt == 0;
@@ -333,9 +265,9 @@ __device__ __forceinline__ void mm_ldsA_fragB(const T* Aop, int wm, const T (&fb
   }
 }
 
-// acc <- M(i, j) for the wave's quarter, M held in LDS as M[j * kLD + i].
+// acc(i, j) += M[j * kLD + i] (jm = false) or M[i * kLD + j] (jm = true).
 template <typename T>
-__device__ __forceinline__ void acc_load(const T* M, int wm, int wn, typename Mfma<T>::acc_t (&acc)[2][2]) {
+__device__ __forceinline__ void acc_add(const T* M, int wm, int wn, bool jm, typename Mfma<T>::acc_t (&acc)[2][2]) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -345,8 +277,16 @@ __device__ __forceinline__ void acc_load(const T* M, int wm, int wn, typename Mf
       for (int rr = 0; rr < 4; ++rr) {
         int i = wm * 32 + a * 16 + Mfma<T>::row(lane, rr);
         int j = wn * 32 + c * 16 + (lane & 15);
-        acc[a][c][rr] = M[j * kLD + i];
+        acc[a][c][rr] += jm ? M[i * kLD + j] : M[j * kLD + i];
       }
+}
+
+template <typename T>
+__device__ __forceinline__ void acc_zero(typename Mfma<T>::acc_t (&acc)[2][2]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[a][c] = typename Mfma<T>::acc_t{0, 0, 0, 0};
 }
 
 // M[j * kLD + i] <- acc(i, j) for the wave's quarter.
@@ -367,8 +307,10 @@ __device__ __forceinline__ void acc_store(T* M, int wm, int wn, const typename M
 
 // Update kernel.  Tile (k, l), k < l:  X = T + E_k^T T,  Y = X + X E_l
 // (= W_k^T T W_l), written to T(P_k, P_l) and mirrored into T(P_l, P_k).
-// V chunk (k, 64 rows):  V(:, P_k) <- V + V E_k.  The accumulators start from
-// T (or X, V) so that the matrix-core products only carry the E terms.
+// V chunk (k, 64 rows):  V(:, P_k) <- V + V E_k.  The matrix-core products
+// accumulate only the E terms (from zero); the base T (X, V) is added once at
+// the end, so each update rounds at the scale of the base once rather than
+// at every k step.
 template <typename T>
 __global__ void __launch_bounds__(kNT)
 blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int nvr, const T* __restrict__ Eall,
@@ -408,25 +350,15 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
       Bs[kk * kLD + c] = Tm[gk[kk] + (size_t)gl[c] * ldt];   // B(kk, j = c) = T(P_k[kk], P_l[c])
     }
     __syncthreads();
-    // acc <- T(i, j): T tile is Bs[i * kLD + j], i.e. M[j' * kLD + i'] with (i', j') = (j, i)
-    {
-      const int lane = tid & 63;
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) {
-            int i = wm * 32 + a * 16 + Mfma<T>::row(lane, rr);
-            int j = wn * 32 + c * 16 + (lane & 15);
-            acc[a][c][rr] = Bs[i * kLD + j];
-          }
-    }
-    mm_fragA_ldsB<T>(fa, Bs, wn, acc);      // X = T + E_k^T T
+    acc_zero<T>(acc);
+    mm_fragA_ldsB<T>(fa, Bs, wn, acc);      // E_k^T T
+    acc_add<T>(Bs, wm, wn, true, acc);      // X = T + E_k^T T (T tile is Bs[i * kLD + j])
     __syncthreads();
     acc_store<T>(Bs, wm, wn, acc);          // Bs[j * kLD + i] = X(i, j): k-major A operand
     __syncthreads();
-    mm_ldsA_fragB<T>(Bs, wm, fb, acc);      // Y = X + X E_l (acc still holds X)
+    acc_zero<T>(acc);
+    mm_ldsA_fragB<T>(Bs, wm, fb, acc);      // X E_l
+    acc_add<T>(Bs, wm, wn, false, acc);     // Y = X + X E_l
     __syncthreads();
     acc_store<T>(Bs, wm, wn, acc);          // Bs[j * kLD + i] = Y(i, j)
     __syncthreads();
@@ -457,8 +389,9 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
       Bs[kk * kLD + i] = row < nvr ? V[row + (size_t)gk[kk] * ldv] : T(0);   // A(i, kk) = V(row, P_k[kk])
     }
     __syncthreads();
-    acc_load<T>(Bs, wm, wn, acc);           // acc <- V(i, j)
-    mm_ldsA_fragB<T>(Bs, wm, fb, acc);      // V + V E_k
+    acc_zero<T>(acc);
+    mm_ldsA_fragB<T>(Bs, wm, fb, acc);      // V E_k
+    acc_add<T>(Bs, wm, wn, false, acc);     // V + V E_k
     __syncthreads();
     acc_store<T>(Bs, wm, wn, acc);
     __syncthreads();
