@@ -7,11 +7,12 @@
 // blocks), giving m disjoint index sets P_k = I_k u J_k of size 2b.  Per step:
 //
 //  1. inner kernel, one workgroup per pair: S = T(P_k, P_k) is loaded into
-//     LDS and diagonalised by cyclic Jacobi (round-robin over its 2b indices,
-//     the rotations of Lemma offa-jr with the skip rule of Remark dc), while
+//     LDS and swept by cyclic Jacobi (the rotations of Lemma offa-jr with the
+//     skip rule of Remark dc; all pairs of the 2b indices at the first block
+//     step of a sweep, only the pairs between I_k and J_k afterwards), while
 //     the rotations are accumulated into W_k (2b x 2b, W_k = I at start).
-//     The diagonalised S is written back to T(P_k, P_k); W_k and a flag
-//     "W_k is exactly I" go to global memory.
+//     S is written back to T(P_k, P_k); W_k and a flag "W_k is exactly I" go
+//     to global memory.
 //  2. update kernel: every tile T(P_k, P_l), k < l, becomes W_k^T T(P_k, P_l)
 //     W_l (two 2b^3 GEMMs on v_mfma_*_16x16x4) and is mirrored into
 //     T(P_l, P_k); every 64-row chunk of V(:, P_k) becomes V(:, P_k) W_k.
@@ -44,23 +45,33 @@ constexpr int kH = kB2 / 2;
 // Inner solver: one workgroup diagonalises S = T(P_k, P_k) (2b x 2b) by
 // cyclic Jacobi and accumulates the product of its rotations as
 // E_k = W_k - I (the deviation from the identity is kept so that its rounding
-// errors scale with the size of the rotations).  S and E stay in LDS in local
-// index order (row-major, row stride 2b + 1) and are updated in place; step
-// ri of an inner sweep pairs the local indices held by ring positions i and
-// 2b-1-i of the circle method (position 0 fixed, the others shifted by ri).
-// Per step:
-//   A. lanes 0..b-1: the angle of pair i from S_pp, S_qq, S_pq (Lemma
-//      offa-jr, skip rule of Remark dc);
-//   B. every lane: two 2x2 blocks S({p_k,q_k}, {p_l,q_l}) -> R_k^T S R_l
-//      (the (k, k) blocks by the t-form: S_pp - t S_pq, S_qq + t S_pq, 0),
-//      and four entries pairs (E_ap, E_aq) of E <- E R + (R - I).
-// The 2b/2 x 2b/2 blocks partition S and the (row, pair) items partition E,
-// so no two lanes touch the same entry within a step; two barriers per step.
-constexpr int kInnerThreads = 512;
-constexpr int kBlkPerThread = kH * kH / kInnerThreads;          // 2
-constexpr int kEPerThread = kB2 * kH / kInnerThreads;           // 4
-static_assert(kBlkPerThread * kInnerThreads == kH * kH, "block split");
-static_assert(kEPerThread * kInnerThreads == kB2 * kH, "E split");
+// errors scale with the size of the rotations).  S (ping-pong) and E live in
+// LDS in local index order (row-major, row stride 2b + 1).  Inner schedules:
+//   block step 0 of a sweep (every block appears once): the full round-robin
+//       on the 2b local indices; step ri pairs the indices held by ring
+//       positions i and 2b-1-i of the circle method (position 0 fixed, the
+//       others shifted by ri), 2b-1 steps;
+//   later block steps: only the b x b pairs between the two blocks (the pairs
+//       inside a block were rotated at step 0 of the sweep); step ri pairs
+//       local index i < b with b + ((i + ri) mod b), b steps.
+// So every index pair of the matrix is rotated exactly once per block sweep
+// (a cyclic order) and a sweep takes about n sequential inner steps rather
+// than 2n.  Per step, with one barrier:
+//   wave 0, lanes 0..b-1: the angles of the NEXT step.  Each next pair (x, y)
+//       takes x and y from two pairs of the current step, so its three entries
+//       after this step follow from the current S and angles: the diagonal
+//       ones by the t-form, the off-diagonal one by rotating the 2x2 block
+//       with the same operations as the lane that owns that block.
+//   waves 1..15: the 2x2 blocks S({p_k,q_k}, {p_l,q_l}) -> R_k^T S R_l (read
+//       from the current S, written to the other copy; the (k, k) blocks by
+//       the t-form S_pp - t S_pq, S_qq + t S_pq, 0) and the entry pairs
+//       (E_ap, E_aq) of E <- E R + (R - I), in place.
+// The blocks partition S and the (row, pair) items partition E, so no two
+// lanes write the same entry within a step.
+constexpr int kInnerThreads = 1024;
+constexpr int kWorkLanes = kInnerThreads - 64;
+constexpr int kBlocks = kH * kH;                 // 2x2 blocks of S
+constexpr int kItems = kBlocks + kB2 * kH;       // blocks, then (row, pair) items of E
 
 // Local index on ring position pos at step ri of the circle method on kB2
 // indices: position 0 keeps index 0, position pos >= 1 holds
@@ -75,6 +86,32 @@ __device__ __forceinline__ void ring_pair(int i, int ri, int& p, int& q) {
   const int a = ring_index(i, ri), b = ring_index(kB2 - 1 - i, ri);
   p = a < b ? a : b;
   q = a < b ? b : a;
+}
+// Pair (0 .. kH-1) that holds local index x at step ri.
+__device__ __forceinline__ int ring_pair_of(int x, int ri) {
+  if (x == 0) return 0;
+  int pos = x - 1 - ri;
+  if (pos < 0) pos += kB2 - 1;
+  pos += 1;
+  return pos < kH ? pos : kB2 - 1 - pos;
+}
+
+// R_k^T B R_l of the 2x2 block B = [tt tb; bt bb] = S({p_k,q_k}, {p_l,q_l}),
+// k != l.  Rows by the rotation of the smaller pair index first, so that the
+// mirror block (l, k) is computed by the same operations and S stays exactly
+// symmetric: for k > l the transpose is rotated.
+template <typename T>
+__device__ __forceinline__ void rotate_block(T& tt, T& tb, T& bt, T& bb, const Ang<T>& ak, const Ang<T>& al,
+                                             bool tr) {
+  const T s1 = tr ? al.s : ak.s, u1 = tr ? al.tau : ak.tau;
+  const T s2 = tr ? ak.s : al.s, u2 = tr ? ak.tau : al.tau;
+  T x01 = tr ? bt : tb, x10 = tr ? tb : bt;
+  rot2(tt, x10, s1, u1);
+  rot2(x01, bb, s1, u1);
+  rot2(tt, x01, s2, u2);
+  rot2(x10, bb, s2, u2);
+  tb = tr ? x10 : x01;
+  bt = tr ? x01 : x10;
 }
 
 // Source of S: the diagonal tile T(P_k, P_k) (symmetric eigenproblem; the
@@ -91,14 +128,23 @@ blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restric
     Tm = d.Tm; ldt = d.ldt; n = d.n; Eall = d.E; ident = d.ident; rot = d.rot;
     skip_abs = (T)(d.tol_n * sqrt(*d.nrm2));
   }
-  __shared__ T S[kB2 * kLD];
+  __shared__ T S[2][kB2 * kLD];
   __shared__ T E[kB2 * kLD];         // E[a * kLD + c]: row a, column c (local indices)
-  __shared__ Ang<T> ang[kH];
+  __shared__ Ang<T> ang[2][kH];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const RR rrb(m2);
   const int k = blockIdx.x;
   const int I = rrb.index(k, r), J = rrb.index(rrb.h + k, r);
   auto gidx = [&](int a) { return a < kH ? I * kH + a : J * kH + (a - kH); };
+  const bool bip = r != 0;                 // bipartite schedule (block steps after the first)
+  const int nsteps = bip ? kH : kB2 - 1;
+  auto pair_at = [&](int i, int ri, int& p, int& q) {
+    if (bip) { p = i; q = kH + ((i + ri) & (kH - 1)); }
+    else ring_pair(i, ri, p, q);
+  };
+  auto pair_of = [&](int x, int ri) {
+    return bip ? (x < kH ? x : ((x - kH - ri) & (kH - 1))) : ring_pair_of(x, ri);
+  };
   for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
     const int a = e % kB2, c = e / kB2;
     T v;
@@ -109,99 +155,102 @@ blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restric
     } else {
       v = Tm[gidx(a) + (size_t)gidx(c) * ldt];
     }
-    S[a * kLD + c] = v;
+    S[0][a * kLD + c] = v;
     E[a * kLD + c] = T(0);
   }
-  // Fixed lane roles: blocks (kb[q], lb) and E items (row er[q], pair lb).
-  const int lb = tid & (kH - 1);
-  int kb[kBlkPerThread], er[kEPerThread];
-#pragma unroll
-  for (int q = 0; q < kBlkPerThread; ++q) kb[q] = (tid >> 5) + q * (kInnerThreads / kH);
-#pragma unroll
-  for (int q = 0; q < kEPerThread; ++q) er[q] = (tid >> 5) + q * (kInnerThreads / kH);
-  unsigned long long cnt = 0;
   __syncthreads();
+  if (tid < kH) {   // angles of the first step
+    int p, q;
+    pair_at(tid, 0, p, q);
+    ang[0][tid] = make_angle(S[0][p * kLD + p], S[0][q * kLD + q], S[0][p * kLD + q], gidx(p), gidx(q), n, skip_abs,
+                             rel);
+  }
+  __syncthreads();
+  unsigned long long cnt = 0;
+  int cur = 0;
   for (int sw = 0; sw < max_inner; ++sw) {
     bool big = false;
     for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
       const int a = e % kB2, c = e / kB2;
-      if (a < c && gidx(a) < n && gidx(c) < n)
-        big |= !negligible2(S[a * kLD + a], S[c * kLD + c], S[a * kLD + c], skip_abs, rel);
+      if (a < c && (!bip || (a < kH && c >= kH)) && gidx(a) < n && gidx(c) < n)
+        big |= !negligible2(S[cur][a * kLD + a], S[cur][c * kLD + c], S[cur][a * kLD + c], skip_abs, rel);
     }
     if (!__syncthreads_or(big)) break;
-    for (int ri = 0; ri < kB2 - 1; ++ri) {
+    for (int ri = 0; ri < nsteps; ++ri) {
+      const T* Sc = S[cur];
+      T* Sn = S[cur ^ 1];
+      const Ang<T>* ac = ang[cur];
       if (wave == 0) {
-        bool applied = false;
+        const unsigned long long m = __ballot(lane < kH && ac[lane & (kH - 1)].applied != T(0));
+        cnt += __popcll(m);
         if (lane < kH) {
-          int p, q;
-          ring_pair(lane, ri, p, q);
-          const Ang<T> an = make_angle(S[p * kLD + p], S[q * kLD + q], S[p * kLD + q], gidx(p), gidx(q), n,
-                                       skip_abs, rel);
-          ang[lane] = an;
-          applied = an.applied != T(0);
+          const int r1 = ri == nsteps - 1 ? 0 : ri + 1;
+          int x, y;
+          pair_at(lane, r1, x, y);
+          const int kx = pair_of(x, ri), ky = pair_of(y, ri);
+          int pkx, qkx, pky, qky;
+          pair_at(kx, ri, pkx, qkx);
+          pair_at(ky, ri, pky, qky);
+          const Ang<T> ax = ac[kx], ay = ac[ky];
+          const T dx = Sc[pkx * kLD + qkx], dy = Sc[pky * kLD + qky];
+          const T sxx = x == pkx ? fmaT(-ax.t, dx, Sc[pkx * kLD + pkx]) : fmaT(ax.t, dx, Sc[qkx * kLD + qkx]);
+          const T syy = y == pky ? fmaT(-ay.t, dy, Sc[pky * kLD + pky]) : fmaT(ay.t, dy, Sc[qky * kLD + qky]);
+          T tt = Sc[pkx * kLD + pky], tb = Sc[pkx * kLD + qky];
+          T bt = Sc[qkx * kLD + pky], bb = Sc[qkx * kLD + qky];
+          rotate_block(tt, tb, bt, bb, ax, ay, kx > ky);
+          const T sxy = x == pkx ? (y == pky ? tt : tb) : (y == pky ? bt : bb);
+          ang[cur ^ 1][lane] = make_angle(sxx, syy, sxy, gidx(x), gidx(y), n, skip_abs, rel);
         }
-        const unsigned long long m = __ballot(applied);
-        if (lane == 0) cnt += __popcll(m);
-      }
-      __syncthreads();
-      int pl, ql;
-      ring_pair(lb, ri, pl, ql);
-      const Ang<T> al = ang[lb];
-#pragma unroll
-      for (int qd = 0; qd < kBlkPerThread; ++qd) {
-        const int kk = kb[qd];
-        int pk, qk;
-        ring_pair(kk, ri, pk, qk);
-        const Ang<T> ak = ang[kk];
-        T tt = S[pk * kLD + pl], tb = S[pk * kLD + ql];
-        T bt = S[qk * kLD + pl], bb = S[qk * kLD + ql];
-        if (kk == lb) {
-          tt = fmaT(-ak.t, tb, tt);
-          bb = fmaT(ak.t, tb, bb);
-          tb = T(0);
-          bt = T(0);
-        } else {
-          // Rows by the rotation of the smaller pair index first, so that the
-          // mirror block (lb, kk) is computed by the same operations and S
-          // stays exactly symmetric: for kk > lb work on the transpose.
-          const bool tr = kk > lb;
-          const T s1 = tr ? al.s : ak.s, u1 = tr ? al.tau : ak.tau;
-          const T s2 = tr ? ak.s : al.s, u2 = tr ? ak.tau : al.tau;
-          T x01 = tr ? bt : tb, x10 = tr ? tb : bt;
-          rot2(tt, x10, s1, u1);
-          rot2(x01, bb, s1, u1);
-          rot2(tt, x01, s2, u2);
-          rot2(x10, bb, s2, u2);
-          tb = tr ? x10 : x01;
-          bt = tr ? x01 : x10;
-        }
-        S[pk * kLD + pl] = tt;
-        S[pk * kLD + ql] = tb;
-        S[qk * kLD + pl] = bt;
-        S[qk * kLD + ql] = bb;
-      }
-      // E <- E R + (R - I) on columns (p, q): with x = E(a, p), y = E(a, q)
-      // and dt, db the entries of I in those columns,
-      // x' = x - s (y + tau x + db + tau dt), y' = y + s (x - tau y + dt - tau db).
-      if (al.applied != T(0)) {
-#pragma unroll
-        for (int qd = 0; qd < kEPerThread; ++qd) {
-          const int a = er[qd];
-          T x = E[a * kLD + pl], y = E[a * kLD + ql];
-          const T dt = a == pl ? T(1) : T(0), db = a == ql ? T(1) : T(0);
-          const T px = fmaT(al.tau, x, y) + fmaT(al.tau, dt, db);
-          const T py = fmaT(-al.tau, y, x) + fmaT(-al.tau, db, dt);
-          E[a * kLD + pl] = fmaT(-al.s, px, x);
-          E[a * kLD + ql] = fmaT(al.s, py, y);
+      } else {
+        for (int e = tid - 64; e < kItems; e += kWorkLanes) {
+          if (e < kBlocks) {
+            const int kk = e >> 5, lb = e & (kH - 1);
+            int pk, qk, pl, ql;
+            pair_at(kk, ri, pk, qk);
+            pair_at(lb, ri, pl, ql);
+            const Ang<T> ak = ac[kk];
+            T tt = Sc[pk * kLD + pl], tb = Sc[pk * kLD + ql];
+            T bt = Sc[qk * kLD + pl], bb = Sc[qk * kLD + ql];
+            if (kk == lb) {
+              tt = fmaT(-ak.t, tb, tt);
+              bb = fmaT(ak.t, tb, bb);
+              tb = T(0);
+              bt = T(0);
+            } else {
+              rotate_block(tt, tb, bt, bb, ak, ac[lb], kk > lb);
+            }
+            Sn[pk * kLD + pl] = tt;
+            Sn[pk * kLD + ql] = tb;
+            Sn[qk * kLD + pl] = bt;
+            Sn[qk * kLD + ql] = bb;
+          } else {
+            // E <- E R + (R - I) on columns (p, q): with x = E(a, p), y = E(a, q)
+            // and dt, db the entries of I in those columns,
+            // x' = x - s (y + tau x + db + tau dt), y' = y + s (x - tau y + dt - tau db).
+            const int e2 = e - kBlocks;
+            const int a = e2 >> 5, pr = e2 & (kH - 1);
+            const Ang<T> al = ac[pr];
+            if (al.applied != T(0)) {
+              int pl, ql;
+              pair_at(pr, ri, pl, ql);
+              const T x = E[a * kLD + pl], y = E[a * kLD + ql];
+              const T dt = a == pl ? T(1) : T(0), db = a == ql ? T(1) : T(0);
+              const T px = fmaT(al.tau, x, y) + fmaT(al.tau, dt, db);
+              const T py = fmaT(-al.tau, y, x) + fmaT(-al.tau, db, dt);
+              E[a * kLD + pl] = fmaT(-al.s, px, x);
+              E[a * kLD + ql] = fmaT(al.s, py, y);
+            }
+          }
         }
       }
       __syncthreads();
+      cur ^= 1;
     }
   }
   if (!Gpart) {
     for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
       const int a = e % kB2, c = e / kB2;
-      Tm[gidx(a) + (size_t)gidx(c) * ldt] = S[a * kLD + c];
+      Tm[gidx(a) + (size_t)gidx(c) * ldt] = S[cur][a * kLD + c];
     }
   }
   // E_k row-major: Eall[k][a * 2b + c] = E(a, c).
