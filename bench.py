@@ -39,6 +39,30 @@ def step_bytes(n: int, dtype_bytes: int) -> float:
     return dtype_bytes * (n * (n + 1) + 2 * n * n)
 
 
+KERNEL_OF = {"inner64": "blk_inner_kernel<double", "update64": "blk_update_kernel<double",
+             "inner32": "blk_inner_kernel<float", "update32": "blk_update_kernel<float",
+             "elem64": "elem_step_kernel<double", "elem32": "elem_step_kernel<float"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_n2048.json")
+
+
+def measured_traffic(cls: str):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (copy-kernel scaled), or None when there is none or the kernel source changed since."""
+    import hashlib
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+        src = os.path.join(ROOT, t["source"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != t["source_sha256"]:
+            return None
+        sel = [v for k, v in t["kernels"].items() if KERNEL_OF.get(cls, "@") in k]
+        calls = sum(v["dispatches"] for v in sel)
+        if not calls:
+            return None
+        return sum(v["bytes"] * v["dispatches"] for v in sel) / calls
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def roofline_for(cls: str, k: dict, n: int, rotations: int) -> dict:
     """Roofline figure of one kernel class from its HIP-event launch times.
     update*: algorithmic flops of the block rotations actually applied: each (2b)x(2b) tile
@@ -54,7 +78,7 @@ def roofline_for(cls: str, k: dict, n: int, rotations: int) -> dict:
         peak = PEAK["fp64_mfma" if cls.endswith("64") else "fp32_mfma"]
         ach = per_launch / avg_s / 1e12
         return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(ach / peak, 4), "traffic": None, "kernel": f"blk_update_kernel<{cls[-2:]}>",
+                "frac": round(ach / peak, 4), "traffic": measured_traffic(cls), "kernel": f"blk_update_kernel<{cls[-2:]}>",
                 "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_flops_per_launch": per_launch,
                 "launches_timed": k["launches"]}
     if cls.startswith("elem"):
@@ -62,7 +86,7 @@ def roofline_for(cls: str, k: dict, n: int, rotations: int) -> dict:
         bpl = step_bytes(n, db)
         ach = bpl / avg_s / 1e9
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": f"elem_step_kernel<{cls[-2:]}>",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(cls), "kernel": f"elem_step_kernel<{cls[-2:]}>",
                 "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_bytes_per_launch": bpl,
                 "launches_timed": k["launches"]}
     flops = rotations * 12 * TILE
@@ -70,7 +94,7 @@ def roofline_for(cls: str, k: dict, n: int, rotations: int) -> dict:
     peak = PEAK["fp64_valu" if cls.endswith("64") else "fp32_valu"]
     ach = per_launch / avg_s / 1e12
     return {"bound": "alu", "achieved": round(ach, 4), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(ach / peak, 6), "traffic": None, "kernel": f"blk_inner_kernel<{cls[-2:]}>",
+            "frac": round(ach / peak, 6), "traffic": measured_traffic(cls), "kernel": f"blk_inner_kernel<{cls[-2:]}>",
             "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_flops_per_launch": per_launch,
             "launches_timed": k["launches"]}
 
@@ -87,7 +111,19 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-Jacobi comparison")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-start row at n=256")
     ap.add_argument("--mlp-train", type=int, default=8192, help="training solves for the learned-start row")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        nb = args.copy_probe << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nb, "copies": 5}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)

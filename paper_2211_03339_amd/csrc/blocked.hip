@@ -62,16 +62,18 @@ constexpr int kH = kB2 / 2;
 //       after this step follow from the current S and angles: the diagonal
 //       ones by the t-form, the off-diagonal one by rotating the 2x2 block
 //       with the same operations as the lane that owns that block.
-//   waves 1..15: the 2x2 blocks S({p_k,q_k}, {p_l,q_l}) -> R_k^T S R_l (read
-//       from the current S, written to the other copy; the (k, k) blocks by
-//       the t-form S_pp - t S_pq, S_qq + t S_pq, 0) and the entry pairs
-//       (E_ap, E_aq) of E <- E R + (R - I), in place.
-// The blocks partition S and the (row, pair) items partition E, so no two
-// lanes write the same entry within a step.
+//   waves 1..15: the 2x2 blocks S({p_k,q_k}, {p_l,q_l}) -> R_k^T S R_l, k <= l
+//       (read from the current S, written with their mirror images to the
+//       other copy; the (k, k) blocks by the t-form S_pp - t S_pq,
+//       S_qq + t S_pq, 0) and the entry pairs (E_ap, E_aq) of
+//       E <- E R + (R - I), in place.
+// The blocks and their mirrors partition S and the (row, pair) items
+// partition E, so no two lanes write the same entry within a step.
 constexpr int kInnerThreads = 1024;
 constexpr int kWorkLanes = kInnerThreads - 64;
-constexpr int kBlocks = kH * kH;                 // 2x2 blocks of S
-constexpr int kItems = kBlocks + kB2 * kH;       // blocks, then (row, pair) items of E
+constexpr int kBlocks = kH * (kH + 1) / 2;       // 2x2 blocks (k, l), k <= l, of S
+constexpr int kBlockLanes = (kBlocks + 63) / 64 * 64;   // whole waves, so that work is wave-uniform
+constexpr int kItems = kBlockLanes + kB2 * kH;   // blocks, then (row, pair) items of E
 
 // Local index on ring position pos at step ri of the circle method on kB2
 // indices: position 0 keeps index 0, position pos >= 1 holds
@@ -97,9 +99,9 @@ __device__ __forceinline__ int ring_pair_of(int x, int ri) {
 }
 
 // R_k^T B R_l of the 2x2 block B = [tt tb; bt bb] = S({p_k,q_k}, {p_l,q_l}),
-// k != l.  Rows by the rotation of the smaller pair index first, so that the
-// mirror block (l, k) is computed by the same operations and S stays exactly
-// symmetric: for k > l the transpose is rotated.
+// k != l.  Rows are rotated by the pair with the smaller index first (the
+// block owner works on k < l and writes the mirror image); for k > l the
+// transpose is rotated, which reproduces the owner's values exactly.
 template <typename T>
 __device__ __forceinline__ void rotate_block(T& tt, T& tb, T& bt, T& bb, const Ang<T>& ak, const Ang<T>& al,
                                              bool tr) {
@@ -118,7 +120,7 @@ __device__ __forceinline__ void rotate_block(T& tt, T& tb, T& bt, T& bb, const A
 // diagonalised S is written back), or, when Gpart is given, the sum of the
 // gsplit partial Gram matrices of the one-sided SVD (rel > 0 selects its
 // negligibility rule; nothing is written back to T).
-template <typename T>
+template <typename T, bool BIP>
 __global__ void __launch_bounds__(kInnerThreads)
 blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restrict__ Eall, int* __restrict__ ident,
                  T skip_abs, int max_inner, unsigned long long* __restrict__ rot, const T* __restrict__ Gpart,
@@ -136,8 +138,8 @@ blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restric
   const int k = blockIdx.x;
   const int I = rrb.index(k, r), J = rrb.index(rrb.h + k, r);
   auto gidx = [&](int a) { return a < kH ? I * kH + a : J * kH + (a - kH); };
-  const bool bip = r != 0;                 // bipartite schedule (block steps after the first)
-  const int nsteps = bip ? kH : kB2 - 1;
+  constexpr bool bip = BIP;                // bipartite schedule (block steps after the first)
+  constexpr int nsteps = bip ? kH : kB2 - 1;
   auto pair_at = [&](int i, int ri, int& p, int& q) {
     if (bip) { p = i; q = kH + ((i + ri) & (kH - 1)); }
     else ring_pair(i, ri, p, q);
@@ -166,6 +168,15 @@ blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restric
                              rel);
   }
   __syncthreads();
+  // Block (bk, bl), bk <= bl, of work lane tid - 64 < kBlocks (fixed for all steps).
+  int bk = -1, bl = -1;
+  if (tid >= 64 && tid - 64 < kBlocks) {
+    const int e = tid - 64;
+    int l = 0;
+    while ((l + 1) * (l + 2) / 2 <= e) ++l;
+    bl = l;
+    bk = e - l * (l + 1) / 2;
+  }
   unsigned long long cnt = 0;
   int cur = 0;
   for (int sw = 0; sw < max_inner; ++sw) {
@@ -203,31 +214,37 @@ blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restric
         }
       } else {
         for (int e = tid - 64; e < kItems; e += kWorkLanes) {
-          if (e < kBlocks) {
-            const int kk = e >> 5, lb = e & (kH - 1);
+          if (e < kBlockLanes) {
+            if (bk < 0) continue;
             int pk, qk, pl, ql;
-            pair_at(kk, ri, pk, qk);
-            pair_at(lb, ri, pl, ql);
-            const Ang<T> ak = ac[kk];
+            pair_at(bk, ri, pk, qk);
+            pair_at(bl, ri, pl, ql);
+            const Ang<T> ak = ac[bk];
             T tt = Sc[pk * kLD + pl], tb = Sc[pk * kLD + ql];
             T bt = Sc[qk * kLD + pl], bb = Sc[qk * kLD + ql];
-            if (kk == lb) {
+            if (bk == bl) {
               tt = fmaT(-ak.t, tb, tt);
               bb = fmaT(ak.t, tb, bb);
-              tb = T(0);
-              bt = T(0);
+              Sn[pk * kLD + pk] = tt;
+              Sn[pk * kLD + qk] = T(0);
+              Sn[qk * kLD + pk] = T(0);
+              Sn[qk * kLD + qk] = bb;
             } else {
-              rotate_block(tt, tb, bt, bb, ak, ac[lb], kk > lb);
+              rotate_block(tt, tb, bt, bb, ak, ac[bl], false);
+              Sn[pk * kLD + pl] = tt;
+              Sn[pk * kLD + ql] = tb;
+              Sn[qk * kLD + pl] = bt;
+              Sn[qk * kLD + ql] = bb;
+              Sn[pl * kLD + pk] = tt;
+              Sn[ql * kLD + pk] = tb;
+              Sn[pl * kLD + qk] = bt;
+              Sn[ql * kLD + qk] = bb;
             }
-            Sn[pk * kLD + pl] = tt;
-            Sn[pk * kLD + ql] = tb;
-            Sn[qk * kLD + pl] = bt;
-            Sn[qk * kLD + ql] = bb;
           } else {
             // E <- E R + (R - I) on columns (p, q): with x = E(a, p), y = E(a, q)
             // and dt, db the entries of I in those columns,
             // x' = x - s (y + tau x + db + tau dt), y' = y + s (x - tau y + dt - tau db).
-            const int e2 = e - kBlocks;
+            const int e2 = e - kBlockLanes;
             const int a = e2 >> 5, pr = e2 & (kH - 1);
             const Ang<T> al = ac[pr];
             if (al.applied != T(0)) {
@@ -386,7 +403,6 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
     const T* Ek = Eall + (size_t)k * kB2 * kB2;
     const T* El = Eall + (size_t)l * kB2 * kB2;
     load_efrag<T>(Ek, wm * 32, fa);   // A(i, kk) = E_k(kk, i)
-    load_efrag<T>(El, wn * 32, fb);   // B(kk, j) = E_l(kk, j)
     if (tid < kB2) {
       int Ik = rrb.index(k, r), Jk = rrb.index(rrb.h + k, r);
       int Il = rrb.index(l, r), Jl = rrb.index(rrb.h + l, r);
@@ -402,6 +418,7 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
     acc_zero<T>(acc);
     mm_fragA_ldsB<T>(fa, Bs, wn, acc);      // E_k^T T
     acc_add<T>(Bs, wm, wn, true, acc);      // X = T + E_k^T T (T tile is Bs[i * kLD + j])
+    load_efrag<T>(El, wn * 32, fb);         // B(kk, j) = E_l(kk, j), loaded once fa is dead
     __syncthreads();
     acc_store<T>(Bs, wm, wn, acc);          // Bs[j * kLD + i] = X(i, j): k-major A operand
     __syncthreads();
@@ -547,8 +564,14 @@ int svd_sweep(T* C, int ldc, int mrows, T* V, int ldv, int n, int np, T* Ebuf, i
     hipLaunchKernelGGL((gram_partial_kernel<T>), dim3(npair, gsplit), dim3(kNT), 0, s, C, ldc, mrows, m2, r, krows,
                        Gpart, npair);
     JAC_CHECK_LAUNCH();
-    hipLaunchKernelGGL((blk_inner_kernel<T>), dim3(npair), dim3(kInnerThreads), 0, s, (T*)nullptr, 0, n, m2, r, Ebuf,
-                       ident, T(0), max_inner, rot, (const T*)Gpart, gsplit, npair, rel, (const BDesc<T>*)nullptr);
+    if (r == 0)
+      hipLaunchKernelGGL((blk_inner_kernel<T, false>), dim3(npair), dim3(kInnerThreads), 0, s, (T*)nullptr, 0, n, m2, r,
+                         Ebuf, ident, T(0), max_inner, rot, (const T*)Gpart, gsplit, npair, rel,
+                         (const BDesc<T>*)nullptr);
+    else
+      hipLaunchKernelGGL((blk_inner_kernel<T, true>), dim3(npair), dim3(kInnerThreads), 0, s, (T*)nullptr, 0, n, m2, r,
+                         Ebuf, ident, T(0), max_inner, rot, (const T*)Gpart, gsplit, npair, rel,
+                         (const BDesc<T>*)nullptr);
     JAC_CHECK_LAUNCH();
     // column updates of C (mrows rows) and V (n rows): the chunk path of the update kernel
     hipLaunchKernelGGL((blk_update_kernel<T>), dim3(npair * cch), dim3(kNT), 0, s, (T*)nullptr, 0, C, ldc, mrows, Ebuf,
@@ -652,9 +675,14 @@ int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s) {
   unsigned long long* work = pf && pf->on ? pf->work + st.cls_update : nullptr;
   int e_prev = pf ? pf->mark(s) : -1;
   for (int r = 0; r < m2 - 1; ++r) {
-    hipLaunchKernelGGL((blk_inner_kernel<T>), dim3(m), dim3(kInnerThreads), 0, s, st.Tm, st.ldt, st.n, m2, r, st.W,
-                       st.ident, st.skip_abs, max_inner, st.rot, (const T*)nullptr, 0, m, T(0),
-                       (const BDesc<T>*)nullptr);
+    if (r == 0)
+      hipLaunchKernelGGL((blk_inner_kernel<T, false>), dim3(m), dim3(kInnerThreads), 0, s, st.Tm, st.ldt, st.n, m2, r,
+                         st.W, st.ident, st.skip_abs, max_inner, st.rot, (const T*)nullptr, 0, m, T(0),
+                         (const BDesc<T>*)nullptr);
+    else
+      hipLaunchKernelGGL((blk_inner_kernel<T, true>), dim3(m), dim3(kInnerThreads), 0, s, st.Tm, st.ldt, st.n, m2, r,
+                         st.W, st.ident, st.skip_abs, max_inner, st.rot, (const T*)nullptr, 0, m, T(0),
+                         (const BDesc<T>*)nullptr);
     JAC_CHECK_LAUNCH();
     int e_mid = pf ? pf->mark(s) : -1;
     if (pf) pf->interval(st.cls_inner, e_prev, e_mid);
@@ -685,9 +713,14 @@ int blk_sweep_batched(const BDesc<T>* desc, int count, int np, int max_nvr, int 
   const int ntile = m * (m - 1) / 2;
   const int nvchunk = cdiv(max_nvr, kB2);
   for (int r = 0; r < m2 - 1; ++r) {
-    hipLaunchKernelGGL((blk_inner_kernel<T>), dim3(m, count), dim3(kInnerThreads), 0, s, (T*)nullptr, 0, 0, m2, r,
-                       (T*)nullptr, (int*)nullptr, T(0), max_inner, (unsigned long long*)nullptr, (const T*)nullptr, 0,
-                       m, T(0), desc);
+    if (r == 0)
+      hipLaunchKernelGGL((blk_inner_kernel<T, false>), dim3(m, count), dim3(kInnerThreads), 0, s, (T*)nullptr, 0, 0, m2,
+                         r, (T*)nullptr, (int*)nullptr, T(0), max_inner, (unsigned long long*)nullptr,
+                         (const T*)nullptr, 0, m, T(0), desc);
+    else
+      hipLaunchKernelGGL((blk_inner_kernel<T, true>), dim3(m, count), dim3(kInnerThreads), 0, s, (T*)nullptr, 0, 0, m2,
+                         r, (T*)nullptr, (int*)nullptr, T(0), max_inner, (unsigned long long*)nullptr,
+                         (const T*)nullptr, 0, m, T(0), desc);
     JAC_CHECK_LAUNCH();
     hipLaunchKernelGGL((blk_update_kernel<T>), dim3(ntile + m * nvchunk, count), dim3(kNT), 0, s, (T*)nullptr, 0,
                        (T*)nullptr, 0, 0, (const T*)nullptr, (const int*)nullptr, m2, r, ntile, nvchunk,

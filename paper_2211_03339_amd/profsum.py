@@ -1,0 +1,82 @@
+"""Summaries of rocprofv3 output for the profiles/ folder.
+
+  python -m paper_2211_03339_amd.profsum stats KERNEL_STATS_CSV OUT_TXT "COMMAND"
+      per-kernel calls / total / average / min / max duration from `rocprofv3 --kernel-trace --stats`.
+  python -m paper_2211_03339_amd.profsum traffic FETCH_CSV WRITE_CSV COPY_FETCH_CSV COPY_WRITE_CSV COPY_BYTES
+      OUT_JSON SOURCE "COMMANDS"
+      mean FETCH_SIZE / WRITE_SIZE per dispatch and kernel from two `rocprofv3 --pmc` runs, each
+      scaled by bytes / counter of a plain device copy of COPY_BYTES bytes measured with the same
+      counter, with the sha256 of the kernel source SOURCE (bench.py reports the traffic only
+      while the source is unchanged).
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import sys
+from collections import defaultdict
+
+
+def _rows(path):
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _short(name: str) -> str:
+    name = name.strip()
+    return name.split("(")[0] if "(" in name else name
+
+
+def stats(csv_path: str, out_path: str, command: str):
+    rows = _rows(csv_path)
+    rows.sort(key=lambda r: -float(r.get("TotalDurationNs", 0) or 0))
+    total = sum(float(r.get("TotalDurationNs", 0) or 0) for r in rows)
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", "",
+             f"{'kernel':70s} {'calls':>7s} {'total ms':>10s} {'avg us':>9s} {'min us':>9s} {'max us':>9s} {'share':>6s}"]
+    for r in rows:
+        tot = float(r["TotalDurationNs"])
+        lines.append(f"{_short(r['Name'])[:70]:70s} {int(r['Calls']):7d} {tot / 1e6:10.3f} "
+                     f"{float(r['AverageNs']) / 1e3:9.2f} {float(r['MinNs']) / 1e3:9.2f} "
+                     f"{float(r['MaxNs']) / 1e3:9.2f} {tot / total:6.3f}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def _per_kernel(path, counter):
+    acc = defaultdict(list)
+    for r in _rows(path):
+        if r.get("Counter_Name", counter) != counter:
+            continue
+        acc[_short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
+
+
+def traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv, copy_bytes, out_json, source, command):
+    fetch, nf = _per_kernel(fetch_csv, "FETCH_SIZE")
+    write, nw = _per_kernel(write_csv, "WRITE_SIZE")
+    cf, _ = _per_kernel(cfetch_csv, "FETCH_SIZE")
+    cw, _ = _per_kernel(cwrite_csv, "WRITE_SIZE")
+    # the copy kernel is the one whose mean counter is largest in the copy runs
+    ck = max(cf, key=cf.get)
+    sf = float(copy_bytes) / (cf[ck] * 1024.0)
+    sw = float(copy_bytes) / (cw[max(cw, key=cw.get)] * 1024.0)
+    out = {"source": source, "source_sha256": hashlib.sha256(open(source, "rb").read()).hexdigest(),
+           "command": command, "copy_kernel": ck, "copy_bytes": int(copy_bytes),
+           "scale_fetch": sf, "scale_write": sw, "kernels": {}}
+    for k in sorted(set(fetch) | set(write)):
+        fb = fetch.get(k, 0.0) * 1024.0 * sf
+        wb = write.get(k, 0.0) * 1024.0 * sw
+        out["kernels"][k] = {"fetch_bytes": fb, "write_bytes": wb, "bytes": fb + wb,
+                             "dispatches": max(nf.get(k, 0), nw.get(k, 0))}
+    with open(out_json, "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "traffic":
+        traffic(*sys.argv[2:10])
+    else:
+        raise SystemExit(__doc__)
