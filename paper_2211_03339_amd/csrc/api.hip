@@ -390,18 +390,38 @@ static int fp32_stage(const void* A, bool a_dbl, int n, int lda, double nrmA, do
   return 0;
 }
 
-// T = Q^T A Q with W = A Q, T = Q^T W, then T mirrored from its upper triangle.
+// T = Q^T A Q: Q^T is formed explicitly in T (a coalesced tiled transpose), then W = Q^T A and
+// T = W Q as untransposed GEMMs (a transposed operand streams 128-byte pieces of columns and
+// runs an order of magnitude slower), then T is mirrored from its upper triangle.
 __global__ void mirror_upper_kernel(double* T, int n, int ldt) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y;
   if (i < n && i > j) T[i + (size_t)j * ldt] = T[j + (size_t)i * ldt];
 }
 
+// B = A^T for an n x n block (32 x 32 tiles staged through LDS).
+__global__ void transpose_kernel(const double* __restrict__ A, int n, int lda, double* __restrict__ B, int ldb) {
+  __shared__ double t[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 8 rows of 32
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bx + tx, j = by + r;
+    if (i < n && j < n) t[r][tx] = A[i + (size_t)j * lda];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = by + tx, j = bx + r;
+    if (i < n && j < n) B[i + (size_t)j * ldb] = t[tx][r];
+  }
+}
+
 static int similarity(const double* A, int n, int lda, const double* Q, int ldq, double* T, int ldt, double* W,
                       hipStream_t s) {
-  int e = gemm<double>(false, false, n, n, n, 1.0, A, lda, Q, ldq, 0.0, W, n, s);
+  hipLaunchKernelGGL(transpose_kernel, dim3(cdiv(n, 32), cdiv(n, 32)), dim3(256), 0, s, Q, n, ldq, T, ldt);
+  JAC_CHECK_LAUNCH();
+  int e = gemm<double>(false, false, n, n, n, 1.0, T, ldt, A, lda, 0.0, W, n, s);
   if (e) return e;
-  e = gemm<double>(true, false, n, n, n, 1.0, Q, ldq, W, n, 0.0, T, ldt, s);
+  e = gemm<double>(false, false, n, n, n, 1.0, W, n, Q, ldq, 0.0, T, ldt, s);
   if (e) return e;
   hipLaunchKernelGGL(mirror_upper_kernel, dim3(cdiv(n, 256), n), dim3(256), 0, s, T, n, ldt);
   JAC_CHECK_LAUNCH();

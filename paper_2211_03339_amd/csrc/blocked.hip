@@ -387,32 +387,37 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
     Tm = d.Tm; ldt = d.ldt; V = d.V; ldv = d.ldv; nvr = d.n; Eall = d.E; ident = d.ident;
   }
   constexpr int b = kB2 / 2;
+  constexpr int kPer = kB2 * kB2 / kNT;   // tile entries per thread
   __shared__ T Bs[kB2 * kLD];
-  __shared__ int gk[kB2], gl[kB2];
   const int tid = threadIdx.x, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const RR rrb(m2);
   typename Mfma<T>::acc_t acc[2][2];
   T fa[2][kB2 / 4], fb[2][kB2 / 4];
+  T tv[kPer];
   int w = blockIdx.x;
   if (w < ntile) {
     int k, l;
     stri_decode(w, k, l);
     if (ident[k] && ident[l]) return;
     if (work && tid == 0) atomicAdd(work, 1ull << 32);
+    const int Ik = rrb.index(k, r) * b, Jk = rrb.index(rrb.h + k, r) * b - b;
+    const int Il = rrb.index(l, r) * b, Jl = rrb.index(rrb.h + l, r) * b - b;
+    auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };   // global index of local index a of P_k
+    auto gl = [&](int a) { return a < b ? Il + a : Jl + a; };
+    // Issue the tile loads (HBM) first, then the E fragment loads (L2), then stage the tile.
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kNT, kk = e % kB2, c = e / kB2;
+      tv[q] = Tm[gk(kk) + (size_t)gl(c) * ldt];
+    }
     const T* Ek = Eall + (size_t)k * kB2 * kB2;
     const T* El = Eall + (size_t)l * kB2 * kB2;
     load_efrag<T>(Ek, wm * 32, fa);   // A(i, kk) = E_k(kk, i)
-    if (tid < kB2) {
-      int Ik = rrb.index(k, r), Jk = rrb.index(rrb.h + k, r);
-      int Il = rrb.index(l, r), Jl = rrb.index(rrb.h + l, r);
-      gk[tid] = tid < b ? Ik * b + tid : Jk * b + (tid - b);
-      gl[tid] = tid < b ? Il * b + tid : Jl * b + (tid - b);
-    }
-    __syncthreads();
-    for (int e = tid; e < kB2 * kB2; e += kNT) {
-      int kk = e % kB2, c = e / kB2;
-      Bs[kk * kLD + c] = Tm[gk[kk] + (size_t)gl[c] * ldt];   // B(kk, j = c) = T(P_k[kk], P_l[c])
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kNT, kk = e % kB2, c = e / kB2;
+      Bs[kk * kLD + c] = tv[q];   // B(kk, j = c) = T(P_k[kk], P_l[c])
     }
     __syncthreads();
     acc_zero<T>(acc);
@@ -428,13 +433,15 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
     __syncthreads();
     acc_store<T>(Bs, wm, wn, acc);          // Bs[j * kLD + i] = Y(i, j)
     __syncthreads();
-    for (int e = tid; e < kB2 * kB2; e += kNT) {
-      int i = e % kB2, j = e / kB2;
-      Tm[gk[i] + (size_t)gl[j] * ldt] = Bs[j * kLD + i];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kNT, i = e % kB2, j = e / kB2;
+      Tm[gk(i) + (size_t)gl(j) * ldt] = Bs[j * kLD + i];
     }
-    for (int e = tid; e < kB2 * kB2; e += kNT) {
-      int j = e % kB2, i = e / kB2;
-      Tm[gl[j] + (size_t)gk[i] * ldt] = Bs[j * kLD + i];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kNT, j = e % kB2, i = e / kB2;
+      Tm[gl(j) + (size_t)gk(i) * ldt] = Bs[j * kLD + i];
     }
   } else {
     int wv = w - ntile;
@@ -442,17 +449,20 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
     if (ident[k]) return;
     if (work && tid == 0) atomicAdd(work, 1ull);
     const int row0 = chunk * kB2;
+    const int Ik = rrb.index(k, r) * b, Jk = rrb.index(rrb.h + k, r) * b - b;
+    auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kNT, i = e % kB2, kk = e / kB2;
+      const int row = row0 + i;
+      tv[q] = row < nvr ? V[row + (size_t)gk(kk) * ldv] : T(0);   // A(i, kk) = V(row, P_k[kk])
+    }
     const T* Ek = Eall + (size_t)k * kB2 * kB2;
     load_efrag<T>(Ek, wn * 32, fb);   // B(kk, j) = E_k(kk, j)
-    if (tid < kB2) {
-      int Ik = rrb.index(k, r), Jk = rrb.index(rrb.h + k, r);
-      gk[tid] = tid < b ? Ik * b + tid : Jk * b + (tid - b);
-    }
-    __syncthreads();
-    for (int e = tid; e < kB2 * kB2; e += kNT) {
-      int i = e % kB2, kk = e / kB2;
-      int row = row0 + i;
-      Bs[kk * kLD + i] = row < nvr ? V[row + (size_t)gk[kk] * ldv] : T(0);   // A(i, kk) = V(row, P_k[kk])
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kNT, i = e % kB2, kk = e / kB2;
+      Bs[kk * kLD + i] = tv[q];
     }
     __syncthreads();
     acc_zero<T>(acc);
@@ -461,10 +471,11 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
     __syncthreads();
     acc_store<T>(Bs, wm, wn, acc);
     __syncthreads();
-    for (int e = tid; e < kB2 * kB2; e += kNT) {
-      int i = e % kB2, j = e / kB2;
-      int row = row0 + i;
-      if (row < nvr) V[row + (size_t)gk[j] * ldv] = Bs[j * kLD + i];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kNT, i = e % kB2, j = e / kB2;
+      const int row = row0 + i;
+      if (row < nvr) V[row + (size_t)gk(j) * ldv] = Bs[j * kLD + i];
     }
   }
 }

@@ -15,27 +15,53 @@ namespace jac {
 
 constexpr int kMT = 512;  // threads of the panel kernel (2 waves per SIMD: 256 VGPRs each)
 
+constexpr int next_pow2(int x) { return x <= 1 ? 1 : 2 * next_pow2((x + 1) / 2); }
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
 // Sum NV values (compile-time count) across the workgroup; the totals are
-// left in red[0..NV-1] for every thread.
+// left in red[0..NV-1] for every thread.  Inside a wave the values are summed
+// by halving exchanges: at offset 1 each lane keeps one half of its values and
+// adds the partner's copy of that half, at offset 2 one half of the rest, and
+// so on, so that NP = next_pow2(NV) values cost NP - 1 + 6 - log2(NP)
+// shuffles instead of 6 NV (the many exchanges use the short offsets); lane l
+// then holds the value whose index is the bit reversal of l's low log2(NP)
+// bits.
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds, double* red) {
+  constexpr int NP = next_pow2(NV);
+  constexpr int K = ilog2(NP);
+  static_assert(NP <= 64, "at most 64 values");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double w[NP];
 #pragma unroll
-  for (int j = 0; j < NV; ++j) {
-    double x = v[j];
+  for (int j = 0; j < NP; ++j) w[j] = j < NV ? v[j] : 0.0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    v[j] = x;
+  for (int lvl = 0; lvl < K; ++lvl) {
+    const int o = 1 << lvl;
+    const int half = NP >> (lvl + 1);
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int j = 0; j < half; ++j) {
+      const double send = up ? w[j] : w[j + half];
+      const double keep = up ? w[j + half] : w[j];
+      w[j] = keep + __shfl_xor(send, o, 64);
+    }
   }
-  if (lane == 0) {
+  double x = w[0];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) lds[wave * NV + j] = v[j];
+  for (int o = 1 << K; o < 64; o <<= 1) x += __shfl_xor(x, o, 64);
+  if (lane < NP) {
+    int idx = 0;
+#pragma unroll
+    for (int lvl = 0; lvl < K; ++lvl)
+      if (lane & (1 << lvl)) idx += NP >> (lvl + 1);
+    if (idx < NV) lds[wave * NV + idx] = x;
   }
   __syncthreads();
   if (threadIdx.x < NV) {
     double s = 0;
 #pragma unroll
-    for (int w = 0; w < kMT / 64; ++w) s += lds[w * NV + threadIdx.x];
+    for (int w2 = 0; w2 < kMT / 64; ++w2) s += lds[w2 * NV + threadIdx.x];
     red[threadIdx.x] = s;
   }
   __syncthreads();
