@@ -73,7 +73,13 @@ constexpr int kInnerThreads = 1024;
 constexpr int kWorkLanes = kInnerThreads - 64;
 constexpr int kBlocks = kH * (kH + 1) / 2;       // 2x2 blocks (k, l), k <= l, of S
 constexpr int kBlockLanes = (kBlocks + 63) / 64 * 64;   // whole waves, so that work is wave-uniform
-constexpr int kItems = kBlockLanes + kB2 * kH;   // blocks, then (row, pair) items of E
+constexpr int kEItems = kB2 * kH;                // (row, pair) items of E
+// Work split: lanes below kBlockLanes take one block and 2 E items, the others
+// up to 3 E items; every E item of a lane has the lane's pair (offsets are
+// multiples of kH), so one angle serves them all.
+constexpr int kEPairLo = 2 * kBlockLanes;        // E items of the block lanes
+static_assert(kEPairLo + 3 * (kWorkLanes - kBlockLanes) >= kEItems, "E items covered");
+static_assert(kBlockLanes % kH == 0 && (kWorkLanes - kBlockLanes) % kH == 0, "pair-aligned offsets");
 
 // Local index on ring position pos at step ri of the circle method on kB2
 // indices: position 0 keeps index 0, position pos >= 1 holds
@@ -213,49 +219,88 @@ blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restric
           ang[cur ^ 1][lane] = make_angle(sxx, syy, sxy, gidx(x), gidx(y), n, skip_abs, rel);
         }
       } else {
-        for (int e = tid - 64; e < kItems; e += kWorkLanes) {
-          if (e < kBlockLanes) {
-            if (bk < 0) continue;
-            int pk, qk, pl, ql;
-            pair_at(bk, ri, pk, qk);
-            pair_at(bl, ri, pl, ql);
-            const Ang<T> ak = ac[bk];
-            T tt = Sc[pk * kLD + pl], tb = Sc[pk * kLD + ql];
-            T bt = Sc[qk * kLD + pl], bb = Sc[qk * kLD + ql];
-            if (bk == bl) {
-              tt = fmaT(-ak.t, tb, tt);
-              bb = fmaT(ak.t, tb, bb);
-              Sn[pk * kLD + pk] = tt;
-              Sn[pk * kLD + qk] = T(0);
-              Sn[qk * kLD + pk] = T(0);
-              Sn[qk * kLD + qk] = bb;
-            } else {
-              rotate_block(tt, tb, bt, bb, ak, ac[bl], false);
-              Sn[pk * kLD + pl] = tt;
-              Sn[pk * kLD + ql] = tb;
-              Sn[qk * kLD + pl] = bt;
-              Sn[qk * kLD + ql] = bb;
-              Sn[pl * kLD + pk] = tt;
-              Sn[ql * kLD + pk] = tb;
-              Sn[pl * kLD + qk] = bt;
-              Sn[ql * kLD + qk] = bb;
+        // Loads of all the lane's items first (S and E accesses share one array
+        // each, so the compiler would otherwise keep every load behind the
+        // previous item's stores), then the arithmetic, then the stores.
+        const int t = tid - 64;
+        const bool has_blk = bk >= 0;
+        int pk = 0, qk = 0, pl = 0, ql = 0;
+        T tt = T(0), tb = T(0), bt = T(0), bb = T(0);
+        Ang<T> ak{}, al{};
+        if (has_blk) {
+          pair_at(bk, ri, pk, qk);
+          pair_at(bl, ri, pl, ql);
+          ak = ac[bk];
+          al = ac[bl];
+          tt = Sc[pk * kLD + pl];
+          tb = Sc[pk * kLD + ql];
+          bt = Sc[qk * kLD + pl];
+          bb = Sc[qk * kLD + ql];
+        }
+        // E items of this lane: rows er[0..ne-1], pair pe.
+        int er[3], ne;
+        if (t < kBlockLanes) {
+          er[0] = t >> 5;
+          er[1] = (kBlockLanes + t) >> 5;
+          er[2] = 0;
+          ne = 2;
+        } else {
+          const int t2 = kEPairLo + (t - kBlockLanes);
+          const int stride = kWorkLanes - kBlockLanes;
+          er[0] = t2 >> 5;
+          er[1] = (t2 + stride) >> 5;
+          er[2] = (t2 + 2 * stride) >> 5;
+          ne = t2 + 2 * stride < kEItems ? 3 : 2;
+        }
+        const int pe = t & (kH - 1);
+        const Ang<T> ae = ac[pe];
+        int pp, qp;
+        pair_at(pe, ri, pp, qp);
+        const bool rot_e = ae.applied != T(0);
+        T ex[3], ey[3];
+        if (rot_e) {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            if (q < ne) {
+              ex[q] = E[er[q] * kLD + pp];
+              ey[q] = E[er[q] * kLD + qp];
             }
+          }
+        }
+        if (has_blk) {
+          if (bk == bl) {
+            tt = fmaT(-ak.t, tb, tt);
+            bb = fmaT(ak.t, tb, bb);
+            Sn[pk * kLD + pk] = tt;
+            Sn[pk * kLD + qk] = T(0);
+            Sn[qk * kLD + pk] = T(0);
+            Sn[qk * kLD + qk] = bb;
           } else {
-            // E <- E R + (R - I) on columns (p, q): with x = E(a, p), y = E(a, q)
-            // and dt, db the entries of I in those columns,
-            // x' = x - s (y + tau x + db + tau dt), y' = y + s (x - tau y + dt - tau db).
-            const int e2 = e - kBlockLanes;
-            const int a = e2 >> 5, pr = e2 & (kH - 1);
-            const Ang<T> al = ac[pr];
-            if (al.applied != T(0)) {
-              int pl, ql;
-              pair_at(pr, ri, pl, ql);
-              const T x = E[a * kLD + pl], y = E[a * kLD + ql];
-              const T dt = a == pl ? T(1) : T(0), db = a == ql ? T(1) : T(0);
-              const T px = fmaT(al.tau, x, y) + fmaT(al.tau, dt, db);
-              const T py = fmaT(-al.tau, y, x) + fmaT(-al.tau, db, dt);
-              E[a * kLD + pl] = fmaT(-al.s, px, x);
-              E[a * kLD + ql] = fmaT(al.s, py, y);
+            rotate_block(tt, tb, bt, bb, ak, al, false);
+            Sn[pk * kLD + pl] = tt;
+            Sn[pk * kLD + ql] = tb;
+            Sn[qk * kLD + pl] = bt;
+            Sn[qk * kLD + ql] = bb;
+            Sn[pl * kLD + pk] = tt;
+            Sn[ql * kLD + pk] = tb;
+            Sn[pl * kLD + qk] = bt;
+            Sn[ql * kLD + qk] = bb;
+          }
+        }
+        // E <- E R + (R - I) on columns (p, q): with x = E(a, p), y = E(a, q)
+        // and dt, db the entries of I in those columns,
+        // x' = x - s (y + tau x + db + tau dt), y' = y + s (x - tau y + dt - tau db).
+        if (rot_e) {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            if (q < ne) {
+              const int a = er[q];
+              const T x = ex[q], y = ey[q];
+              const T dt = a == pp ? T(1) : T(0), db = a == qp ? T(1) : T(0);
+              const T px = fmaT(ae.tau, x, y) + fmaT(ae.tau, dt, db);
+              const T py = fmaT(-ae.tau, y, x) + fmaT(-ae.tau, db, dt);
+              E[a * kLD + pp] = fmaT(-ae.s, px, x);
+              E[a * kLD + qp] = fmaT(ae.s, py, y);
             }
           }
         }

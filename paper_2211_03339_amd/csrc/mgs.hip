@@ -94,12 +94,15 @@ __device__ __forceinline__ void mgs_column(double (&v)[R][P], int ncols, const d
         if (threadIdx.x == 0) atomicOr(flag, 1);
         if (!(nrm > 0)) nrm = 1;
       }
+      // One division per column: q_c = v_c * (1 / ||v_c||) and q_c . v_j = (v_c . v_j) * (1 / ||v_c||)
+      // (within an ulp of the quotients; FP64 division is a long instruction sequence).
+      const double inv = 1.0 / nrm;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r][C] = v[r][C] / nrm;
+      for (int r = 0; r < R; ++r) v[r][C] = v[r][C] * inv;
 #pragma unroll
       for (int j = 1; j < NV; ++j) {
         if (C + j < ncols) {
-          double d = red[j] / nrm;
+          double d = red[j] * inv;
 #pragma unroll
           for (int r = 0; r < R; ++r) v[r][C + j] = fma(-d, v[r][C], v[r][C + j]);
         }
