@@ -42,8 +42,13 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds, double* 
     const bool up = (lane & o) != 0;
 #pragma unroll
     for (int j = 0; j < half; ++j) {
-      const double send = up ? w[j] : w[j + half];
-      const double keep = up ? w[j + half] : w[j];
+      // Both halves are pinned in registers before the select; otherwise the
+      // compiler turns "up ? w[j] : w[j + half]" into a runtime index into w,
+      // which it lowers to a compare-and-select chain over all of w.
+      double lo = w[j], hi = w[j + half];
+      asm volatile("" : "+v"(lo), "+v"(hi));
+      const double send = up ? lo : hi;
+      const double keep = up ? hi : lo;
       w[j] = keep + __shfl_xor(send, o, 64);
     }
   }
@@ -72,7 +77,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds, double* 
 // q_c . v_j = (v_c . v_j) / ||v_c||.  C is a compile-time column index so
 // that the register panel is never indexed dynamically.
 template <int R, int P, int C>
-__device__ __forceinline__ void mgs_column(double (&v)[R][P], int ncols, const double* __restrict__ nrm0,
+__device__ __forceinline__ void mgs_column(double (&v)[R][P], int ncols, const double* nrm0,
                                            double* lds, double* red, int* flag) {
   if constexpr (C < P) {
     if (C < ncols) {
@@ -117,14 +122,17 @@ __global__ void __launch_bounds__(kMT) mgs_panel_kernel(double* __restrict__ Q, 
                                                         const double* __restrict__ nrm0, int* __restrict__ flag) {
   __shared__ double lds[(kMT / 64) * P];
   __shared__ double red[P];
+  __shared__ double n0[P];   // original column norms, staged once (a global read per column would
+                             // sit behind every column's reduction)
   double v[R][P];
+  if (threadIdx.x < P) n0[threadIdx.x] = (int)threadIdx.x < ncols ? nrm0[threadIdx.x] : 1.0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     int i = threadIdx.x + r * kMT;
 #pragma unroll
     for (int c = 0; c < P; ++c) v[r][c] = (i < m && c < ncols) ? Q[i + (size_t)c * ldq] : 0.0;
   }
-  mgs_column<R, P, 0>(v, ncols, nrm0, lds, red, flag);
+  mgs_column<R, P, 0>(v, ncols, n0, lds, red, flag);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     int i = threadIdx.x + r * kMT;
