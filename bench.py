@@ -39,9 +39,11 @@ def step_bytes(n: int, dtype_bytes: int) -> float:
     return dtype_bytes * (n * (n + 1) + 2 * n * n)
 
 
-KERNEL_OF = {"inner64": "blk_inner_kernel<double", "update64": "blk_update_kernel<double",
-             "inner32": "blk_inner_kernel<float", "update32": "blk_update_kernel<float",
-             "elem64": "elem_step_kernel<double", "elem32": "elem_step_kernel<float"}
+KERNEL_OF = {"inner64": ("blk_inner_kernel<double", "blk_inner_v_kernel<double"),
+             "update64": ("blk_update_kernel<double",),
+             "inner32": ("blk_inner_kernel<float", "blk_inner_v_kernel<float"),
+             "update32": ("blk_update_kernel<float",),
+             "elem64": ("elem_step_kernel<double",), "elem32": ("elem_step_kernel<float",)}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_n2048.json")
 
 
@@ -54,7 +56,7 @@ def measured_traffic(cls: str):
         src = os.path.join(ROOT, t["source"])
         if hashlib.sha256(open(src, "rb").read()).hexdigest() != t["source_sha256"]:
             return None
-        sel = [v for k, v in t["kernels"].items() if KERNEL_OF.get(cls, "@") in k]
+        sel = [v for k, v in t["kernels"].items() if any(p in k for p in KERNEL_OF.get(cls, ()))]
         calls = sum(v["dispatches"] for v in sel)
         if not calls:
             return None
@@ -69,7 +71,8 @@ def roofline_for(cls: str, k: dict, n: int, rotations: int) -> dict:
     W_k^T T W_l costs 2 * 2(2b)^3, each 2b-row chunk of V W_k costs 2(2b)^3.
     elem*: algorithmic bytes of a parallel step (step_bytes).
     inner*: rotation flops (each rotation of a 2b x 2b subproblem updates two rows and two
-    columns of S and two columns of E: about 12 * 2b flops) on the vector units."""
+    columns of S and two columns of E: about 12 * 2b flops) on the vector units, plus the V
+    chunks (2 (2b)^3 flop each) the same launches update for the previous block step."""
     ms, launches = k["ms"], max(k["launches"], 1)
     avg_s = ms / 1e3 / launches
     if cls.startswith("update"):
@@ -89,7 +92,9 @@ def roofline_for(cls: str, k: dict, n: int, rotations: int) -> dict:
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(cls), "kernel": f"elem_step_kernel<{cls[-2:]}>",
                 "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_bytes_per_launch": bpl,
                 "launches_timed": k["launches"]}
-    flops = rotations * 12 * TILE
+    # inner launches after a sweep's first block step also update V chunks of the previous step
+    # (2 (2b)^3 flop each, on the matrix cores), counted alongside the rotation flops
+    flops = rotations * 12 * TILE + k.get("chunks", 0) * 2 * TILE ** 3
     per_launch = flops / launches
     peak = PEAK["fp64_valu" if cls.endswith("64") else "fp32_valu"]
     ach = per_launch / avg_s / 1e12

@@ -82,8 +82,10 @@ typedef struct jac_stats {
   /* With opts.profile: per kernel class, summed HIP-event time, launch count and
    * work done.  Classes: 0 FP64 inner solve, 1 FP64 block update, 2 FP32 inner
    * solve, 3 FP32 block update, 4 FP64 element step, 5 FP32 element step.
-   * kern_work: update classes = 64x64 GEMM tiles + 64-row chunks computed
-   * (tiles in the high 32 bits, chunks in the low 32 bits); element classes =
+   * The inner-solve launches of block steps after the first also carry the V
+   * update of the previous step.  kern_work: update classes = 64x64 T tiles
+   * (high 32 bits) and 64-row V chunks (low 32 bits) updated; inner classes =
+   * 64-row V chunks updated in the inner-solve launches; element classes =
    * steps. */
   double kern_ms[6];
   long long kern_launches[6];

@@ -103,8 +103,8 @@ static size_t blk_bytes(int n) {
   size_t b = 0;
   b += align_up((size_t)np * np * sizeof(T), 256);
   b += align_up((size_t)n * np * sizeof(T), 256);
-  b += align_up((size_t)m * blk_b2() * blk_b2() * sizeof(T), 256);
-  b += align_up((size_t)m * sizeof(int), 256);
+  b += align_up((size_t)2 * m * blk_b2() * blk_b2() * sizeof(T), 256);   // E, two step parities
+  b += align_up((size_t)2 * m * sizeof(int), 256);
   return b;
 }
 
@@ -231,8 +231,8 @@ static void carve_blk(Carve& c, BlkState<T>& st, int n) {
   st.nvr = n;
   st.ldv = n > 1 ? n : 1;
   st.V = c.take<T>((size_t)n * st.np);
-  st.W = c.take<T>((size_t)(st.np / blk_b2()) * blk_b2() * blk_b2());
-  st.ident = c.take<int>(st.np / blk_b2());
+  st.W = c.take<T>((size_t)2 * (st.np / blk_b2()) * blk_b2() * blk_b2());   // two step parities
+  st.ident = c.take<int>(2 * (st.np / blk_b2()));
 }
 
 // Blocked sweeps until off <= tol*nrm or max_sweeps (same contract as elem_run).

@@ -126,22 +126,21 @@ __device__ __forceinline__ void rotate_block(T& tt, T& tb, T& bt, T& bb, const A
 // diagonalised S is written back), or, when Gpart is given, the sum of the
 // gsplit partial Gram matrices of the one-sided SVD (rel > 0 selects its
 // negligibility rule; nothing is written back to T).
+// LDS of one inner solve: S (ping-pong), E, angles (ping-pong).
+template <typename T>
+constexpr size_t inner_lds_bytes() { return 3 * kB2 * kLD * sizeof(T) + 2 * kH * sizeof(Ang<T>); }
+
 template <typename T, bool BIP>
-__global__ void __launch_bounds__(kInnerThreads)
-blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restrict__ Eall, int* __restrict__ ident,
-                 T skip_abs, int max_inner, unsigned long long* __restrict__ rot, const T* __restrict__ Gpart,
-                 int gsplit, int npair, T rel, const BDesc<T>* __restrict__ desc) {
-  if (desc) {   // batched: matrix blockIdx.y of a size class
-    const BDesc<T> d = desc[blockIdx.y];
-    Tm = d.Tm; ldt = d.ldt; n = d.n; Eall = d.E; ident = d.ident; rot = d.rot;
-    skip_abs = (T)(d.tol_n * sqrt(*d.nrm2));
-  }
-  __shared__ T S[2][kB2 * kLD];
-  __shared__ T E[kB2 * kLD];         // E[a * kLD + c]: row a, column c (local indices)
-  __shared__ Ang<T> ang[2][kH];
+__device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, int n, int m2, int r,
+                                            T* __restrict__ Eall, int* __restrict__ ident, T skip_abs,
+                                            int max_inner, unsigned long long* __restrict__ rot,
+                                            const T* __restrict__ Gpart, int gsplit, int npair, T rel,
+                                            char* __restrict__ smem) {
+  T (*S)[kB2 * kLD] = reinterpret_cast<T (*)[kB2 * kLD]>(smem);            // S[2][..]
+  T* E = reinterpret_cast<T*>(smem) + 2 * kB2 * kLD;                         // E[a * kLD + c]
+  Ang<T> (*ang)[kH] = reinterpret_cast<Ang<T> (*)[kH]>(smem + 3 * kB2 * kLD * sizeof(T));   // ang[2][..]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const RR rrb(m2);
-  const int k = blockIdx.x;
   const int I = rrb.index(k, r), J = rrb.index(rrb.h + k, r);
   auto gidx = [&](int a) { return a < kH ? I * kH + a : J * kH + (a - kH); };
   constexpr bool bip = BIP;                // bipartite schedule (block steps after the first)
@@ -327,6 +326,21 @@ blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restric
   }
 }
 
+template <typename T, bool BIP>
+__global__ void __launch_bounds__(kInnerThreads)
+blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restrict__ Eall, int* __restrict__ ident,
+                 T skip_abs, int max_inner, unsigned long long* __restrict__ rot, const T* __restrict__ Gpart,
+                 int gsplit, int npair, T rel, const BDesc<T>* __restrict__ desc) {
+  if (desc) {   // batched: matrix blockIdx.y of a size class
+    const BDesc<T> d = desc[blockIdx.y];
+    Tm = d.Tm; ldt = d.ldt; n = d.n; Eall = d.E; ident = d.ident; rot = d.rot;
+    skip_abs = (T)(d.tol_n * sqrt(*d.nrm2));
+  }
+  __shared__ __attribute__((aligned(16))) char smem[inner_lds_bytes<T>()];
+  inner_solve<T, BIP>(blockIdx.x, Tm, ldt, n, m2, r, Eall, ident, skip_abs, max_inner, rot, Gpart, gsplit, npair,
+                      rel, smem);
+}
+
 // Fragments of a 2b x 2b row-major E (global, L2-resident) for the MFMA
 // operand of a wave's 32 x 32 quarter: as the A operand of E^T (A(i, kk) =
 // E(kk, i)) or as the B operand of E (B(kk, j) = E(kk, j)) the lane reads
@@ -416,6 +430,54 @@ __device__ __forceinline__ void acc_store(T* M, int wm, int wn, const typename M
       }
 }
 
+// V(row0 .. row0+63, P_k) <- V + V E_k for one 64-row chunk, by 256 threads
+// (tid 0..255, four waves) of the workgroup; Bs: a 64 x (64+1) LDS tile.  Ik
+// and Jk are the global offsets of P_k's two blocks (local index a < b maps
+// to Ik + a, a >= b to Jk + a).  Every thread of the workgroup reaches the
+// same barriers; inactive quarters skip the memory traffic and arithmetic.
+template <typename T>
+__device__ __forceinline__ void vchunk_update(T* __restrict__ V, int ldv, int nvr, const T* __restrict__ Ek, int Ik,
+                                              int Jk, int row0, T* __restrict__ Bs, int tid, bool active) {
+  constexpr int b = kB2 / 2;
+  constexpr int kPer = kB2 * kB2 / kNT;
+  const int wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+  auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };
+  typename Mfma<T>::acc_t acc[2][2];
+  T fb[2][kB2 / 4];
+  T tv[kPer];
+  if (active) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kNT, i = e % kB2, kk = e / kB2;
+      const int row = row0 + i;
+      tv[q] = row < nvr ? V[row + (size_t)gk(kk) * ldv] : T(0);   // A(i, kk) = V(row, P_k[kk])
+    }
+    load_efrag<T>(Ek, wn * 32, fb);   // B(kk, j) = E_k(kk, j)
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kNT, i = e % kB2, kk = e / kB2;
+      Bs[kk * kLD + i] = tv[q];
+    }
+  }
+  __syncthreads();
+  if (active) {
+    acc_zero<T>(acc);
+    mm_ldsA_fragB<T>(Bs, wm, fb, acc);      // V E_k
+    acc_add<T>(Bs, wm, wn, false, acc);     // V + V E_k
+  }
+  __syncthreads();
+  if (active) acc_store<T>(Bs, wm, wn, acc);
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kNT, i = e % kB2, j = e / kB2;
+      const int row = row0 + i;
+      if (row < nvr) V[row + (size_t)gk(j) * ldv] = Bs[j * kLD + i];
+    }
+  }
+}
+
 // Update kernel.  Tile (k, l), k < l:  X = T + E_k^T T,  Y = X + X E_l
 // (= W_k^T T W_l), written to T(P_k, P_l) and mirrored into T(P_l, P_k).
 // V chunk (k, 64 rows):  V(:, P_k) <- V + V E_k.  The matrix-core products
@@ -493,36 +555,49 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
     int k = wv / nvchunk, chunk = wv % nvchunk;
     if (ident[k]) return;
     if (work && tid == 0) atomicAdd(work, 1ull);
-    const int row0 = chunk * kB2;
-    const int Ik = rrb.index(k, r) * b, Jk = rrb.index(rrb.h + k, r) * b - b;
-    auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kNT, i = e % kB2, kk = e / kB2;
-      const int row = row0 + i;
-      tv[q] = row < nvr ? V[row + (size_t)gk(kk) * ldv] : T(0);   // A(i, kk) = V(row, P_k[kk])
-    }
-    const T* Ek = Eall + (size_t)k * kB2 * kB2;
-    load_efrag<T>(Ek, wn * 32, fb);   // B(kk, j) = E_k(kk, j)
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kNT, i = e % kB2, kk = e / kB2;
-      Bs[kk * kLD + i] = tv[q];
-    }
-    __syncthreads();
-    acc_zero<T>(acc);
-    mm_ldsA_fragB<T>(Bs, wm, fb, acc);      // V E_k
-    acc_add<T>(Bs, wm, wn, false, acc);     // V + V E_k
-    __syncthreads();
-    acc_store<T>(Bs, wm, wn, acc);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kNT, i = e % kB2, j = e / kB2;
-      const int row = row0 + i;
-      if (row < nvr) V[row + (size_t)gk(j) * ldv] = Bs[j * kLD + i];
-    }
+    vchunk_update<T>(V, ldv, nvr, Eall + (size_t)k * kB2 * kB2, rrb.index(k, r) * b, rrb.index(rrb.h + k, r) * b - b,
+                     chunk * kB2, Bs, tid, true);
   }
+}
+
+// Inner solves of block step r (workgroups 0 .. npair-1) together with the V
+// update of block step rv = r - 1 (the other workgroups, four 64-row chunks
+// each, one per 256-thread quarter): the V update needs only E of its own
+// step, so it runs on the CUs the 32-odd inner solves leave idle instead of
+// after them.  E and the identity flags alternate between two buffers by step
+// parity (Eall/ident for step r, Ev/identv for step rv).
+template <typename T>
+constexpr size_t inner_v_lds_bytes() {
+  return inner_lds_bytes<T>() > 4 * kB2 * kLD * sizeof(T) ? inner_lds_bytes<T>() : 4 * kB2 * kLD * sizeof(T);
+}
+
+template <typename T, bool BIP>
+__global__ void __launch_bounds__(kInnerThreads)
+blk_inner_v_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restrict__ Eall, int* __restrict__ ident,
+                   T skip_abs, int max_inner, unsigned long long* __restrict__ rot, int npair, T* __restrict__ V,
+                   int ldv, int nvr, const T* __restrict__ Ev, const int* __restrict__ identv, int nvchunk,
+                   unsigned long long* __restrict__ work) {
+  __shared__ __attribute__((aligned(16))) char smem[inner_v_lds_bytes<T>()];
+  if ((int)blockIdx.x < npair) {
+    inner_solve<T, BIP>(blockIdx.x, Tm, ldt, n, m2, r, Eall, ident, skip_abs, max_inner, rot, (const T*)nullptr, 0,
+                        npair, T(0), smem);
+    return;
+  }
+  constexpr int b = kB2 / 2;
+  const int quarter = threadIdx.x >> 8, qt = threadIdx.x & 255;
+  const int ci = ((int)blockIdx.x - npair) * 4 + quarter;
+  const int rv = r - 1;
+  const RR rrb(m2);
+  int k = 0, chunk = 0;
+  bool active = ci < npair * nvchunk;
+  if (active) {
+    k = ci / nvchunk;
+    chunk = ci % nvchunk;
+    active = identv[k] == 0;
+  }
+  if (active && work && qt == 0) atomicAdd(work, 1ull);
+  vchunk_update<T>(V, ldv, nvr, Ev + (size_t)k * kB2 * kB2, rrb.index(k, rv) * b, rrb.index(rrb.h + k, rv) * b - b,
+                   chunk * kB2, reinterpret_cast<T*>(smem) + quarter * kB2 * kLD, qt, active);
 }
 
 // ---------------------------------------------------------------- one-sided
@@ -727,29 +802,46 @@ int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s) {
   const int m2 = st.np / (kB2 / 2), m = m2 / 2;
   const int ntile = m * (m - 1) / 2;
   const int nvchunk = cdiv(st.nvr, kB2);
+  const int vwg = cdiv((long long)m * nvchunk, 4);   // merged launches: four V chunks per workgroup
+  // E and the identity flags alternate by step parity: step r's inner solve
+  // writes buffer r & 1 while the V update of step r - 1 still reads the other.
+  T* Eb[2] = {st.W, st.W + (size_t)m * kB2 * kB2};
+  int* Ib[2] = {st.ident, st.ident + m};
   Prof* pf = st.prof;
-  unsigned long long* work = pf && pf->on ? pf->work + st.cls_update : nullptr;
+  unsigned long long* work_u = pf && pf->on ? pf->work + st.cls_update : nullptr;
+  unsigned long long* work_i = pf && pf->on ? pf->work + st.cls_inner : nullptr;
   int e_prev = pf ? pf->mark(s) : -1;
   for (int r = 0; r < m2 - 1; ++r) {
+    const int par = r & 1;
     if (r == 0)
       hipLaunchKernelGGL((blk_inner_kernel<T, false>), dim3(m), dim3(kInnerThreads), 0, s, st.Tm, st.ldt, st.n, m2, r,
-                         st.W, st.ident, st.skip_abs, max_inner, st.rot, (const T*)nullptr, 0, m, T(0),
+                         Eb[par], Ib[par], st.skip_abs, max_inner, st.rot, (const T*)nullptr, 0, m, T(0),
                          (const BDesc<T>*)nullptr);
     else
-      hipLaunchKernelGGL((blk_inner_kernel<T, true>), dim3(m), dim3(kInnerThreads), 0, s, st.Tm, st.ldt, st.n, m2, r,
-                         st.W, st.ident, st.skip_abs, max_inner, st.rot, (const T*)nullptr, 0, m, T(0),
-                         (const BDesc<T>*)nullptr);
+      hipLaunchKernelGGL((blk_inner_v_kernel<T, true>), dim3(m + vwg), dim3(kInnerThreads), 0, s, st.Tm, st.ldt, st.n,
+                         m2, r, Eb[par], Ib[par], st.skip_abs, max_inner, st.rot, m, st.V, st.ldv, st.nvr,
+                         (const T*)Eb[par ^ 1], (const int*)Ib[par ^ 1], nvchunk, work_i);
     JAC_CHECK_LAUNCH();
     int e_mid = pf ? pf->mark(s) : -1;
     if (pf) pf->interval(st.cls_inner, e_prev, e_mid);
-    int nwg = ntile + m * nvchunk;
-    hipLaunchKernelGGL((blk_update_kernel<T>), dim3(nwg), dim3(kNT), 0, s, st.Tm, st.ldt, st.V, st.ldv, st.nvr, st.W,
-                       st.ident, m2, r, ntile, nvchunk, work);
-    JAC_CHECK_LAUNCH();
-    int e_end = pf ? pf->mark(s) : -1;
-    if (pf) pf->interval(st.cls_update, e_mid, e_end);
-    e_prev = e_end;
+    e_prev = e_mid;
+    if (ntile > 0) {
+      hipLaunchKernelGGL((blk_update_kernel<T>), dim3(ntile), dim3(kNT), 0, s, st.Tm, st.ldt, st.V, st.ldv, st.nvr,
+                         Eb[par], Ib[par], m2, r, ntile, nvchunk, work_u);
+      JAC_CHECK_LAUNCH();
+      int e_end = pf ? pf->mark(s) : -1;
+      if (pf) pf->interval(st.cls_update, e_mid, e_end);
+      e_prev = e_end;
+    }
   }
+  // V update of the sweep's last step (its merged partner would be the next
+  // sweep's first step, which runs the full schedule on its own).
+  const int rl = m2 - 2;
+  hipLaunchKernelGGL((blk_update_kernel<T>), dim3(m * nvchunk), dim3(kNT), 0, s, st.Tm, st.ldt, st.V, st.ldv, st.nvr,
+                     Eb[rl & 1], Ib[rl & 1], m2, rl, 0, nvchunk, work_i);
+  JAC_CHECK_LAUNCH();
+  int e_last = pf ? pf->mark(s) : -1;
+  if (pf) pf->interval(st.cls_inner, e_prev, e_last);
   return 0;
 }
 

@@ -279,8 +279,8 @@ struct BlkState {
   int ldt;
   T* V;                 // nvr x np, leading dimension ldv (pad columns zero)
   int ldv, nvr;
-  T* W;                 // (np / blk_b2()) accumulated 2b x 2b rotations
-  int* ident;           // per pair: W is exactly I
+  T* W;                 // 2 x (np / blk_b2()) accumulated 2b x 2b rotations (E = W - I), by step parity
+  int* ident;           // 2 x (np / blk_b2()) flags: W is exactly I
   T skip_abs;
   double* partial;      // >= 1024
   double* scalars;      // [0] off^2
