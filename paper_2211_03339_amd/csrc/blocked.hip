@@ -561,8 +561,8 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
 }
 
 // Inner solves of block step r (workgroups 0 .. npair-1) together with the V
-// update of block step rv = r - 1 (the other workgroups, four 64-row chunks
-// each, one per 256-thread quarter): the V update needs only E of its own
+// update of block step rv = r - 1 (the other workgroups, 64-row chunks, one
+// per 256-thread quarter at a time): the V update needs only E of its own
 // step, so it runs on the CUs the 32-odd inner solves leave idle instead of
 // after them.  E and the identity flags alternate between two buffers by step
 // parity (Eall/ident for step r, Ev/identv for step rv).
@@ -585,19 +585,25 @@ blk_inner_v_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restr
   }
   constexpr int b = kB2 / 2;
   const int quarter = threadIdx.x >> 8, qt = threadIdx.x & 255;
-  const int ci = ((int)blockIdx.x - npair) * 4 + quarter;
+  const int vwg = (int)gridDim.x - npair;           // V workgroups; each quarter strides over the chunks
+  const int total = npair * nvchunk;
+  const int per = (total + 4 * vwg - 1) / (4 * vwg);   // same trip count in every quarter (shared barriers)
   const int rv = r - 1;
   const RR rrb(m2);
-  int k = 0, chunk = 0;
-  bool active = ci < npair * nvchunk;
-  if (active) {
-    k = ci / nvchunk;
-    chunk = ci % nvchunk;
-    active = identv[k] == 0;
+  for (int it = 0; it < per; ++it) {
+    const int ci = ((int)blockIdx.x - npair) * 4 + quarter + it * 4 * vwg;
+    int k = 0, chunk = 0;
+    bool active = ci < total;
+    if (active) {
+      k = ci / nvchunk;
+      chunk = ci % nvchunk;
+      active = identv[k] == 0;
+    }
+    if (active && work && qt == 0) atomicAdd(work, 1ull);
+    vchunk_update<T>(V, ldv, nvr, Ev + (size_t)k * kB2 * kB2, rrb.index(k, rv) * b,
+                     rrb.index(rrb.h + k, rv) * b - b, chunk * kB2, reinterpret_cast<T*>(smem) + quarter * kB2 * kLD,
+                     qt, active);
   }
-  if (active && work && qt == 0) atomicAdd(work, 1ull);
-  vchunk_update<T>(V, ldv, nvr, Ev + (size_t)k * kB2 * kB2, rrb.index(k, rv) * b, rrb.index(rrb.h + k, rv) * b - b,
-                   chunk * kB2, reinterpret_cast<T*>(smem) + quarter * kB2 * kLD, qt, active);
 }
 
 // ---------------------------------------------------------------- one-sided
@@ -802,7 +808,18 @@ int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s) {
   const int m2 = st.np / (kB2 / 2), m = m2 / 2;
   const int ntile = m * (m - 1) / 2;
   const int nvchunk = cdiv(st.nvr, kB2);
-  const int vwg = cdiv((long long)m * nvchunk, 4);   // merged launches: four V chunks per workgroup
+  // Merged launches: the V workgroups (four chunks at a time, 130 KB of LDS: one per CU) are
+  // sized to the CUs the m inner solves leave free, each looping over its share of the chunks.
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+              ? prop.multiProcessorCount : 256;
+  }
+  int vwg = cdiv((long long)m * nvchunk, 4);
+  const int free_cus = cus - m > 16 ? cus - m : 16;
+  if (vwg > free_cus) vwg = free_cus;
   // E and the identity flags alternate by step parity: step r's inner solve
   // writes buffer r & 1 while the V update of step r - 1 still reads the other.
   T* Eb[2] = {st.W, st.W + (size_t)m * kB2 * kB2};
