@@ -390,6 +390,48 @@ __device__ __forceinline__ void mm_ldsA_fragB(const T* Aop, int wm, const T (&fb
   }
 }
 
+// acc += A * B for a wave's 32 x 32 quarter, one operand a k-major LDS array and
+// the other E (2b x 2b row-major, global and L2-resident), read one k step at a
+// time: the lane reads E[(k0 + lane/16) * 2b + c0 + lane%16] (as the A operand
+// of E^T, A(i, kk) = E(kk, i); as the B operand of E, B(kk, j) = E(kk, j)).
+template <typename T>
+__device__ __forceinline__ void mm_gA_ldsB(const T* __restrict__ Eg, int c0, const T* Bop, int wn,
+                                           typename Mfma<T>::acc_t (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll 4
+  for (int q = 0; q < kB2 / 4; ++q) {
+    const int kr = q * 4 + (lane >> 4), cc = lane & 15;
+    T av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) av[a] = Eg[kr * kB2 + c0 + a * 16 + cc];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) bv[c] = Bop[kr * kLD + wn * 32 + c * 16 + cc];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) acc[a][c] = Mfma<T>::op(av[a], bv[c], acc[a][c]);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void mm_ldsA_gB(const T* Aop, int wm, const T* __restrict__ Eg, int c0,
+                                           typename Mfma<T>::acc_t (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll 4
+  for (int q = 0; q < kB2 / 4; ++q) {
+    const int kr = q * 4 + (lane >> 4), cc = lane & 15;
+    T av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) av[a] = Aop[kr * kLD + wm * 32 + a * 16 + cc];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) bv[c] = Eg[kr * kB2 + c0 + c * 16 + cc];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) acc[a][c] = Mfma<T>::op(av[a], bv[c], acc[a][c]);
+  }
+}
+
 // acc(i, j) += M[j * kLD + i] (jm = false) or M[i * kLD + j] (jm = true).
 template <typename T>
 __device__ __forceinline__ void acc_add(const T* M, int wm, int wn, bool jm, typename Mfma<T>::acc_t (&acc)[2][2]) {
@@ -435,7 +477,7 @@ __device__ __forceinline__ void acc_store(T* M, int wm, int wn, const typename M
 // and Jk are the global offsets of P_k's two blocks (local index a < b maps
 // to Ik + a, a >= b to Jk + a).  Every thread of the workgroup reaches the
 // same barriers; inactive quarters skip the memory traffic and arithmetic.
-template <typename T>
+template <typename T, bool PRELOAD>
 __device__ __forceinline__ void vchunk_update(T* __restrict__ V, int ldv, int nvr, const T* __restrict__ Ek, int Ik,
                                               int Jk, int row0, T* __restrict__ Bs, int tid, bool active) {
   constexpr int b = kB2 / 2;
@@ -443,8 +485,8 @@ __device__ __forceinline__ void vchunk_update(T* __restrict__ V, int ldv, int nv
   const int wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
   auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };
   typename Mfma<T>::acc_t acc[2][2];
-  T fb[2][kB2 / 4];
   T tv[kPer];
+  T fb[PRELOAD ? 2 : 1][PRELOAD ? kB2 / 4 : 1];
   if (active) {
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
@@ -452,7 +494,7 @@ __device__ __forceinline__ void vchunk_update(T* __restrict__ V, int ldv, int nv
       const int row = row0 + i;
       tv[q] = row < nvr ? V[row + (size_t)gk(kk) * ldv] : T(0);   // A(i, kk) = V(row, P_k[kk])
     }
-    load_efrag<T>(Ek, wn * 32, fb);   // B(kk, j) = E_k(kk, j)
+    if constexpr (PRELOAD) load_efrag<T>(Ek, wn * 32, fb);   // B(kk, j) = E_k(kk, j)
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int e = tid + q * kNT, i = e % kB2, kk = e / kB2;
@@ -462,8 +504,9 @@ __device__ __forceinline__ void vchunk_update(T* __restrict__ V, int ldv, int nv
   __syncthreads();
   if (active) {
     acc_zero<T>(acc);
-    mm_ldsA_fragB<T>(Bs, wm, fb, acc);      // V E_k
-    acc_add<T>(Bs, wm, wn, false, acc);     // V + V E_k
+    if constexpr (PRELOAD) mm_ldsA_fragB<T>(Bs, wm, fb, acc);   // V E_k
+    else mm_ldsA_gB<T>(Bs, wm, Ek, wn * 32, acc);
+    acc_add<T>(Bs, wm, wn, false, acc);        // V + V E_k
   }
   __syncthreads();
   if (active) acc_store<T>(Bs, wm, wn, acc);
@@ -478,68 +521,64 @@ __device__ __forceinline__ void vchunk_update(T* __restrict__ V, int ldv, int nv
   }
 }
 
-// Update kernel.  Tile (k, l), k < l:  X = T + E_k^T T,  Y = X + X E_l
-// (= W_k^T T W_l), written to T(P_k, P_l) and mirrored into T(P_l, P_k).
-// V chunk (k, 64 rows):  V(:, P_k) <- V + V E_k.  The matrix-core products
-// accumulate only the E terms (from zero); the base T (X, V) is added once at
-// the end, so each update rounds at the scale of the base once rather than
-// at every k step.
-template <typename T>
-__global__ void __launch_bounds__(kNT)
-blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int nvr, const T* __restrict__ Eall,
-                  const int* __restrict__ ident, int m2, int r, int ntile, int nvchunk,
-                  unsigned long long* __restrict__ work, const BDesc<T>* __restrict__ desc = nullptr) {
-  if (desc) {   // batched: matrix blockIdx.y of a size class
-    const BDesc<T> d = desc[blockIdx.y];
-    Tm = d.Tm; ldt = d.ldt; V = d.V; ldv = d.ldv; nvr = d.n; Eall = d.E; ident = d.ident;
-  }
+// T(P_k, P_l) <- W_k^T T(P_k, P_l) W_l (k < l, W = I + E) and its mirror
+// T(P_l, P_k), by 256 threads (tid 0..255, four waves) of the workgroup; Bs: a
+// 64 x (64+1) LDS tile.  The matrix-core products carry only the E terms and
+// the base tile is added once.  Every thread of the workgroup reaches the
+// same barriers; inactive quarters skip the memory traffic and arithmetic.
+// PRELOAD: the E operands are loaded into registers up front (64 values per
+// lane in FP64: for workgroups with registers to spare); otherwise they are
+// streamed from L2 inside the products (for the 1024-thread merged launches).
+template <typename T, bool PRELOAD>
+__device__ __forceinline__ void tile_update(T* __restrict__ Tm, int ldt, const T* __restrict__ Eall, const RR& rrb,
+                                            int r, int k, int l, T* __restrict__ Bs, int tid, bool active) {
   constexpr int b = kB2 / 2;
-  constexpr int kPer = kB2 * kB2 / kNT;   // tile entries per thread
-  __shared__ T Bs[kB2 * kLD];
-  const int tid = threadIdx.x, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const RR rrb(m2);
+  constexpr int kPer = kB2 * kB2 / kNT;
+  const int wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
   typename Mfma<T>::acc_t acc[2][2];
-  T fa[2][kB2 / 4], fb[2][kB2 / 4];
   T tv[kPer];
-  int w = blockIdx.x;
-  if (w < ntile) {
-    int k, l;
-    stri_decode(w, k, l);
-    if (ident[k] && ident[l]) return;
-    if (work && tid == 0) atomicAdd(work, 1ull << 32);
-    const int Ik = rrb.index(k, r) * b, Jk = rrb.index(rrb.h + k, r) * b - b;
-    const int Il = rrb.index(l, r) * b, Jl = rrb.index(rrb.h + l, r) * b - b;
-    auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };   // global index of local index a of P_k
-    auto gl = [&](int a) { return a < b ? Il + a : Jl + a; };
+  T fa[PRELOAD ? 2 : 1][PRELOAD ? kB2 / 4 : 1], fb[PRELOAD ? 2 : 1][PRELOAD ? kB2 / 4 : 1];
+  const int Ik = rrb.index(k, r) * b, Jk = rrb.index(rrb.h + k, r) * b - b;
+  const int Il = rrb.index(l, r) * b, Jl = rrb.index(rrb.h + l, r) * b - b;
+  auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };   // global index of local index a of P_k
+  auto gl = [&](int a) { return a < b ? Il + a : Jl + a; };
+  const T* Ek = Eall + (size_t)k * kB2 * kB2;
+  const T* El = Eall + (size_t)l * kB2 * kB2;
+  if (active) {
     // Issue the tile loads (HBM) first, then the E fragment loads (L2), then stage the tile.
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int e = tid + q * kNT, kk = e % kB2, c = e / kB2;
       tv[q] = Tm[gk(kk) + (size_t)gl(c) * ldt];
     }
-    const T* Ek = Eall + (size_t)k * kB2 * kB2;
-    const T* El = Eall + (size_t)l * kB2 * kB2;
-    load_efrag<T>(Ek, wm * 32, fa);   // A(i, kk) = E_k(kk, i)
+    if constexpr (PRELOAD) load_efrag<T>(Ek, wm * 32, fa);   // A(i, kk) = E_k(kk, i)
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int e = tid + q * kNT, kk = e % kB2, c = e / kB2;
       Bs[kk * kLD + c] = tv[q];   // B(kk, j = c) = T(P_k[kk], P_l[c])
     }
-    __syncthreads();
+  }
+  __syncthreads();
+  if (active) {
     acc_zero<T>(acc);
-    mm_fragA_ldsB<T>(fa, Bs, wn, acc);      // E_k^T T
-    acc_add<T>(Bs, wm, wn, true, acc);      // X = T + E_k^T T (T tile is Bs[i * kLD + j])
-    load_efrag<T>(El, wn * 32, fb);         // B(kk, j) = E_l(kk, j), loaded once fa is dead
-    __syncthreads();
-    acc_store<T>(Bs, wm, wn, acc);          // Bs[j * kLD + i] = X(i, j): k-major A operand
-    __syncthreads();
+    if constexpr (PRELOAD) mm_fragA_ldsB<T>(fa, Bs, wn, acc);   // E_k^T T
+    else mm_gA_ldsB<T>(Ek, wm * 32, Bs, wn, acc);
+    acc_add<T>(Bs, wm, wn, true, acc);         // X = T + E_k^T T (T tile is Bs[i * kLD + j])
+    if constexpr (PRELOAD) load_efrag<T>(El, wn * 32, fb);   // B(kk, j) = E_l(kk, j), once fa is dead
+  }
+  __syncthreads();
+  if (active) acc_store<T>(Bs, wm, wn, acc);   // Bs[j * kLD + i] = X(i, j): k-major A operand
+  __syncthreads();
+  if (active) {
     acc_zero<T>(acc);
-    mm_ldsA_fragB<T>(Bs, wm, fb, acc);      // X E_l
-    acc_add<T>(Bs, wm, wn, false, acc);     // Y = X + X E_l
-    __syncthreads();
-    acc_store<T>(Bs, wm, wn, acc);          // Bs[j * kLD + i] = Y(i, j)
-    __syncthreads();
+    if constexpr (PRELOAD) mm_ldsA_fragB<T>(Bs, wm, fb, acc);   // X E_l
+    else mm_ldsA_gB<T>(Bs, wm, El, wn * 32, acc);
+    acc_add<T>(Bs, wm, wn, false, acc);        // Y = X + X E_l
+  }
+  __syncthreads();
+  if (active) acc_store<T>(Bs, wm, wn, acc);   // Bs[j * kLD + i] = Y(i, j)
+  __syncthreads();
+  if (active) {
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int e = tid + q * kNT, i = e % kB2, j = e / kB2;
@@ -550,22 +589,104 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
       const int e = tid + q * kNT, j = e % kB2, i = e / kB2;
       Tm[gl(j) + (size_t)gk(i) * ldt] = Bs[j * kLD + i];
     }
+  }
+}
+
+// Block pair (0 .. m-1) holding block B at block step r of the circle method
+// on m2 blocks (the slot rule of RR read backwards).
+__device__ __forceinline__ int block_pair_of(const RR& rrb, int B, int r) {
+  int p = 0;
+  if (B != 0) {
+    p = B - 1 - r;
+    if (p < 0) p += rrb.ne - 1;
+    p += 1;
+  }
+  return p < rrb.h ? p : rrb.ne - 1 - p;
+}
+
+// Tiles of block step r that the inner solves of step r + 1 read: next pair
+// k' = (B1, B2) reads T(B1, B2), which lies in the tile of the step-r pairs
+// holding B1 and B2.  critical_tile(k') gives that tile (a < b) and whether k'
+// is the one that updates it (two next pairs can share a tile; the smaller
+// one does it).  is_critical(a, b) tells the tiles the next pairs need.
+__device__ __forceinline__ bool critical_tile(const RR& rrb, int r, int kn, int& a, int& b) {
+  const int r1 = r + 1;
+  const int B1 = rrb.index(kn, r1), B2 = rrb.index(rrb.h + kn, r1);
+  const int a1 = block_pair_of(rrb, B1, r), b1 = block_pair_of(rrb, B2, r);
+  a = a1 < b1 ? a1 : b1;
+  b = a1 < b1 ? b1 : a1;
+  // the other block of B1's step-r pair, and the next pair it goes to
+  const int A2 = rrb.index(a1, r) == B1 ? rrb.index(rrb.h + a1, r) : rrb.index(a1, r);
+  const int k2 = block_pair_of(rrb, A2, r1);
+  if (k2 == kn) return true;
+  const int C1 = rrb.index(k2, r1), C2 = rrb.index(rrb.h + k2, r1);
+  const int c1 = block_pair_of(rrb, C1, r), c2 = block_pair_of(rrb, C2, r);
+  const bool same = (c1 < c2 ? c1 : c2) == a && (c1 < c2 ? c2 : c1) == b;
+  return !same || kn < k2;
+}
+
+__device__ __forceinline__ bool is_critical(const RR& rrb, int r, int a, int b) {
+  const int r1 = r + 1;
+  const int blocks[2] = {rrb.index(a, r), rrb.index(rrb.h + a, r)};
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int kn = block_pair_of(rrb, blocks[i], r1);
+    const int P1 = rrb.index(kn, r1), P2 = rrb.index(rrb.h + kn, r1);
+    const int partner = P1 == blocks[i] ? P2 : P1;
+    if (block_pair_of(rrb, partner, r) == b) return true;
+  }
+  return false;
+}
+
+// Update kernel.  Tile (k, l), k < l:  X = T + E_k^T T,  Y = X + X E_l
+// (= W_k^T T W_l), written to T(P_k, P_l) and mirrored into T(P_l, P_k).
+// V chunk (k, 64 rows):  V(:, P_k) <- V + V E_k.  The matrix-core products
+// accumulate only the E terms (from zero); the base T (X, V) is added once at
+// the end, so each update rounds at the scale of the base once rather than
+// at every k step.
+template <typename T>
+__global__ void __launch_bounds__(kNT)
+blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int nvr, const T* __restrict__ Eall,
+                  const int* __restrict__ ident, int m2, int r, int ntile, int nvchunk,
+                  unsigned long long* __restrict__ work, const BDesc<T>* __restrict__ desc = nullptr,
+                  int critical = 0) {
+  if (desc) {   // batched: matrix blockIdx.y of a size class
+    const BDesc<T> d = desc[blockIdx.y];
+    Tm = d.Tm; ldt = d.ldt; V = d.V; ldv = d.ldv; nvr = d.n; Eall = d.E; ident = d.ident;
+  }
+  constexpr int b = kB2 / 2;
+  __shared__ T Bs[kB2 * kLD];
+  const int tid = threadIdx.x;
+  const RR rrb(m2);
+  int w = blockIdx.x;
+  if (w < ntile) {
+    int k, l;
+    if (critical) {   // workgroup w: the tile next pair w reads (ntile = number of pairs)
+      if (!critical_tile(rrb, r, w, k, l)) return;
+    } else {
+      stri_decode(w, k, l);
+    }
+    if (ident[k] && ident[l]) return;
+    if (work && tid == 0) atomicAdd(work, 1ull << 32);
+    tile_update<T, true>(Tm, ldt, Eall, rrb, r, k, l, Bs, tid, true);
   } else {
     int wv = w - ntile;
     int k = wv / nvchunk, chunk = wv % nvchunk;
     if (ident[k]) return;
     if (work && tid == 0) atomicAdd(work, 1ull);
-    vchunk_update<T>(V, ldv, nvr, Eall + (size_t)k * kB2 * kB2, rrb.index(k, r) * b, rrb.index(rrb.h + k, r) * b - b,
+    vchunk_update<T, true>(V, ldv, nvr, Eall + (size_t)k * kB2 * kB2, rrb.index(k, r) * b, rrb.index(rrb.h + k, r) * b - b,
                      chunk * kB2, Bs, tid, true);
   }
 }
 
-// Inner solves of block step r (workgroups 0 .. npair-1) together with the V
-// update of block step rv = r - 1 (the other workgroups, 64-row chunks, one
-// per 256-thread quarter at a time): the V update needs only E of its own
-// step, so it runs on the CUs the 32-odd inner solves leave idle instead of
-// after them.  E and the identity flags alternate between two buffers by step
-// parity (Eall/ident for step r, Ev/identv for step rv).
+// Inner solves of block step r (workgroups 0 .. npair-1) together with the
+// rest of the update of block step rv = r - 1 (the other workgroups, one tile
+// or 64-row chunk per 256-thread quarter at a time): the V chunks and, with
+// merge_tiles, the T tiles the inner solves of step r do not read (the ones
+// they read were updated before this launch).  Those need only E of step rv and touch no entry
+// the inner solves touch, so they run on the CUs the inner solves leave idle
+// instead of after them.  E and the identity flags alternate between two
+// buffers by step parity (Eall/ident for step r, Ev/identv for step rv).
 template <typename T>
 constexpr size_t inner_v_lds_bytes() {
   return inner_lds_bytes<T>() > 4 * kB2 * kLD * sizeof(T) ? inner_lds_bytes<T>() : 4 * kB2 * kLD * sizeof(T);
@@ -576,7 +697,7 @@ __global__ void __launch_bounds__(kInnerThreads)
 blk_inner_v_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restrict__ Eall, int* __restrict__ ident,
                    T skip_abs, int max_inner, unsigned long long* __restrict__ rot, int npair, T* __restrict__ V,
                    int ldv, int nvr, const T* __restrict__ Ev, const int* __restrict__ identv, int nvchunk,
-                   unsigned long long* __restrict__ work) {
+                   unsigned long long* __restrict__ work, int merge_tiles) {
   __shared__ __attribute__((aligned(16))) char smem[inner_v_lds_bytes<T>()];
   if ((int)blockIdx.x < npair) {
     inner_solve<T, BIP>(blockIdx.x, Tm, ldt, n, m2, r, Eall, ident, skip_abs, max_inner, rot, (const T*)nullptr, 0,
@@ -585,13 +706,31 @@ blk_inner_v_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restr
   }
   constexpr int b = kB2 / 2;
   const int quarter = threadIdx.x >> 8, qt = threadIdx.x & 255;
-  const int vwg = (int)gridDim.x - npair;           // V workgroups; each quarter strides over the chunks
-  const int total = npair * nvchunk;
-  const int per = (total + 4 * vwg - 1) / (4 * vwg);   // same trip count in every quarter (shared barriers)
+  const int vwg = (int)gridDim.x - npair;           // helper workgroups; each quarter strides over the items
+  const int wq = ((int)blockIdx.x - npair) * 4 + quarter;
   const int rv = r - 1;
   const RR rrb(m2);
+  T* Bs = reinterpret_cast<T*>(smem) + quarter * kB2 * kLD;
+  // The tiles of step rv that the inner solves of step r do not read (the others were updated
+  // before this launch).  All quarters run the same number of iterations (shared barriers).
+  const int ntile = merge_tiles ? npair * (npair - 1) / 2 : 0;
+  const int per_t = (ntile + 4 * vwg - 1) / (4 * vwg);
+  for (int it = 0; it < per_t; ++it) {
+    const int ti = wq + it * 4 * vwg;
+    int k = 0, l = 1;
+    bool active = ti < ntile;
+    if (active) {
+      stri_decode(ti, k, l);
+      active = !is_critical(rrb, rv, k, l) && !(identv[k] && identv[l]);
+    }
+    if (active && work && qt == 0) atomicAdd(work, 1ull << 32);
+    tile_update<T, false>(Tm, ldt, Ev, rrb, rv, k, l, Bs, qt, active);
+  }
+  // The V chunks of step rv.
+  const int total = npair * nvchunk;
+  const int per = (total + 4 * vwg - 1) / (4 * vwg);
   for (int it = 0; it < per; ++it) {
-    const int ci = ((int)blockIdx.x - npair) * 4 + quarter + it * 4 * vwg;
+    const int ci = wq + it * 4 * vwg;
     int k = 0, chunk = 0;
     bool active = ci < total;
     if (active) {
@@ -600,9 +739,8 @@ blk_inner_v_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restr
       active = identv[k] == 0;
     }
     if (active && work && qt == 0) atomicAdd(work, 1ull);
-    vchunk_update<T>(V, ldv, nvr, Ev + (size_t)k * kB2 * kB2, rrb.index(k, rv) * b,
-                     rrb.index(rrb.h + k, rv) * b - b, chunk * kB2, reinterpret_cast<T*>(smem) + quarter * kB2 * kLD,
-                     qt, active);
+    vchunk_update<T, false>(V, ldv, nvr, Ev + (size_t)k * kB2 * kB2, rrb.index(k, rv) * b,
+                     rrb.index(rrb.h + k, rv) * b - b, chunk * kB2, Bs, qt, active);
   }
 }
 
@@ -827,9 +965,15 @@ int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s) {
   Prof* pf = st.prof;
   unsigned long long* work_u = pf && pf->on ? pf->work + st.cls_update : nullptr;
   unsigned long long* work_i = pf && pf->on ? pf->work + st.cls_inner : nullptr;
+  // The helper workgroups of the merged launches also take the T tiles the next inner solves do
+  // not read in FP32; in FP64 (twice the bytes and half the matrix-core rate) those tiles would
+  // outlast the inner solves, so the whole T update stays a launch of its own (measured at
+  // n = 2048: 58.7 vs 64 us per FP32 step, 81.5 vs 78.9 us per FP64 step).
+  constexpr bool kMergeTiles = sizeof(T) == 4;
   int e_prev = pf ? pf->mark(s) : -1;
   for (int r = 0; r < m2 - 1; ++r) {
     const int par = r & 1;
+    const bool last = r == m2 - 2;
     if (r == 0)
       hipLaunchKernelGGL((blk_inner_kernel<T, false>), dim3(m), dim3(kInnerThreads), 0, s, st.Tm, st.ldt, st.n, m2, r,
                          Eb[par], Ib[par], st.skip_abs, max_inner, st.rot, (const T*)nullptr, 0, m, T(0),
@@ -837,28 +981,30 @@ int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s) {
     else
       hipLaunchKernelGGL((blk_inner_v_kernel<T, true>), dim3(m + vwg), dim3(kInnerThreads), 0, s, st.Tm, st.ldt, st.n,
                          m2, r, Eb[par], Ib[par], st.skip_abs, max_inner, st.rot, m, st.V, st.ldv, st.nvr,
-                         (const T*)Eb[par ^ 1], (const int*)Ib[par ^ 1], nvchunk, work_i);
+                         (const T*)Eb[par ^ 1], (const int*)Ib[par ^ 1], nvchunk, work_i, (int)kMergeTiles);
     JAC_CHECK_LAUNCH();
     int e_mid = pf ? pf->mark(s) : -1;
     if (pf) pf->interval(st.cls_inner, e_prev, e_mid);
-    e_prev = e_mid;
-    if (ntile > 0) {
-      hipLaunchKernelGGL((blk_update_kernel<T>), dim3(ntile), dim3(kNT), 0, s, st.Tm, st.ldt, st.V, st.ldv, st.nvr,
-                         Eb[par], Ib[par], m2, r, ntile, nvchunk, work_u);
-      JAC_CHECK_LAUNCH();
-      int e_end = pf ? pf->mark(s) : -1;
-      if (pf) pf->interval(st.cls_update, e_mid, e_end);
-      e_prev = e_end;
+    if (!last && !kMergeTiles) {
+      if (ntile > 0)
+        hipLaunchKernelGGL((blk_update_kernel<T>), dim3(ntile), dim3(kNT), 0, s, st.Tm, st.ldt, st.V, st.ldv, st.nvr,
+                           Eb[par], Ib[par], m2, r, ntile, nvchunk, work_u, (const BDesc<T>*)nullptr, 0);
+    } else if (!last) {
+      // the tiles the next step's inner solves read; the rest go with the next merged launch
+      if (m > 1)
+        hipLaunchKernelGGL((blk_update_kernel<T>), dim3(m), dim3(kNT), 0, s, st.Tm, st.ldt, st.V, st.ldv, st.nvr,
+                           Eb[par], Ib[par], m2, r, m, nvchunk, work_u, (const BDesc<T>*)nullptr, 1);
+    } else {
+      // last step of the sweep: every tile and the V chunks
+      hipLaunchKernelGGL((blk_update_kernel<T>), dim3(ntile + m * nvchunk), dim3(kNT), 0, s, st.Tm, st.ldt, st.V,
+                         st.ldv, st.nvr, Eb[par], Ib[par], m2, r, ntile, nvchunk, work_u, (const BDesc<T>*)nullptr,
+                         0);
     }
+    JAC_CHECK_LAUNCH();
+    int e_end = pf ? pf->mark(s) : -1;
+    if (pf) pf->interval(st.cls_update, e_mid, e_end);
+    e_prev = e_end;
   }
-  // V update of the sweep's last step (its merged partner would be the next
-  // sweep's first step, which runs the full schedule on its own).
-  const int rl = m2 - 2;
-  hipLaunchKernelGGL((blk_update_kernel<T>), dim3(m * nvchunk), dim3(kNT), 0, s, st.Tm, st.ldt, st.V, st.ldv, st.nvr,
-                     Eb[rl & 1], Ib[rl & 1], m2, rl, 0, nvchunk, work_i);
-  JAC_CHECK_LAUNCH();
-  int e_last = pf ? pf->mark(s) : -1;
-  if (pf) pf->interval(st.cls_inner, e_prev, e_last);
   return 0;
 }
 
