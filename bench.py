@@ -92,11 +92,12 @@ def roofline_for(cls: str, k: dict, n: int, rotations: int) -> dict:
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(cls), "kernel": f"elem_step_kernel<{cls[-2:]}>",
                 "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_bytes_per_launch": bpl,
                 "launches_timed": k["launches"]}
-    # inner launches after a sweep's first block step also update the V chunks of the previous
-    # step (2 (2b)^3 flop each, on the matrix cores); those dominate the launch's flops, so the
-    # launch is placed on the matrix-core roofline (its time is set by the sequential inner solve)
+    # inner launches after a sweep's first block step also update the V chunks (2 (2b)^3 flop
+    # each) and, in FP32, T tiles (4 (2b)^3 each) of the previous step on the matrix cores; those
+    # dominate the launch's flops, so the launch is placed on the matrix-core roofline (its time
+    # is set by the sequential inner solve)
     rot_flops = rotations * 12 * TILE
-    v_flops = k.get("chunks", 0) * 2 * TILE ** 3
+    v_flops = k.get("chunks", 0) * 2 * TILE ** 3 + k.get("tiles", 0) * 4 * TILE ** 3
     per_launch = (rot_flops + v_flops) / launches
     bound = "mfma" if v_flops > rot_flops else "alu"
     peak = PEAK[("fp64_" if cls.endswith("64") else "fp32_") + ("mfma" if bound == "mfma" else "valu")]
@@ -105,7 +106,7 @@ def roofline_for(cls: str, k: dict, n: int, rotations: int) -> dict:
             "frac": round(ach / peak, 6), "traffic": measured_traffic(cls),
             "kernel": f"blk_inner_v_kernel<{cls[-2:]}> (+ blk_inner_kernel at step 0)",
             "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_flops_per_launch": per_launch,
-            "rotation_flops_per_launch": rot_flops / launches, "v_update_flops_per_launch": v_flops / launches,
+            "rotation_flops_per_launch": rot_flops / launches, "update_flops_per_launch": v_flops / launches,
             "launches_timed": k["launches"]}
 
 

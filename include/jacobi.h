@@ -83,10 +83,10 @@ typedef struct jac_stats {
    * work done.  Classes: 0 FP64 inner solve, 1 FP64 block update, 2 FP32 inner
    * solve, 3 FP32 block update, 4 FP64 element step, 5 FP32 element step.
    * The inner-solve launches of block steps after the first also carry the V
-   * update of the previous step.  kern_work: update classes = 64x64 T tiles
-   * (high 32 bits) and 64-row V chunks (low 32 bits) updated; inner classes =
-   * 64-row V chunks updated in the inner-solve launches; element classes =
-   * steps. */
+   * update (and in FP32 part of the T update) of the previous step.
+   * kern_work of the inner and update classes: 64x64 T tiles (high 32 bits)
+   * and 64-row V chunks (low 32 bits) updated in those launches; element
+   * classes: steps. */
   double kern_ms[6];
   long long kern_launches[6];
   long long kern_work[6];

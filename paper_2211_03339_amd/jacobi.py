@@ -52,9 +52,8 @@ class JacStats(ctypes.Structure):
              if f not in ("off_hist", "stage_ms", "kern_ms", "kern_launches", "kern_work")}
         names = ["inner64", "update64", "inner32", "update32", "elem64", "elem32"]
         d["kernels"] = {names[i]: {"ms": self.kern_ms[i], "launches": self.kern_launches[i],
-                                   "tiles": self.kern_work[i] >> 32 if i in (1, 3) else 0,
-                                   "chunks": (self.kern_work[i] & 0xFFFFFFFF if i in (1, 3)
-                                              else self.kern_work[i] if i in (0, 2) else 0)}
+                                   "tiles": self.kern_work[i] >> 32 if i < 4 else 0,
+                                   "chunks": self.kern_work[i] & 0xFFFFFFFF if i < 4 else 0}
                         for i in range(6) if self.kern_launches[i]}
         d["off_hist"] = list(self.off_hist[: self.sweeps + 1])
         d["stage_ms"] = dict(zip(["start", "mgs", "similarity", "sweeps", "output", "total", "checks"],
