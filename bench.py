@@ -42,7 +42,7 @@ def step_bytes(n: int, dtype_bytes: int) -> float:
 KERNEL_OF = {"inner64": ("blk_inner_kernel<double", "blk_inner_v_kernel<double"),
              "update64": ("blk_update_kernel<double",),
              "inner32": ("blk_inner_kernel<float", "blk_inner_v_kernel<float"),
-             "update32": ("blk_update_kernel<float",),
+             "update32": ("blk_update_kernel<float", "blk_update16_kernel<float"),
              "elem64": ("elem_step_kernel<double",), "elem32": ("elem_step_kernel<float",)}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_n2048.json")
 
@@ -81,7 +81,7 @@ def roofline_for(cls: str, k: dict, n: int, rotations: int) -> dict:
         peak = PEAK["fp64_mfma" if cls.endswith("64") else "fp32_mfma"]
         ach = per_launch / avg_s / 1e12
         return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(ach / peak, 4), "traffic": measured_traffic(cls), "kernel": f"blk_update_kernel<{cls[-2:]}>",
+                "frac": round(ach / peak, 4), "traffic": measured_traffic(cls), "kernel": ">, ".join(KERNEL_OF[cls]) + ">",
                 "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_flops_per_launch": per_launch,
                 "launches_timed": k["launches"]}
     if cls.startswith("elem"):
@@ -121,6 +121,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-Jacobi comparison")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-start row at n=256")
+    ap.add_argument("--no-elem", action="store_true", help="skip the element-wise variant's step rooflines")
     ap.add_argument("--mlp-train", type=int, default=8192, help="training solves for the learned-start row")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates the HBM byte counters)")
@@ -233,6 +234,22 @@ def main():
                    "share_of_profiled_step": round(v["ms"] / prof_ms, 4)} for c, v in kern.items()}
     others = {c: roofline_for(c, kern[c], n, rot[c[-2:]]) for c in kern if c != dom}
 
+    # The element-wise variant (n/2 disjoint rotations per launch, T and V streamed through HBM):
+    # one profiled preconditioned solve of the U[-1,1] matrix, for its step kernels' rooflines.
+    elem = None
+    if not args.no_elem:
+        est = jacobi.JacStats()
+        o = jacobi._opts("fp32", "element", profile=1)
+        code = jacobi.syev_jacobi_raw(dev[0].data_ptr(), n, n, Ws[0].data_ptr(), Vs[0].data_ptr(), n, args.tol, o,
+                                      est, sp)
+        if code != 0:
+            raise RuntimeError(f"syev_jacobi_ex (element) returned {code}: {jacobi.last_error()}")
+        torch.cuda.synchronize()
+        ed = est.as_dict()
+        elem = {"ms_total": round(ed["stage_ms"]["total"], 3), "sweeps": ed["sweeps"], "fp32_sweeps": ed["fp32_sweeps"],
+                "rooflines": {c: roofline_for(c, v, n, 0) for c, v in ed["kernels"].items() if c.startswith("elem")}}
+        log(f"[bench] element variant: {json.dumps(elem)}")
+
     mlp_row = None
     if not args.no_mlp:
         mlp_row = learned_row(args.mlp_train)
@@ -263,7 +280,8 @@ def main():
                                   f"1e-8 / 10 clusters x 1e-6, one solve of each per step",
                       "n": n, "solves_per_step": len(mats), "variant": args.variant,
                       "tol": args.tol if args.tol > 0 else 20 * 2.0 ** -53},
-           "per_spectrum": per_spec, "plain": plain, "learned_n256": mlp_row, "roofline": roofline,
+           "per_spectrum": per_spec, "plain": plain, "learned_n256": mlp_row, "element_variant": elem,
+           "roofline": roofline,
            "cpu_baseline": cpu,
            "kernels": kernels, "other_rooflines": others}
     print(json.dumps(out), flush=True)

@@ -390,48 +390,6 @@ __device__ __forceinline__ void mm_ldsA_fragB(const T* Aop, int wm, const T (&fb
   }
 }
 
-// acc += A * B for a wave's 32 x 32 quarter, one operand a k-major LDS array and
-// the other E (2b x 2b row-major, global and L2-resident), read one k step at a
-// time: the lane reads E[(k0 + lane/16) * 2b + c0 + lane%16] (as the A operand
-// of E^T, A(i, kk) = E(kk, i); as the B operand of E, B(kk, j) = E(kk, j)).
-template <typename T>
-__device__ __forceinline__ void mm_gA_ldsB(const T* __restrict__ Eg, int c0, const T* Bop, int wn,
-                                           typename Mfma<T>::acc_t (&acc)[2][2]) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll 4
-  for (int q = 0; q < kB2 / 4; ++q) {
-    const int kr = q * 4 + (lane >> 4), cc = lane & 15;
-    T av[2], bv[2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a) av[a] = Eg[kr * kB2 + c0 + a * 16 + cc];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) bv[c] = Bop[kr * kLD + wn * 32 + c * 16 + cc];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) acc[a][c] = Mfma<T>::op(av[a], bv[c], acc[a][c]);
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void mm_ldsA_gB(const T* Aop, int wm, const T* __restrict__ Eg, int c0,
-                                           typename Mfma<T>::acc_t (&acc)[2][2]) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll 4
-  for (int q = 0; q < kB2 / 4; ++q) {
-    const int kr = q * 4 + (lane >> 4), cc = lane & 15;
-    T av[2], bv[2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a) av[a] = Aop[kr * kLD + wm * 32 + a * 16 + cc];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) bv[c] = Eg[kr * kB2 + c0 + c * 16 + cc];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) acc[a][c] = Mfma<T>::op(av[a], bv[c], acc[a][c]);
-  }
-}
-
 // acc(i, j) += M[j * kLD + i] (jm = false) or M[i * kLD + j] (jm = true).
 template <typename T>
 __device__ __forceinline__ void acc_add(const T* M, int wm, int wn, bool jm, typename Mfma<T>::acc_t (&acc)[2][2]) {
@@ -472,123 +430,101 @@ __device__ __forceinline__ void acc_store(T* M, int wm, int wn, const typename M
       }
 }
 
-// V(row0 .. row0+63, P_k) <- V + V E_k for one 64-row chunk, by 256 threads
-// (tid 0..255, four waves) of the workgroup; Bs: a 64 x (64+1) LDS tile.  Ik
-// and Jk are the global offsets of P_k's two blocks (local index a < b maps
-// to Ik + a, a >= b to Jk + a).  Every thread of the workgroup reaches the
-// same barriers; inactive quarters skip the memory traffic and arithmetic.
-template <typename T, bool PRELOAD>
+// V(row0 .. row0+63, P_k) <- V + V E_k for one 64-row chunk by a 256-thread
+// (four-wave) workgroup; Bs: a 64 x (64+1) LDS tile.  Ik and Jk are the global
+// offsets of P_k's two blocks (local index a < b maps to Ik + a, a >= b to
+// Jk + a).  The E operand is held in registers (64 values per lane in FP64).
+template <typename T>
 __device__ __forceinline__ void vchunk_update(T* __restrict__ V, int ldv, int nvr, const T* __restrict__ Ek, int Ik,
-                                              int Jk, int row0, T* __restrict__ Bs, int tid, bool active) {
+                                              int Jk, int row0, T* __restrict__ Bs) {
   constexpr int b = kB2 / 2;
   constexpr int kPer = kB2 * kB2 / kNT;
-  const int wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+  const int tid = threadIdx.x, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
   auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };
   typename Mfma<T>::acc_t acc[2][2];
   T tv[kPer];
-  T fb[PRELOAD ? 2 : 1][PRELOAD ? kB2 / 4 : 1];
-  if (active) {
+  T fb[2][kB2 / 4];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kNT, i = e % kB2, kk = e / kB2;
-      const int row = row0 + i;
-      tv[q] = row < nvr ? V[row + (size_t)gk(kk) * ldv] : T(0);   // A(i, kk) = V(row, P_k[kk])
-    }
-    if constexpr (PRELOAD) load_efrag<T>(Ek, wn * 32, fb);   // B(kk, j) = E_k(kk, j)
+  for (int q = 0; q < kPer; ++q) {
+    const int e = tid + q * kNT, i = e % kB2, kk = e / kB2;
+    const int row = row0 + i;
+    tv[q] = row < nvr ? V[row + (size_t)gk(kk) * ldv] : T(0);   // A(i, kk) = V(row, P_k[kk])
+  }
+  load_efrag<T>(Ek, wn * 32, fb);   // B(kk, j) = E_k(kk, j)
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kNT, i = e % kB2, kk = e / kB2;
-      Bs[kk * kLD + i] = tv[q];
-    }
+  for (int q = 0; q < kPer; ++q) {
+    const int e = tid + q * kNT, i = e % kB2, kk = e / kB2;
+    Bs[kk * kLD + i] = tv[q];
   }
   __syncthreads();
-  if (active) {
-    acc_zero<T>(acc);
-    if constexpr (PRELOAD) mm_ldsA_fragB<T>(Bs, wm, fb, acc);   // V E_k
-    else mm_ldsA_gB<T>(Bs, wm, Ek, wn * 32, acc);
-    acc_add<T>(Bs, wm, wn, false, acc);        // V + V E_k
-  }
+  acc_zero<T>(acc);
+  mm_ldsA_fragB<T>(Bs, wm, fb, acc);    // V E_k
+  acc_add<T>(Bs, wm, wn, false, acc);   // V + V E_k
   __syncthreads();
-  if (active) acc_store<T>(Bs, wm, wn, acc);
+  acc_store<T>(Bs, wm, wn, acc);
   __syncthreads();
-  if (active) {
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kNT, i = e % kB2, j = e / kB2;
-      const int row = row0 + i;
-      if (row < nvr) V[row + (size_t)gk(j) * ldv] = Bs[j * kLD + i];
-    }
+  for (int q = 0; q < kPer; ++q) {
+    const int e = tid + q * kNT, i = e % kB2, j = e / kB2;
+    const int row = row0 + i;
+    if (row < nvr) V[row + (size_t)gk(j) * ldv] = Bs[j * kLD + i];
   }
 }
 
 // T(P_k, P_l) <- W_k^T T(P_k, P_l) W_l (k < l, W = I + E) and its mirror
-// T(P_l, P_k), by 256 threads (tid 0..255, four waves) of the workgroup; Bs: a
-// 64 x (64+1) LDS tile.  The matrix-core products carry only the E terms and
-// the base tile is added once.  Every thread of the workgroup reaches the
-// same barriers; inactive quarters skip the memory traffic and arithmetic.
-// PRELOAD: the E operands are loaded into registers up front (64 values per
-// lane in FP64: for workgroups with registers to spare); otherwise they are
-// streamed from L2 inside the products (for the 1024-thread merged launches).
-template <typename T, bool PRELOAD>
+// T(P_l, P_k) by a 256-thread (four-wave) workgroup; Bs: a 64 x (64+1) LDS
+// tile.  The matrix-core products carry only the E terms and the base tile is
+// added once.  The E operands are held in registers.
+template <typename T>
 __device__ __forceinline__ void tile_update(T* __restrict__ Tm, int ldt, const T* __restrict__ Eall, const RR& rrb,
-                                            int r, int k, int l, T* __restrict__ Bs, int tid, bool active) {
+                                            int r, int k, int l, T* __restrict__ Bs) {
   constexpr int b = kB2 / 2;
   constexpr int kPer = kB2 * kB2 / kNT;
-  const int wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+  const int tid = threadIdx.x, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
   typename Mfma<T>::acc_t acc[2][2];
   T tv[kPer];
-  T fa[PRELOAD ? 2 : 1][PRELOAD ? kB2 / 4 : 1], fb[PRELOAD ? 2 : 1][PRELOAD ? kB2 / 4 : 1];
+  T fa[2][kB2 / 4], fb[2][kB2 / 4];
   const int Ik = rrb.index(k, r) * b, Jk = rrb.index(rrb.h + k, r) * b - b;
   const int Il = rrb.index(l, r) * b, Jl = rrb.index(rrb.h + l, r) * b - b;
   auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };   // global index of local index a of P_k
   auto gl = [&](int a) { return a < b ? Il + a : Jl + a; };
   const T* Ek = Eall + (size_t)k * kB2 * kB2;
   const T* El = Eall + (size_t)l * kB2 * kB2;
-  if (active) {
-    // Issue the tile loads (HBM) first, then the E fragment loads (L2), then stage the tile.
+  // Issue the tile loads (HBM) first, then the E fragment loads (L2), then stage the tile.
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kNT, kk = e % kB2, c = e / kB2;
-      tv[q] = Tm[gk(kk) + (size_t)gl(c) * ldt];
-    }
-    if constexpr (PRELOAD) load_efrag<T>(Ek, wm * 32, fa);   // A(i, kk) = E_k(kk, i)
+  for (int q = 0; q < kPer; ++q) {
+    const int e = tid + q * kNT, kk = e % kB2, c = e / kB2;
+    tv[q] = Tm[gk(kk) + (size_t)gl(c) * ldt];
+  }
+  load_efrag<T>(Ek, wm * 32, fa);   // A(i, kk) = E_k(kk, i)
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kNT, kk = e % kB2, c = e / kB2;
-      Bs[kk * kLD + c] = tv[q];   // B(kk, j = c) = T(P_k[kk], P_l[c])
-    }
+  for (int q = 0; q < kPer; ++q) {
+    const int e = tid + q * kNT, kk = e % kB2, c = e / kB2;
+    Bs[kk * kLD + c] = tv[q];   // B(kk, j = c) = T(P_k[kk], P_l[c])
   }
   __syncthreads();
-  if (active) {
-    acc_zero<T>(acc);
-    if constexpr (PRELOAD) mm_fragA_ldsB<T>(fa, Bs, wn, acc);   // E_k^T T
-    else mm_gA_ldsB<T>(Ek, wm * 32, Bs, wn, acc);
-    acc_add<T>(Bs, wm, wn, true, acc);         // X = T + E_k^T T (T tile is Bs[i * kLD + j])
-    if constexpr (PRELOAD) load_efrag<T>(El, wn * 32, fb);   // B(kk, j) = E_l(kk, j), once fa is dead
-  }
+  acc_zero<T>(acc);
+  mm_fragA_ldsB<T>(fa, Bs, wn, acc);   // E_k^T T
+  acc_add<T>(Bs, wm, wn, true, acc);   // X = T + E_k^T T (T tile is Bs[i * kLD + j])
+  load_efrag<T>(El, wn * 32, fb);      // B(kk, j) = E_l(kk, j), once fa is dead
   __syncthreads();
-  if (active) acc_store<T>(Bs, wm, wn, acc);   // Bs[j * kLD + i] = X(i, j): k-major A operand
+  acc_store<T>(Bs, wm, wn, acc);       // Bs[j * kLD + i] = X(i, j): k-major A operand
   __syncthreads();
-  if (active) {
-    acc_zero<T>(acc);
-    if constexpr (PRELOAD) mm_ldsA_fragB<T>(Bs, wm, fb, acc);   // X E_l
-    else mm_ldsA_gB<T>(Bs, wm, El, wn * 32, acc);
-    acc_add<T>(Bs, wm, wn, false, acc);        // Y = X + X E_l
-  }
+  acc_zero<T>(acc);
+  mm_ldsA_fragB<T>(Bs, wm, fb, acc);   // X E_l
+  acc_add<T>(Bs, wm, wn, false, acc);  // Y = X + X E_l
   __syncthreads();
-  if (active) acc_store<T>(Bs, wm, wn, acc);   // Bs[j * kLD + i] = Y(i, j)
+  acc_store<T>(Bs, wm, wn, acc);       // Bs[j * kLD + i] = Y(i, j)
   __syncthreads();
-  if (active) {
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kNT, i = e % kB2, j = e / kB2;
-      Tm[gk(i) + (size_t)gl(j) * ldt] = Bs[j * kLD + i];
-    }
+  for (int q = 0; q < kPer; ++q) {
+    const int e = tid + q * kNT, i = e % kB2, j = e / kB2;
+    Tm[gk(i) + (size_t)gl(j) * ldt] = Bs[j * kLD + i];
+  }
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kNT, j = e % kB2, i = e / kB2;
-      Tm[gl(j) + (size_t)gk(i) * ldt] = Bs[j * kLD + i];
-    }
+  for (int q = 0; q < kPer; ++q) {
+    const int e = tid + q * kNT, j = e % kB2, i = e / kB2;
+    Tm[gl(j) + (size_t)gk(i) * ldt] = Bs[j * kLD + i];
   }
 }
 
@@ -648,40 +584,192 @@ template <typename T>
 __global__ void __launch_bounds__(kNT)
 blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int nvr, const T* __restrict__ Eall,
                   const int* __restrict__ ident, int m2, int r, int ntile, int nvchunk,
-                  unsigned long long* __restrict__ work, const BDesc<T>* __restrict__ desc = nullptr,
-                  int critical = 0) {
+                  unsigned long long* __restrict__ work, const BDesc<T>* __restrict__ desc = nullptr) {
   if (desc) {   // batched: matrix blockIdx.y of a size class
     const BDesc<T> d = desc[blockIdx.y];
     Tm = d.Tm; ldt = d.ldt; V = d.V; ldv = d.ldv; nvr = d.n; Eall = d.E; ident = d.ident;
   }
   constexpr int b = kB2 / 2;
   __shared__ T Bs[kB2 * kLD];
-  const int tid = threadIdx.x;
   const RR rrb(m2);
-  int w = blockIdx.x;
+  const int w = blockIdx.x;
   if (w < ntile) {
     int k, l;
-    if (critical) {   // workgroup w: the tile next pair w reads (ntile = number of pairs)
+    stri_decode(w, k, l);
+    if (ident[k] && ident[l]) return;
+    if (work && threadIdx.x == 0) atomicAdd(work, 1ull << 32);
+    tile_update<T>(Tm, ldt, Eall, rrb, r, k, l, Bs);
+  } else {
+    const int wv = w - ntile, k = wv / nvchunk, chunk = wv % nvchunk;
+    if (ident[k]) return;
+    if (work && threadIdx.x == 0) atomicAdd(work, 1ull);
+    vchunk_update<T>(V, ldv, nvr, Eall + (size_t)k * kB2 * kB2, rrb.index(k, r) * b, rrb.index(rrb.h + k, r) * b - b,
+                     chunk * kB2, Bs);
+  }
+}
+
+// The same two updates by a whole 1024-thread workgroup: wave w computes the
+// 16 x 16 output block (w / 4, w % 4) of the 64 x 64 result, so each wave runs
+// 16 matrix-core steps per product and holds 16 E values per lane.
+constexpr int kWT = 1024;   // threads of the 16-wave update paths
+
+template <typename T>
+__device__ __forceinline__ void tile_update16(T* __restrict__ Tm, int ldt, const T* __restrict__ Eall, const RR& rrb,
+                                              int r, int k, int l, T* __restrict__ Bs, bool active) {
+  constexpr int b = kB2 / 2;
+  constexpr int kPer = kB2 * kB2 / kWT;   // 4
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bi = wave >> 2, bj = wave & 3, cc = lane & 15, kq = lane >> 4;
+  const int Ik = rrb.index(k, r) * b, Jk = rrb.index(rrb.h + k, r) * b - b;
+  const int Il = rrb.index(l, r) * b, Jl = rrb.index(rrb.h + l, r) * b - b;
+  auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };
+  auto gl = [&](int a) { return a < b ? Il + a : Jl + a; };
+  const T* Ek = Eall + (size_t)k * kB2 * kB2;
+  const T* El = Eall + (size_t)l * kB2 * kB2;
+  typename Mfma<T>::acc_t acc;
+  T fa[kB2 / 4], fb[kB2 / 4];
+  if (active) {
+    T tv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kWT, kk = e % kB2, c = e / kB2;
+      tv[q] = Tm[gk(kk) + (size_t)gl(c) * ldt];
+    }
+#pragma unroll
+    for (int q = 0; q < kB2 / 4; ++q) fa[q] = Ek[(q * 4 + kq) * kB2 + bi * 16 + cc];   // A(i, kk) = E_k(kk, i)
+#pragma unroll
+    for (int q = 0; q < kB2 / 4; ++q) fb[q] = El[(q * 4 + kq) * kB2 + bj * 16 + cc];   // B(kk, j) = E_l(kk, j)
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kWT, kk = e % kB2, c = e / kB2;
+      Bs[kk * kLD + c] = tv[q];   // B(kk, j = c) = T(P_k[kk], P_l[c])
+    }
+  }
+  __syncthreads();
+  if (active) {
+    acc = typename Mfma<T>::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < kB2 / 4; ++q) acc = Mfma<T>::op(fa[q], Bs[(q * 4 + kq) * kLD + bj * 16 + cc], acc);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[rr] += Bs[(bi * 16 + Mfma<T>::row(lane, rr)) * kLD + bj * 16 + cc];   // + T
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) Bs[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)] = acc[rr];   // X, k-major
+  }
+  __syncthreads();
+  if (active) {
+    acc = typename Mfma<T>::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < kB2 / 4; ++q) acc = Mfma<T>::op(Bs[(q * 4 + kq) * kLD + bi * 16 + cc], fb[q], acc);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[rr] += Bs[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)];   // + X
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) Bs[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)] = acc[rr];   // Y
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kWT, i = e % kB2, j = e / kB2;
+      Tm[gk(i) + (size_t)gl(j) * ldt] = Bs[j * kLD + i];
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kWT, j = e % kB2, i = e / kB2;
+      Tm[gl(j) + (size_t)gk(i) * ldt] = Bs[j * kLD + i];
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void vchunk_update16(T* __restrict__ V, int ldv, int nvr, const T* __restrict__ Ek, int Ik,
+                                                int Jk, int row0, T* __restrict__ Bs, bool active) {
+  constexpr int b = kB2 / 2;
+  constexpr int kPer = kB2 * kB2 / kWT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bi = wave >> 2, bj = wave & 3, cc = lane & 15, kq = lane >> 4;
+  auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };
+  typename Mfma<T>::acc_t acc;
+  T fb[kB2 / 4];
+  if (active) {
+    T tv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kWT, i = e % kB2, kk = e / kB2;
+      const int row = row0 + i;
+      tv[q] = row < nvr ? V[row + (size_t)gk(kk) * ldv] : T(0);   // A(i, kk) = V(row, P_k[kk])
+    }
+#pragma unroll
+    for (int q = 0; q < kB2 / 4; ++q) fb[q] = Ek[(q * 4 + kq) * kB2 + bj * 16 + cc];   // B(kk, j) = E_k(kk, j)
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kWT, i = e % kB2, kk = e / kB2;
+      Bs[kk * kLD + i] = tv[q];
+    }
+  }
+  __syncthreads();
+  if (active) {
+    acc = typename Mfma<T>::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < kB2 / 4; ++q) acc = Mfma<T>::op(Bs[(q * 4 + kq) * kLD + bi * 16 + cc], fb[q], acc);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[rr] += Bs[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)];   // + V
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) Bs[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)] = acc[rr];
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kWT, i = e % kB2, j = e / kB2;
+      const int row = row0 + i;
+      if (row < nvr) V[row + (size_t)gk(j) * ldv] = Bs[j * kLD + i];
+    }
+  }
+}
+
+// Update of one block step of the single-matrix path by 1024-thread
+// workgroups: mode 0 every tile then the V chunks (workgroups ntile ..),
+// mode 1 the tiles the next step's inner solves read (workgroup = next pair).
+template <typename T>
+__global__ void __launch_bounds__(kWT)
+blk_update16_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int nvr, const T* __restrict__ Eall,
+                    const int* __restrict__ ident, int m2, int r, int ntile, int nvchunk, int critical,
+                    unsigned long long* __restrict__ work) {
+  constexpr int b = kB2 / 2;
+  __shared__ T Bs[kB2 * kLD];
+  const RR rrb(m2);
+  const int w = blockIdx.x;
+  if (w < ntile) {
+    int k, l;
+    if (critical) {
       if (!critical_tile(rrb, r, w, k, l)) return;
     } else {
       stri_decode(w, k, l);
     }
     if (ident[k] && ident[l]) return;
-    if (work && tid == 0) atomicAdd(work, 1ull << 32);
-    tile_update<T, true>(Tm, ldt, Eall, rrb, r, k, l, Bs, tid, true);
+    if (work && threadIdx.x == 0) atomicAdd(work, 1ull << 32);
+    tile_update16<T>(Tm, ldt, Eall, rrb, r, k, l, Bs, true);
   } else {
-    int wv = w - ntile;
-    int k = wv / nvchunk, chunk = wv % nvchunk;
+    const int wv = w - ntile, k = wv / nvchunk, chunk = wv % nvchunk;
     if (ident[k]) return;
-    if (work && tid == 0) atomicAdd(work, 1ull);
-    vchunk_update<T, true>(V, ldv, nvr, Eall + (size_t)k * kB2 * kB2, rrb.index(k, r) * b, rrb.index(rrb.h + k, r) * b - b,
-                     chunk * kB2, Bs, tid, true);
+    if (work && threadIdx.x == 0) atomicAdd(work, 1ull);
+    vchunk_update16<T>(V, ldv, nvr, Eall + (size_t)k * kB2 * kB2, rrb.index(k, r) * b, rrb.index(rrb.h + k, r) * b - b,
+                       chunk * kB2, Bs, true);
   }
 }
 
 // Inner solves of block step r (workgroups 0 .. npair-1) together with the
 // rest of the update of block step rv = r - 1 (the other workgroups, one tile
-// or 64-row chunk per 256-thread quarter at a time): the V chunks and, with
+// or 64-row chunk at a time, by all 16 waves): the V chunks and, with
 // merge_tiles, the T tiles the inner solves of step r do not read (the ones
 // they read were updated before this launch).  Those need only E of step rv and touch no entry
 // the inner solves touch, so they run on the CUs the inner solves leave idle
@@ -689,7 +777,7 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
 // buffers by step parity (Eall/ident for step r, Ev/identv for step rv).
 template <typename T>
 constexpr size_t inner_v_lds_bytes() {
-  return inner_lds_bytes<T>() > 4 * kB2 * kLD * sizeof(T) ? inner_lds_bytes<T>() : 4 * kB2 * kLD * sizeof(T);
+  return inner_lds_bytes<T>() > kB2 * kLD * sizeof(T) ? inner_lds_bytes<T>() : kB2 * kLD * sizeof(T);
 }
 
 template <typename T, bool BIP>
@@ -705,32 +793,32 @@ blk_inner_v_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restr
     return;
   }
   constexpr int b = kB2 / 2;
-  const int quarter = threadIdx.x >> 8, qt = threadIdx.x & 255;
-  const int vwg = (int)gridDim.x - npair;           // helper workgroups; each quarter strides over the items
-  const int wq = ((int)blockIdx.x - npair) * 4 + quarter;
+  const int vwg = (int)gridDim.x - npair;           // helper workgroups, one item at a time each
+  const int wq = (int)blockIdx.x - npair;
   const int rv = r - 1;
   const RR rrb(m2);
-  T* Bs = reinterpret_cast<T*>(smem) + quarter * kB2 * kLD;
+  T* Bs = reinterpret_cast<T*>(smem);
   // The tiles of step rv that the inner solves of step r do not read (the others were updated
-  // before this launch).  All quarters run the same number of iterations (shared barriers).
+  // before this launch).  Every thread of a workgroup runs the same iterations (barriers).
   const int ntile = merge_tiles ? npair * (npair - 1) / 2 : 0;
-  const int per_t = (ntile + 4 * vwg - 1) / (4 * vwg);
+  const int per_t = (ntile + vwg - 1) / vwg;
   for (int it = 0; it < per_t; ++it) {
-    const int ti = wq + it * 4 * vwg;
+    const int ti = wq + it * vwg;
     int k = 0, l = 1;
     bool active = ti < ntile;
     if (active) {
       stri_decode(ti, k, l);
       active = !is_critical(rrb, rv, k, l) && !(identv[k] && identv[l]);
     }
-    if (active && work && qt == 0) atomicAdd(work, 1ull << 32);
-    tile_update<T, false>(Tm, ldt, Ev, rrb, rv, k, l, Bs, qt, active);
+    if (active && work && threadIdx.x == 0) atomicAdd(work, 1ull << 32);
+    __syncthreads();   // the previous item's last phase still reads Bs
+    tile_update16<T>(Tm, ldt, Ev, rrb, rv, k, l, Bs, active);
   }
   // The V chunks of step rv.
   const int total = npair * nvchunk;
-  const int per = (total + 4 * vwg - 1) / (4 * vwg);
+  const int per = (total + vwg - 1) / vwg;
   for (int it = 0; it < per; ++it) {
-    const int ci = wq + it * 4 * vwg;
+    const int ci = wq + it * vwg;
     int k = 0, chunk = 0;
     bool active = ci < total;
     if (active) {
@@ -738,9 +826,10 @@ blk_inner_v_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restr
       chunk = ci % nvchunk;
       active = identv[k] == 0;
     }
-    if (active && work && qt == 0) atomicAdd(work, 1ull);
-    vchunk_update<T, false>(V, ldv, nvr, Ev + (size_t)k * kB2 * kB2, rrb.index(k, rv) * b,
-                     rrb.index(rrb.h + k, rv) * b - b, chunk * kB2, Bs, qt, active);
+    if (active && work && threadIdx.x == 0) atomicAdd(work, 1ull);
+    __syncthreads();
+    vchunk_update16<T>(V, ldv, nvr, Ev + (size_t)k * kB2 * kB2, rrb.index(k, rv) * b, rrb.index(rrb.h + k, rv) * b - b,
+                       chunk * kB2, Bs, active);
   }
 }
 
@@ -946,8 +1035,8 @@ int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s) {
   const int m2 = st.np / (kB2 / 2), m = m2 / 2;
   const int ntile = m * (m - 1) / 2;
   const int nvchunk = cdiv(st.nvr, kB2);
-  // Merged launches: the V workgroups (four chunks at a time, 130 KB of LDS: one per CU) are
-  // sized to the CUs the m inner solves leave free, each looping over its share of the chunks.
+  // Merged launches: the helper workgroups (one 64 x 64 tile or V chunk at a time, all 16 waves)
+  // are sized to the CUs the m inner solves leave free, each looping over its share of the items.
   static int cus = 0;
   if (!cus) {
     int dev = 0;
@@ -955,9 +1044,11 @@ int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s) {
     cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
               ? prop.multiProcessorCount : 256;
   }
-  int vwg = cdiv((long long)m * nvchunk, 4);
-  const int free_cus = cus - m > 16 ? cus - m : 16;
-  if (vwg > free_cus) vwg = free_cus;
+  // (FP64: the inner solve's LDS allows one workgroup per CU; FP32: two.)
+  const int per_cu = sizeof(T) == 4 ? 2 : 1;
+  int vwg = m * nvchunk;
+  const int free_wgs = (cus - m > 16 ? cus - m : 16) * per_cu;
+  if (vwg > free_wgs) vwg = free_wgs;
   // E and the identity flags alternate by step parity: step r's inner solve
   // writes buffer r & 1 while the V update of step r - 1 still reads the other.
   T* Eb[2] = {st.W, st.W + (size_t)m * kB2 * kB2};
@@ -966,9 +1057,9 @@ int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s) {
   unsigned long long* work_u = pf && pf->on ? pf->work + st.cls_update : nullptr;
   unsigned long long* work_i = pf && pf->on ? pf->work + st.cls_inner : nullptr;
   // The helper workgroups of the merged launches also take the T tiles the next inner solves do
-  // not read in FP32; in FP64 (twice the bytes and half the matrix-core rate) those tiles would
-  // outlast the inner solves, so the whole T update stays a launch of its own (measured at
-  // n = 2048: 58.7 vs 64 us per FP32 step, 81.5 vs 78.9 us per FP64 step).
+  // not read, so only those few tiles stay on the critical path.
+  // In FP64 the helpers have no room left for them (the V chunks alone keep them busy for about
+  // as long as the inner solves take), so all FP64 tiles are updated after the inner launch.
   constexpr bool kMergeTiles = sizeof(T) == 4;
   int e_prev = pf ? pf->mark(s) : -1;
   for (int r = 0; r < m2 - 1; ++r) {
@@ -988,17 +1079,21 @@ int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s) {
     if (!last && !kMergeTiles) {
       if (ntile > 0)
         hipLaunchKernelGGL((blk_update_kernel<T>), dim3(ntile), dim3(kNT), 0, s, st.Tm, st.ldt, st.V, st.ldv, st.nvr,
-                           Eb[par], Ib[par], m2, r, ntile, nvchunk, work_u, (const BDesc<T>*)nullptr, 0);
+                           (const T*)Eb[par], (const int*)Ib[par], m2, r, ntile, nvchunk, work_u,
+                           (const BDesc<T>*)nullptr);
     } else if (!last) {
       // the tiles the next step's inner solves read; the rest go with the next merged launch
       if (m > 1)
-        hipLaunchKernelGGL((blk_update_kernel<T>), dim3(m), dim3(kNT), 0, s, st.Tm, st.ldt, st.V, st.ldv, st.nvr,
-                           Eb[par], Ib[par], m2, r, m, nvchunk, work_u, (const BDesc<T>*)nullptr, 1);
-    } else {
+        hipLaunchKernelGGL((blk_update16_kernel<T>), dim3(m), dim3(kWT), 0, s, st.Tm, st.ldt, st.V, st.ldv, st.nvr,
+                           Eb[par], Ib[par], m2, r, m, nvchunk, 1, work_u);
+    } else if (kMergeTiles) {
       // last step of the sweep: every tile and the V chunks
+      hipLaunchKernelGGL((blk_update16_kernel<T>), dim3(ntile + m * nvchunk), dim3(kWT), 0, s, st.Tm, st.ldt, st.V,
+                         st.ldv, st.nvr, Eb[par], Ib[par], m2, r, ntile, nvchunk, 0, work_u);
+    } else {
       hipLaunchKernelGGL((blk_update_kernel<T>), dim3(ntile + m * nvchunk), dim3(kNT), 0, s, st.Tm, st.ldt, st.V,
-                         st.ldv, st.nvr, Eb[par], Ib[par], m2, r, ntile, nvchunk, work_u, (const BDesc<T>*)nullptr,
-                         0);
+                         st.ldv, st.nvr, (const T*)Eb[par], (const int*)Ib[par], m2, r, ntile, nvchunk, work_u,
+                         (const BDesc<T>*)nullptr);
     }
     JAC_CHECK_LAUNCH();
     int e_end = pf ? pf->mark(s) : -1;
