@@ -40,9 +40,9 @@ def step_bytes(n: int, dtype_bytes: int) -> float:
 
 
 KERNEL_OF = {"inner64": ("blk_inner_kernel<double", "blk_inner_v_kernel<double"),
-             "update64": ("blk_update_kernel<double",),
+             "update64": ("blk_update16_kernel<double",),
              "inner32": ("blk_inner_kernel<float", "blk_inner_v_kernel<float"),
-             "update32": ("blk_update_kernel<float", "blk_update16_kernel<float"),
+             "update32": ("blk_update16_kernel<float",),
              "elem64": ("elem_step_kernel<double",), "elem32": ("elem_step_kernel<float",)}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_n2048.json")
 
@@ -92,10 +92,10 @@ def roofline_for(cls: str, k: dict, n: int, rotations: int) -> dict:
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(cls), "kernel": f"elem_step_kernel<{cls[-2:]}>",
                 "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_bytes_per_launch": bpl,
                 "launches_timed": k["launches"]}
-    # inner launches after a sweep's first block step also update the V chunks (2 (2b)^3 flop
-    # each) and, in FP32, T tiles (4 (2b)^3 each) of the previous step on the matrix cores; those
-    # dominate the launch's flops, so the launch is placed on the matrix-core roofline (its time
-    # is set by the sequential inner solve)
+    # inner launches after a sweep's first block step also carry the whole update of the previous
+    # step on the matrix cores: its V chunks (2 (2b)^3 flop each) and T tiles (4 (2b)^3 each,
+    # counted once also where two inner workgroups compute the same tile); those dominate the
+    # launch's flops, so the launch is placed on the matrix-core roofline
     rot_flops = rotations * 12 * TILE
     v_flops = k.get("chunks", 0) * 2 * TILE ** 3 + k.get("tiles", 0) * 4 * TILE ** 3
     per_launch = (rot_flops + v_flops) / launches

@@ -97,6 +97,12 @@ static size_t elem_bytes(int n) {
   return b;
 }
 
+// Off-diagonal tiles of the block sweeps (at least one slot).
+static int blk_ntile(int np) {
+  const int m = np / blk_b2();
+  return m > 1 ? m * (m - 1) / 2 : 1;
+}
+
 template <typename T>
 static size_t blk_bytes(int n) {
   int np = blk_np(n), m = np / blk_b2();
@@ -105,6 +111,7 @@ static size_t blk_bytes(int n) {
   b += align_up((size_t)n * np * sizeof(T), 256);
   b += align_up((size_t)2 * m * blk_b2() * blk_b2() * sizeof(T), 256);   // E, two step parities
   b += align_up((size_t)2 * m * sizeof(int), 256);
+  b += align_up((size_t)blk_ntile(np) * sizeof(int), 256);   // tile reader counters
   return b;
 }
 
@@ -233,6 +240,7 @@ static void carve_blk(Carve& c, BlkState<T>& st, int n) {
   st.V = c.take<T>((size_t)n * st.np);
   st.W = c.take<T>((size_t)2 * (st.np / blk_b2()) * blk_b2() * blk_b2());   // two step parities
   st.ident = c.take<int>(2 * (st.np / blk_b2()));
+  st.tcount = c.take<int>(blk_ntile(st.np));
 }
 
 // Blocked sweeps until off <= tol*nrm or max_sweeps (same contract as elem_run).
@@ -247,6 +255,7 @@ static int blk_run(BlkState<T>& st, double tol, double nrm, int max_sweeps, int 
     *step_ms = 0;
   }
   JAC_HIP(hipMemsetAsync(st.rot, 0, sizeof(unsigned long long), s));
+  JAC_HIP(hipMemsetAsync(st.tcount, 0, (size_t)blk_ntile(st.np) * sizeof(int), s));
   double off2 = 0;
   int e = blk_offnorm2<T>(st, s);
   if (e) return e;

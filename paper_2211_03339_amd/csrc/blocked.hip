@@ -127,6 +127,86 @@ __device__ __forceinline__ void rotate_block(T& tt, T& tb, T& bt, T& bb, const A
 // gsplit partial Gram matrices of the one-sided SVD (rel > 0 selects its
 // negligibility rule; nothing is written back to T).
 // LDS of one inner solve: S (ping-pong), E, angles (ping-pong).
+// Block pair (0 .. m-1) holding block B at block step r of the circle method
+// on m2 blocks (the slot rule of RR read backwards).
+__device__ __forceinline__ int block_pair_of(const RR& rrb, int B, int r) {
+  int p = 0;
+  if (B != 0) {
+    p = B - 1 - r;
+    if (p < 0) p += rrb.ne - 1;
+    p += 1;
+  }
+  return p < rrb.h ? p : rrb.ne - 1 - p;
+}
+
+// Y = W_k^T T(P_k, P_l) W_l (W = I + E) of one 64 x 64 tile by the 16 waves of
+// a 1024-thread workgroup: wave w computes the 16 x 16 output block
+// (w / 4, w % 4), so each wave runs 16 matrix-core steps per product and holds
+// 16 E values per lane.  Global index of local index a: P_k(a) = a < b ? Ik + a
+// : Jk + a (Jk already offset by -b), likewise P_l.  The products carry only
+// the E terms; the base is added once.  Leaves Y in Bs (Bs[j * kLD + i] =
+// Y(i, j), a 64 x (64+1) LDS tile) and ends with a barrier; every thread of
+// the workgroup reaches the same barriers, inactive ones skip the work.
+constexpr int kWT = 1024;   // threads of the 16-wave update paths
+
+template <typename T>
+__device__ __forceinline__ void tile_product16(const T* __restrict__ Tm, int ldt, const T* __restrict__ Ek,
+                                               const T* __restrict__ El, int Ik, int Jk, int Il, int Jl,
+                                               T* __restrict__ Bs, bool active) {
+  constexpr int b = kB2 / 2;
+  constexpr int kPer = kB2 * kB2 / kWT;   // 4
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bi = wave >> 2, bj = wave & 3, cc = lane & 15, kq = lane >> 4;
+  auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };
+  auto gl = [&](int a) { return a < b ? Il + a : Jl + a; };
+  typename Mfma<T>::acc_t acc;
+  T fa[kB2 / 4], fb[kB2 / 4];
+  if (active) {
+    T tv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kWT, kk = e % kB2, c = e / kB2;
+      tv[q] = Tm[gk(kk) + (size_t)gl(c) * ldt];
+    }
+#pragma unroll
+    for (int q = 0; q < kB2 / 4; ++q) fa[q] = Ek[(q * 4 + kq) * kB2 + bi * 16 + cc];   // A(i, kk) = E_k(kk, i)
+#pragma unroll
+    for (int q = 0; q < kB2 / 4; ++q) fb[q] = El[(q * 4 + kq) * kB2 + bj * 16 + cc];   // B(kk, j) = E_l(kk, j)
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kWT, kk = e % kB2, c = e / kB2;
+      Bs[kk * kLD + c] = tv[q];   // B(kk, j = c) = T(P_k[kk], P_l[c])
+    }
+  }
+  __syncthreads();
+  if (active) {
+    acc = typename Mfma<T>::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < kB2 / 4; ++q) acc = Mfma<T>::op(fa[q], Bs[(q * 4 + kq) * kLD + bj * 16 + cc], acc);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[rr] += Bs[(bi * 16 + Mfma<T>::row(lane, rr)) * kLD + bj * 16 + cc];   // + T
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) Bs[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)] = acc[rr];   // X, k-major
+  }
+  __syncthreads();
+  if (active) {
+    acc = typename Mfma<T>::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < kB2 / 4; ++q) acc = Mfma<T>::op(Bs[(q * 4 + kq) * kLD + bi * 16 + cc], fb[q], acc);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[rr] += Bs[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)];   // + X
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) Bs[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)] = acc[rr];   // Y
+  }
+  __syncthreads();
+}
+
 template <typename T>
 constexpr size_t inner_lds_bytes() { return 3 * kB2 * kLD * sizeof(T) + 2 * kH * sizeof(Ang<T>); }
 
@@ -135,7 +215,10 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
                                             T* __restrict__ Eall, int* __restrict__ ident, T skip_abs,
                                             int max_inner, unsigned long long* __restrict__ rot,
                                             const T* __restrict__ Gpart, int gsplit, int npair, T rel,
-                                            char* __restrict__ smem) {
+                                            char* __restrict__ smem, const T* __restrict__ Ev = nullptr,
+                                            const int* __restrict__ identv = nullptr,
+                                            int* __restrict__ tcount = nullptr,
+                                            unsigned long long* __restrict__ work = nullptr) {
   T (*S)[kB2 * kLD] = reinterpret_cast<T (*)[kB2 * kLD]>(smem);            // S[2][..]
   T* E = reinterpret_cast<T*>(smem) + 2 * kB2 * kLD;                         // E[a * kLD + c]
   Ang<T> (*ang)[kH] = reinterpret_cast<Ang<T> (*)[kH]>(smem + 3 * kB2 * kLD * sizeof(T));   // ang[2][..]
@@ -152,18 +235,87 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
   auto pair_of = [&](int x, int ri) {
     return bip ? (x < kH ? x : ((x - kH - ri) & (kH - 1))) : ring_pair_of(x, ri);
   };
-  for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
-    const int a = e % kB2, c = e / kB2;
-    T v;
-    if (Gpart) {
-      // partial Grams are indexed by local indices (a, c), column-major
-      v = T(0);
-      for (int z = 0; z < gsplit; ++z) v += Gpart[((size_t)z * npair + k) * kB2 * kB2 + a + c * kB2];
-    } else {
-      v = Tm[gidx(a) + (size_t)gidx(c) * ldt];
+  if (Ev) {
+    // The update of block step r - 1 has not been applied to the tile that holds T(I, J):
+    // compute that tile Y = W_ka^T T(P_ka, P_kb) W_kb here (ka < kb: the step r - 1 pairs of I
+    // and J), take the quarter T(I, J) from it, and write back the quarters no inner solve of
+    // this step reads.  A tile can hold the quarters of two pairs of this step; both compute it,
+    // and the later of the two (per-tile counter) writes, after both have read the old tile.
+    // T(I, I) and T(J, J) lie in diagonal blocks of step r - 1, final since its inner solves.
+    constexpr int kPer = kB2 * kB2 / kInnerThreads;
+    const int rv = r - 1;
+    const int k1 = block_pair_of(rrb, I, rv), k2 = block_pair_of(rrb, J, rv);
+    const bool swap = k1 > k2;   // I belongs to the second pair of the tile
+    const int ka = swap ? k2 : k1, kb = swap ? k1 : k2;
+    const int A0 = rrb.index(ka, rv), A1 = rrb.index(rrb.h + ka, rv);
+    const int B0 = rrb.index(kb, rv), B1 = rrb.index(rrb.h + kb, rv);
+    const int hI = I == (swap ? B0 : A0) ? 0 : 1, hJ = J == (swap ? A0 : B0) ? 0 : 1;
+    const bool id = identv[ka] && identv[kb];
+    T sv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kInnerThreads, a = e % kB2, c = e / kB2;
+      sv[q] = (id || (a < kH) == (c < kH)) ? Tm[gidx(a) + (size_t)gidx(c) * ldt] : T(0);
     }
-    S[0][a * kLD + c] = v;
-    E[a * kLD + c] = T(0);
+    T* Y = S[1];
+    tile_product16<T>(Tm, ldt, Ev + (size_t)ka * kB2 * kB2, Ev + (size_t)kb * kB2 * kB2, A0 * kH, A1 * kH - kH,
+                      B0 * kH, B1 * kH - kH, Y, !id);
+    int* flag = reinterpret_cast<int*>(ang);
+    // quarters (x, y), x of pair ka, y of pair kb, that pairs of this step read
+    auto read_now = [&](int x, int y) { return block_pair_of(rrb, x, r) == block_pair_of(rrb, y, r); };
+    const int readers = (int)read_now(A0, B0) + (int)read_now(A0, B1) + (int)read_now(A1, B0) + (int)read_now(A1, B1);
+    if (tid == 0 && !id) {
+      bool last = true;
+      if (readers > 1) {
+        const int ti = kb * (kb - 1) / 2 + ka;
+        last = atomicAdd(tcount + ti, 1) == readers - 1;
+        if (last) atomicExch(tcount + ti, 0);
+      }
+      flag[0] = last;
+      if (last && work) atomicAdd(work, 1ull << 32);
+    }
+    __syncthreads();
+    const bool write_rest = !id && flag[0];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kInnerThreads, a = e % kB2, c = e / kB2;
+      T v = sv[q];
+      if (!id && (a < kH) != (c < kH)) {
+        const int x = a < kH ? a : c, y = a < kH ? c - kH : a - kH;   // S(x, kH + y) = T(I_x, J_y)
+        v = swap ? Y[(hI * kH + x) * kLD + hJ * kH + y] : Y[(hJ * kH + y) * kLD + hI * kH + x];
+      }
+      S[0][a * kLD + c] = v;
+      E[a * kLD + c] = T(0);
+    }
+    if (write_rest) {
+      auto gA = [&](int u) { return u < kH ? A0 * kH + u : A1 * kH + u - kH; };
+      auto gB = [&](int v) { return v < kH ? B0 * kH + v : B1 * kH + v - kH; };
+      auto keep = [&](int u, int v) { return !read_now(u < kH ? A0 : A1, v < kH ? B0 : B1); };
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int e = tid + q * kInnerThreads, u = e % kB2, v = e / kB2;
+        if (keep(u, v)) Tm[gA(u) + (size_t)gB(v) * ldt] = Y[v * kLD + u];
+      }
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int e = tid + q * kInnerThreads, v = e % kB2, u = e / kB2;
+        if (keep(u, v)) Tm[gB(v) + (size_t)gA(u) * ldt] = Y[v * kLD + u];
+      }
+    }
+  } else {
+    for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
+      const int a = e % kB2, c = e / kB2;
+      T v;
+      if (Gpart) {
+        // partial Grams are indexed by local indices (a, c), column-major
+        v = T(0);
+        for (int z = 0; z < gsplit; ++z) v += Gpart[((size_t)z * npair + k) * kB2 * kB2 + a + c * kB2];
+      } else {
+        v = Tm[gidx(a) + (size_t)gidx(c) * ldt];
+      }
+      S[0][a * kLD + c] = v;
+      E[a * kLD + c] = T(0);
+    }
   }
   __syncthreads();
   if (tid < kH) {   // angles of the first step
@@ -528,39 +680,10 @@ __device__ __forceinline__ void tile_update(T* __restrict__ Tm, int ldt, const T
   }
 }
 
-// Block pair (0 .. m-1) holding block B at block step r of the circle method
-// on m2 blocks (the slot rule of RR read backwards).
-__device__ __forceinline__ int block_pair_of(const RR& rrb, int B, int r) {
-  int p = 0;
-  if (B != 0) {
-    p = B - 1 - r;
-    if (p < 0) p += rrb.ne - 1;
-    p += 1;
-  }
-  return p < rrb.h ? p : rrb.ne - 1 - p;
-}
-
 // Tiles of block step r that the inner solves of step r + 1 read: next pair
 // k' = (B1, B2) reads T(B1, B2), which lies in the tile of the step-r pairs
-// holding B1 and B2.  critical_tile(k') gives that tile (a < b) and whether k'
-// is the one that updates it (two next pairs can share a tile; the smaller
-// one does it).  is_critical(a, b) tells the tiles the next pairs need.
-__device__ __forceinline__ bool critical_tile(const RR& rrb, int r, int kn, int& a, int& b) {
-  const int r1 = r + 1;
-  const int B1 = rrb.index(kn, r1), B2 = rrb.index(rrb.h + kn, r1);
-  const int a1 = block_pair_of(rrb, B1, r), b1 = block_pair_of(rrb, B2, r);
-  a = a1 < b1 ? a1 : b1;
-  b = a1 < b1 ? b1 : a1;
-  // the other block of B1's step-r pair, and the next pair it goes to
-  const int A2 = rrb.index(a1, r) == B1 ? rrb.index(rrb.h + a1, r) : rrb.index(a1, r);
-  const int k2 = block_pair_of(rrb, A2, r1);
-  if (k2 == kn) return true;
-  const int C1 = rrb.index(k2, r1), C2 = rrb.index(rrb.h + k2, r1);
-  const int c1 = block_pair_of(rrb, C1, r), c2 = block_pair_of(rrb, C2, r);
-  const bool same = (c1 < c2 ? c1 : c2) == a && (c1 < c2 ? c2 : c1) == b;
-  return !same || kn < k2;
-}
-
+// holding B1 and B2 (two next pairs can share a tile).  is_critical(a, b)
+// tells those tiles.
 __device__ __forceinline__ bool is_critical(const RR& rrb, int r, int a, int b) {
   const int r1 = r + 1;
   const int blocks[2] = {rrb.index(a, r), rrb.index(rrb.h + a, r)};
@@ -608,70 +731,19 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
   }
 }
 
-// The same two updates by a whole 1024-thread workgroup: wave w computes the
-// 16 x 16 output block (w / 4, w % 4) of the 64 x 64 result, so each wave runs
-// 16 matrix-core steps per product and holds 16 E values per lane.
-constexpr int kWT = 1024;   // threads of the 16-wave update paths
-
+// Tile update by a 1024-thread workgroup: Y = W_k^T T(P_k, P_l) W_l written to
+// T(P_k, P_l) and mirrored into T(P_l, P_k).
 template <typename T>
 __device__ __forceinline__ void tile_update16(T* __restrict__ Tm, int ldt, const T* __restrict__ Eall, const RR& rrb,
                                               int r, int k, int l, T* __restrict__ Bs, bool active) {
   constexpr int b = kB2 / 2;
-  constexpr int kPer = kB2 * kB2 / kWT;   // 4
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int bi = wave >> 2, bj = wave & 3, cc = lane & 15, kq = lane >> 4;
+  constexpr int kPer = kB2 * kB2 / kWT;
+  const int tid = threadIdx.x;
   const int Ik = rrb.index(k, r) * b, Jk = rrb.index(rrb.h + k, r) * b - b;
   const int Il = rrb.index(l, r) * b, Jl = rrb.index(rrb.h + l, r) * b - b;
   auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };
   auto gl = [&](int a) { return a < b ? Il + a : Jl + a; };
-  const T* Ek = Eall + (size_t)k * kB2 * kB2;
-  const T* El = Eall + (size_t)l * kB2 * kB2;
-  typename Mfma<T>::acc_t acc;
-  T fa[kB2 / 4], fb[kB2 / 4];
-  if (active) {
-    T tv[kPer];
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kWT, kk = e % kB2, c = e / kB2;
-      tv[q] = Tm[gk(kk) + (size_t)gl(c) * ldt];
-    }
-#pragma unroll
-    for (int q = 0; q < kB2 / 4; ++q) fa[q] = Ek[(q * 4 + kq) * kB2 + bi * 16 + cc];   // A(i, kk) = E_k(kk, i)
-#pragma unroll
-    for (int q = 0; q < kB2 / 4; ++q) fb[q] = El[(q * 4 + kq) * kB2 + bj * 16 + cc];   // B(kk, j) = E_l(kk, j)
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kWT, kk = e % kB2, c = e / kB2;
-      Bs[kk * kLD + c] = tv[q];   // B(kk, j = c) = T(P_k[kk], P_l[c])
-    }
-  }
-  __syncthreads();
-  if (active) {
-    acc = typename Mfma<T>::acc_t{0, 0, 0, 0};
-#pragma unroll
-    for (int q = 0; q < kB2 / 4; ++q) acc = Mfma<T>::op(fa[q], Bs[(q * 4 + kq) * kLD + bj * 16 + cc], acc);
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) acc[rr] += Bs[(bi * 16 + Mfma<T>::row(lane, rr)) * kLD + bj * 16 + cc];   // + T
-  }
-  __syncthreads();
-  if (active) {
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) Bs[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)] = acc[rr];   // X, k-major
-  }
-  __syncthreads();
-  if (active) {
-    acc = typename Mfma<T>::acc_t{0, 0, 0, 0};
-#pragma unroll
-    for (int q = 0; q < kB2 / 4; ++q) acc = Mfma<T>::op(Bs[(q * 4 + kq) * kLD + bi * 16 + cc], fb[q], acc);
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) acc[rr] += Bs[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)];   // + X
-  }
-  __syncthreads();
-  if (active) {
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) Bs[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)] = acc[rr];   // Y
-  }
-  __syncthreads();
+  tile_product16<T>(Tm, ldt, Eall + (size_t)k * kB2 * kB2, Eall + (size_t)l * kB2 * kB2, Ik, Jk, Il, Jl, Bs, active);
   if (active) {
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
@@ -686,6 +758,7 @@ __device__ __forceinline__ void tile_update16(T* __restrict__ Tm, int ldt, const
   }
 }
 
+// V chunk update by a 1024-thread workgroup (see tile_product16 for the wave layout).
 template <typename T>
 __device__ __forceinline__ void vchunk_update16(T* __restrict__ V, int ldv, int nvr, const T* __restrict__ Ek, int Ik,
                                                 int Jk, int row0, T* __restrict__ Bs, bool active) {
@@ -736,13 +809,12 @@ __device__ __forceinline__ void vchunk_update16(T* __restrict__ V, int ldv, int 
   }
 }
 
-// Update of one block step of the single-matrix path by 1024-thread
-// workgroups: mode 0 every tile then the V chunks (workgroups ntile ..),
-// mode 1 the tiles the next step's inner solves read (workgroup = next pair).
+// Update of one whole block step of the single-matrix path by 1024-thread
+// workgroups: every tile, then the V chunks (workgroups ntile ..).
 template <typename T>
 __global__ void __launch_bounds__(kWT)
 blk_update16_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int nvr, const T* __restrict__ Eall,
-                    const int* __restrict__ ident, int m2, int r, int ntile, int nvchunk, int critical,
+                    const int* __restrict__ ident, int m2, int r, int ntile, int nvchunk,
                     unsigned long long* __restrict__ work) {
   constexpr int b = kB2 / 2;
   __shared__ T Bs[kB2 * kLD];
@@ -750,11 +822,7 @@ blk_update16_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int
   const int w = blockIdx.x;
   if (w < ntile) {
     int k, l;
-    if (critical) {
-      if (!critical_tile(rrb, r, w, k, l)) return;
-    } else {
-      stri_decode(w, k, l);
-    }
+    stri_decode(w, k, l);
     if (ident[k] && ident[l]) return;
     if (work && threadIdx.x == 0) atomicAdd(work, 1ull << 32);
     tile_update16<T>(Tm, ldt, Eall, rrb, r, k, l, Bs, true);
@@ -768,13 +836,14 @@ blk_update16_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int
 }
 
 // Inner solves of block step r (workgroups 0 .. npair-1) together with the
-// rest of the update of block step rv = r - 1 (the other workgroups, one tile
-// or 64-row chunk at a time, by all 16 waves): the V chunks and, with
-// merge_tiles, the T tiles the inner solves of step r do not read (the ones
-// they read were updated before this launch).  Those need only E of step rv and touch no entry
-// the inner solves touch, so they run on the CUs the inner solves leave idle
-// instead of after them.  E and the identity flags alternate between two
-// buffers by step parity (Eall/ident for step r, Ev/identv for step rv).
+// update of block step rv = r - 1 (the other workgroups, one tile or 64-row
+// chunk at a time, by all 16 waves): the V chunks and, with merge_tiles, the
+// T tiles the inner solves of step r do not read.  The tiles they do read are
+// computed by the inner workgroups themselves (inner_solve with Ev), so the
+// whole update of step rv runs inside this launch, the helpers on the CUs the
+// inner solves leave idle.  Helper items touch no entry an inner solve
+// touches.  E and the identity flags alternate between two buffers by step
+// parity (Eall/ident for step r, Ev/identv for step rv).
 template <typename T>
 constexpr size_t inner_v_lds_bytes() {
   return inner_lds_bytes<T>() > kB2 * kLD * sizeof(T) ? inner_lds_bytes<T>() : kB2 * kLD * sizeof(T);
@@ -785,11 +854,11 @@ __global__ void __launch_bounds__(kInnerThreads)
 blk_inner_v_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restrict__ Eall, int* __restrict__ ident,
                    T skip_abs, int max_inner, unsigned long long* __restrict__ rot, int npair, T* __restrict__ V,
                    int ldv, int nvr, const T* __restrict__ Ev, const int* __restrict__ identv, int nvchunk,
-                   unsigned long long* __restrict__ work, int merge_tiles) {
+                   unsigned long long* __restrict__ work, int* __restrict__ tcount) {
   __shared__ __attribute__((aligned(16))) char smem[inner_v_lds_bytes<T>()];
   if ((int)blockIdx.x < npair) {
     inner_solve<T, BIP>(blockIdx.x, Tm, ldt, n, m2, r, Eall, ident, skip_abs, max_inner, rot, (const T*)nullptr, 0,
-                        npair, T(0), smem);
+                        npair, T(0), smem, Ev, identv, tcount, work);
     return;
   }
   constexpr int b = kB2 / 2;
@@ -798,9 +867,9 @@ blk_inner_v_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restr
   const int rv = r - 1;
   const RR rrb(m2);
   T* Bs = reinterpret_cast<T*>(smem);
-  // The tiles of step rv that the inner solves of step r do not read (the others were updated
-  // before this launch).  Every thread of a workgroup runs the same iterations (barriers).
-  const int ntile = merge_tiles ? npair * (npair - 1) / 2 : 0;
+  // The tiles of step rv that the inner solves of step r do not read (the inner workgroups
+  // compute the others).  Every thread of a workgroup runs the same iterations (barriers).
+  const int ntile = npair * (npair - 1) / 2;
   const int per_t = (ntile + vwg - 1) / vwg;
   for (int it = 0; it < per_t; ++it) {
     const int ti = wq + it * vwg;
@@ -1056,15 +1125,12 @@ int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s) {
   Prof* pf = st.prof;
   unsigned long long* work_u = pf && pf->on ? pf->work + st.cls_update : nullptr;
   unsigned long long* work_i = pf && pf->on ? pf->work + st.cls_inner : nullptr;
-  // The helper workgroups of the merged launches also take the T tiles the next inner solves do
-  // not read, so only those few tiles stay on the critical path.
-  // In FP64 the helpers have no room left for them (the V chunks alone keep them busy for about
-  // as long as the inner solves take), so all FP64 tiles are updated after the inner launch.
-  constexpr bool kMergeTiles = sizeof(T) == 4;
+  // The whole update of block step r runs inside the launch of step r + 1: the tiles its inner
+  // solves read by those inner workgroups, the other tiles and the V chunks by the helpers.  The
+  // last step of a sweep is updated in full by a launch of its own.
   int e_prev = pf ? pf->mark(s) : -1;
   for (int r = 0; r < m2 - 1; ++r) {
     const int par = r & 1;
-    const bool last = r == m2 - 2;
     if (r == 0)
       hipLaunchKernelGGL((blk_inner_kernel<T, false>), dim3(m), dim3(kInnerThreads), 0, s, st.Tm, st.ldt, st.n, m2, r,
                          Eb[par], Ib[par], st.skip_abs, max_inner, st.rot, (const T*)nullptr, 0, m, T(0),
@@ -1072,34 +1138,18 @@ int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s) {
     else
       hipLaunchKernelGGL((blk_inner_v_kernel<T, true>), dim3(m + vwg), dim3(kInnerThreads), 0, s, st.Tm, st.ldt, st.n,
                          m2, r, Eb[par], Ib[par], st.skip_abs, max_inner, st.rot, m, st.V, st.ldv, st.nvr,
-                         (const T*)Eb[par ^ 1], (const int*)Ib[par ^ 1], nvchunk, work_i, (int)kMergeTiles);
+                         (const T*)Eb[par ^ 1], (const int*)Ib[par ^ 1], nvchunk, work_i, st.tcount);
     JAC_CHECK_LAUNCH();
-    int e_mid = pf ? pf->mark(s) : -1;
+    const int e_mid = pf ? pf->mark(s) : -1;
     if (pf) pf->interval(st.cls_inner, e_prev, e_mid);
-    if (!last && !kMergeTiles) {
-      if (ntile > 0)
-        hipLaunchKernelGGL((blk_update_kernel<T>), dim3(ntile), dim3(kNT), 0, s, st.Tm, st.ldt, st.V, st.ldv, st.nvr,
-                           (const T*)Eb[par], (const int*)Ib[par], m2, r, ntile, nvchunk, work_u,
-                           (const BDesc<T>*)nullptr);
-    } else if (!last) {
-      // the tiles the next step's inner solves read; the rest go with the next merged launch
-      if (m > 1)
-        hipLaunchKernelGGL((blk_update16_kernel<T>), dim3(m), dim3(kWT), 0, s, st.Tm, st.ldt, st.V, st.ldv, st.nvr,
-                           Eb[par], Ib[par], m2, r, m, nvchunk, 1, work_u);
-    } else if (kMergeTiles) {
-      // last step of the sweep: every tile and the V chunks
-      hipLaunchKernelGGL((blk_update16_kernel<T>), dim3(ntile + m * nvchunk), dim3(kWT), 0, s, st.Tm, st.ldt, st.V,
-                         st.ldv, st.nvr, Eb[par], Ib[par], m2, r, ntile, nvchunk, 0, work_u);
-    } else {
-      hipLaunchKernelGGL((blk_update_kernel<T>), dim3(ntile + m * nvchunk), dim3(kNT), 0, s, st.Tm, st.ldt, st.V,
-                         st.ldv, st.nvr, (const T*)Eb[par], (const int*)Ib[par], m2, r, ntile, nvchunk, work_u,
-                         (const BDesc<T>*)nullptr);
-    }
-    JAC_CHECK_LAUNCH();
-    int e_end = pf ? pf->mark(s) : -1;
-    if (pf) pf->interval(st.cls_update, e_mid, e_end);
-    e_prev = e_end;
+    e_prev = e_mid;
   }
+  const int rl = m2 - 2;
+  hipLaunchKernelGGL((blk_update16_kernel<T>), dim3(ntile + m * nvchunk), dim3(kWT), 0, s, st.Tm, st.ldt, st.V, st.ldv,
+                     st.nvr, Eb[rl & 1], Ib[rl & 1], m2, rl, ntile, nvchunk, work_u);
+  JAC_CHECK_LAUNCH();
+  const int e_end = pf ? pf->mark(s) : -1;
+  if (pf) pf->interval(st.cls_update, e_prev, e_end);
   return 0;
 }
 

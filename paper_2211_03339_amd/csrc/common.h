@@ -281,6 +281,7 @@ struct BlkState {
   int ldv, nvr;
   T* W;                 // 2 x (np / blk_b2()) accumulated 2b x 2b rotations (E = W - I), by step parity
   int* ident;           // 2 x (np / blk_b2()) flags: W is exactly I
+  int* tcount;          // per-tile reader counters of the merged launches (m (m - 1) / 2, >= 1; zero between launches)
   T skip_abs;
   double* partial;      // >= 1024
   double* scalars;      // [0] off^2
