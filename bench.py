@@ -5,8 +5,8 @@ round-robin Jacobi sweeps) of each of three n = 2048 matrices A = Q diag(lambda)
 with lambda ~ U[-1,1], a signed geometric spectrum 10^(-8 i/(n-1)), and ten clusters of width
 1e-6.  Inputs are resident in device memory before the timed region.  Printed beside it: plain
 FP64 Jacobi on the same matrices, sweep counts, residuals, the dominant kernel's roofline figure
-(HIP events around every launch, in one more untimed pass), the learned start at n = 256 (the
-size where the network is feasible) and the CPU oracle timed on a bounded sample.
+(HIP events around each run of one class's launches, in one more untimed pass), the learned start
+at n = 256 (the size where the network is feasible) and the CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 2048] [--variant auto]
 """
@@ -33,10 +33,11 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def step_bytes(n: int, dtype_bytes: int) -> float:
-    """Algorithmic bytes of one element-wise parallel step: the symmetric T read and written
-    once (n(n+1)/2 entries each way) and V read and written once."""
-    return dtype_bytes * (n * (n + 1) + 2 * n * n)
+def elem_bytes(n: int, dtype_bytes: int, steps: int, rotations: int) -> float:
+    """Algorithmic bytes of `steps` element-wise steps that applied `rotations` rotations: T is
+    read and written in full every step; V moves only the two columns of an applied rotation
+    (read and written: 4 n entries)."""
+    return dtype_bytes * (steps * n * (n + 1) + rotations * 4 * n)
 
 
 KERNEL_OF = {"inner64": ("blk_inner_kernel<double", "blk_inner_v_kernel<double"),
@@ -53,9 +54,9 @@ def measured_traffic(cls: str):
     import hashlib
     try:
         t = json.load(open(TRAFFIC_FILE))
-        src = os.path.join(ROOT, t["source"])
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() != t["source_sha256"]:
-            return None
+        for src, digest in t["sources"].items():
+            if hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != digest:
+                return None
         sel = [v for k, v in t["kernels"].items() if any(p in k for p in KERNEL_OF.get(cls, ()))]
         calls = sum(v["dispatches"] for v in sel)
         if not calls:
@@ -66,10 +67,10 @@ def measured_traffic(cls: str):
 
 
 def roofline_for(cls: str, k: dict, n: int, rotations: int) -> dict:
-    """Roofline figure of one kernel class from its HIP-event launch times.
+    """Roofline figure of one kernel class from its HIP-event launch times (runs of launches).
     update*: algorithmic flops of the block rotations actually applied: each (2b)x(2b) tile
     W_k^T T W_l costs 2 * 2(2b)^3, each 2b-row chunk of V W_k costs 2(2b)^3.
-    elem*: algorithmic bytes of a parallel step (step_bytes).
+    elem*: algorithmic bytes of the steps (elem_bytes: T in full, V for the applied rotations).
     inner*: rotation flops (each rotation of a 2b x 2b subproblem updates two rows and two
     columns of S and two columns of E: about 12 * 2b flops) on the vector units, plus the V
     chunks (2 (2b)^3 flop each) the same launches update for the previous block step."""
@@ -86,7 +87,7 @@ def roofline_for(cls: str, k: dict, n: int, rotations: int) -> dict:
                 "launches_timed": k["launches"]}
     if cls.startswith("elem"):
         db = 8 if cls.endswith("64") else 4
-        bpl = step_bytes(n, db)
+        bpl = elem_bytes(n, db, launches, rotations) / launches
         ach = bpl / avg_s / 1e9
         return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(cls), "kernel": f"elem_step_kernel<{cls[-2:]}>",
@@ -177,8 +178,9 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s")
-    # Per-kernel-class launch times come from one more, untimed pass with a HIP event around every
-    # launch (the events themselves cost time, so they stay out of the timed region).
+    # Per-kernel-class launch times come from one more, untimed pass with HIP events around each run
+    # of consecutive launches of one class (a sweep's inner launches, its final update, an element
+    # sweep's steps), divided by the run's launch count; the events stay out of the timed region.
     kern = {}
     rot = {"64": 0, "32": 0}
     prof_ms = 0.0
@@ -247,7 +249,8 @@ def main():
         torch.cuda.synchronize()
         ed = est.as_dict()
         elem = {"ms_total": round(ed["stage_ms"]["total"], 3), "sweeps": ed["sweeps"], "fp32_sweeps": ed["fp32_sweeps"],
-                "rooflines": {c: roofline_for(c, v, n, 0) for c, v in ed["kernels"].items() if c.startswith("elem")}}
+                "rooflines": {c: roofline_for(c, v, n, ed["rotations"] if c == "elem64" else ed["fp32_rotations"])
+                              for c, v in ed["kernels"].items() if c.startswith("elem")}}
         log(f"[bench] element variant: {json.dumps(elem)}")
 
     mlp_row = None

@@ -82,8 +82,11 @@ typedef struct jac_stats {
   /* With opts.profile: per kernel class, summed HIP-event time, launch count and
    * work done.  Classes: 0 FP64 inner solve, 1 FP64 block update, 2 FP32 inner
    * solve, 3 FP32 block update, 4 FP64 element step, 5 FP32 element step.
-   * The inner-solve launches of block steps after the first also carry the V
-   * update (and in FP32 part of the T update) of the previous step.
+   * Events bracket each run of consecutive launches of one class (the inner
+   * launches of a block sweep, the steps of an element sweep), not each launch.
+   * The inner-solve launches of block steps after the first also carry the
+   * whole update (T tiles and V chunks) of the previous step; the block update
+   * class is the full update of a sweep's last step.
    * kern_work of the inner and update classes: 64x64 T tiles (high 32 bits)
    * and 64-row V chunks (low 32 bits) updated in those launches; element
    * classes: steps. */

@@ -71,7 +71,7 @@ int Prof::flush() {
     float t = 0;
     if (hipEventElapsedTime(&t, ev[iv.e0], ev[iv.e1]) == hipSuccess) {
       ms[iv.cls] += t;
-      launches[iv.cls] += 1;
+      launches[iv.cls] += iv.count;
     }
   }
   ivs.clear();

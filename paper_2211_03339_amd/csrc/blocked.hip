@@ -1128,7 +1128,7 @@ int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s) {
   // The whole update of block step r runs inside the launch of step r + 1: the tiles its inner
   // solves read by those inner workgroups, the other tiles and the V chunks by the helpers.  The
   // last step of a sweep is updated in full by a launch of its own.
-  int e_prev = pf ? pf->mark(s) : -1;
+  const int e0 = pf ? pf->mark(s) : -1;
   for (int r = 0; r < m2 - 1; ++r) {
     const int par = r & 1;
     if (r == 0)
@@ -1140,16 +1140,15 @@ int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s) {
                          m2, r, Eb[par], Ib[par], st.skip_abs, max_inner, st.rot, m, st.V, st.ldv, st.nvr,
                          (const T*)Eb[par ^ 1], (const int*)Ib[par ^ 1], nvchunk, work_i, st.tcount);
     JAC_CHECK_LAUNCH();
-    const int e_mid = pf ? pf->mark(s) : -1;
-    if (pf) pf->interval(st.cls_inner, e_prev, e_mid);
-    e_prev = e_mid;
   }
+  const int e_mid = pf ? pf->mark(s) : -1;
+  if (pf) pf->interval(st.cls_inner, e0, e_mid, m2 - 1);
   const int rl = m2 - 2;
   hipLaunchKernelGGL((blk_update16_kernel<T>), dim3(ntile + m * nvchunk), dim3(kWT), 0, s, st.Tm, st.ldt, st.V, st.ldv,
                      st.nvr, Eb[rl & 1], Ib[rl & 1], m2, rl, ntile, nvchunk, work_u);
   JAC_CHECK_LAUNCH();
   const int e_end = pf ? pf->mark(s) : -1;
-  if (pf) pf->interval(st.cls_update, e_prev, e_end);
+  if (pf) pf->interval(st.cls_update, e_mid, e_end);
   return 0;
 }
 

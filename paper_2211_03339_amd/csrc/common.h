@@ -29,20 +29,23 @@ const char* last_error();
 #define JAC_CHECK_LAUNCH() JAC_HIP(hipGetLastError())
 
 // ---------------------------------------------------------------- profiling
-// Optional per-launch timing with HIP events recorded in the stream between
-// consecutive launches (classes as in jac_stats.kern_*).
+// Optional kernel timing with HIP events recorded in the stream around runs of
+// consecutive launches of one class (classes as in jac_stats.kern_*).  An
+// event between every two launches would add its own cost to each launch, so
+// a run of launches is timed as a whole and divided by its count.
 struct Prof {
   bool on = false;
   std::vector<hipEvent_t> ev;
   int used = 0;
-  struct Iv { int cls, e0, e1; };
+  struct Iv { int cls, e0, e1, count; };
   std::vector<Iv> ivs;
   double ms[6] = {0, 0, 0, 0, 0, 0};
   long long launches[6] = {0, 0, 0, 0, 0, 0};
   unsigned long long* work = nullptr;   // device counters [6]
   int mark(hipStream_t s);              // record an event, return its id (-1 if off)
-  void interval(int cls, int e0, int e1) {
-    if (on && e0 >= 0 && e1 >= 0) ivs.push_back({cls, e0, e1});
+  // count launches of class cls ran back to back between events e0 and e1
+  void interval(int cls, int e0, int e1, int count = 1) {
+    if (on && e0 >= 0 && e1 >= 0) ivs.push_back({cls, e0, e1, count});
   }
   int flush();                          // after the stream is synchronised
   ~Prof();

@@ -3,11 +3,11 @@
   python -m paper_2211_03339_amd.profsum stats KERNEL_STATS_CSV OUT_TXT "COMMAND"
       per-kernel calls / total / average / min / max duration from `rocprofv3 --kernel-trace --stats`.
   python -m paper_2211_03339_amd.profsum traffic FETCH_CSV WRITE_CSV COPY_FETCH_CSV COPY_WRITE_CSV COPY_BYTES
-      OUT_JSON SOURCE "COMMANDS"
+      OUT_JSON SOURCES "COMMANDS"
       mean FETCH_SIZE / WRITE_SIZE per dispatch and kernel from two `rocprofv3 --pmc` runs, each
       scaled by bytes / counter of a plain device copy of COPY_BYTES bytes measured with the same
-      counter, with the sha256 of the kernel source SOURCE (bench.py reports the traffic only
-      while the source is unchanged).
+      counter, with the sha256 of each kernel source in SOURCES (comma-separated; bench.py reports
+      the traffic only while they are unchanged).
 """
 from __future__ import annotations
 
@@ -52,7 +52,7 @@ def _per_kernel(path, counter):
     return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
 
 
-def traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv, copy_bytes, out_json, source, command):
+def traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv, copy_bytes, out_json, sources, command):
     fetch, nf = _per_kernel(fetch_csv, "FETCH_SIZE")
     write, nw = _per_kernel(write_csv, "WRITE_SIZE")
     cf, _ = _per_kernel(cfetch_csv, "FETCH_SIZE")
@@ -61,7 +61,7 @@ def traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv, copy_bytes, out_json, 
     ck = max(cf, key=cf.get)
     sf = float(copy_bytes) / (cf[ck] * 1024.0)
     sw = float(copy_bytes) / (cw[max(cw, key=cw.get)] * 1024.0)
-    out = {"source": source, "source_sha256": hashlib.sha256(open(source, "rb").read()).hexdigest(),
+    out = {"sources": {src: hashlib.sha256(open(src, "rb").read()).hexdigest() for src in sources.split(",")},
            "command": command, "copy_kernel": ck, "copy_bytes": int(copy_bytes),
            "scale_fetch": sf, "scale_write": sw, "kernels": {}}
     for k in sorted(set(fetch) | set(write)):
