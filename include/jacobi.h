@@ -53,7 +53,8 @@ typedef struct jac_opts {
   int variant;         /* jac_variant_t */
   int block_b;         /* block size b of the blocked variant; 0 = library choice */
   int max_sweeps;      /* FP64 sweeps; <= 0 means 64 */
-  double fp32_tol;     /* FP32 stage stops at off(T32) <= fp32_tol ||A||_F; <= 0: default */
+  double fp32_tol;     /* FP32 stage stops at off(T32) <= fp32_tol ||A||_F; <= 0: default
+                          (1e-4 for syev_jacobi_ex, 1e-6 for the Gram matrix of gesvd_jacobi_ex) */
   int fp32_max_sweeps; /* <= 0 means 30 */
   const struct jac_mlp* mlp;  /* JAC_PRECOND_MLP: the network */
   const float* theta;  /* JAC_PRECOND_MLP: device pointer to its input */

@@ -287,8 +287,8 @@ def test_preconditioned_n256(kind):
     plain = jacobi.syev_jacobi_ex(dev(A), tol=1e-15, precond="none", variant="element")[2]
     assert st["sweeps"] < plain["sweeps"]
     # Theorem evd-ubd with the Section 6 proxy bd = n ||A||_2 upsilon, plus the FP32 stage's own
-    # stopping tolerance (default 1e-6 ||A||_F), which dominates off(T0) when it is the larger
-    bd = n * np.abs(lam).max() * 2.0 ** -24 + 1e-6 * np.linalg.norm(A)
+    # stopping tolerance (default 1e-4 ||A||_F), which dominates off(T0) when it is the larger
+    bd = n * np.abs(lam).max() * 2.0 ** -24 + 1e-4 * np.linalg.norm(A)
     assert st["off0"] <= 2 * bd
 
 
