@@ -334,6 +334,30 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
     bl = l;
     bk = e - l * (l + 1) / 2;
   }
+  // E items of work lane t = tid - 64 (fixed for all steps): rows er[0..ne-1], pair pe; every
+  // 32-lane group shares its rows and holds pairs 0..31.
+  int er[3] = {0, 0, 0}, ne = 0;
+  const int pe = (tid - 64) & (kH - 1);
+  if (tid >= 64) {
+    const int t = tid - 64;
+    if (t < kBlockLanes) {
+      er[0] = t >> 5;
+      er[1] = (kBlockLanes + t) >> 5;
+      ne = 2;
+    } else {
+      const int t2 = kEPairLo + (t - kBlockLanes);
+      const int stride = kWorkLanes - kBlockLanes;
+      er[0] = t2 >> 5;
+      er[1] = (t2 + stride) >> 5;
+      er[2] = (t2 + 2 * stride) >> 5;
+      ne = t2 + 2 * stride < kEItems ? 3 : 2;
+    }
+  }
+  // Bipartite schedule: the lane keeps its E entries in registers, ex = E(er, pe) and
+  // ey = E(er, kH + ((pe + ri) mod kH)).  Step ri + 1 pairs pe with the column the lane of pair
+  // pe + 1 holds, so after each step ey moves one lane down inside the 32-lane group.
+  T ex[3] = {T(0), T(0), T(0)}, ey[3] = {T(0), T(0), T(0)};
+  const int ey_src = (lane & 32) | ((lane + 1) & 31);
   unsigned long long cnt = 0;
   int cur = 0;
   for (int sw = 0; sw < max_inner; ++sw) {
@@ -373,7 +397,6 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
         // Loads of all the lane's items first (S and E accesses share one array
         // each, so the compiler would otherwise keep every load behind the
         // previous item's stores), then the arithmetic, then the stores.
-        const int t = tid - 64;
         const bool has_blk = bk >= 0;
         int pk = 0, qk = 0, pl = 0, ql = 0;
         T tt = T(0), tb = T(0), bt = T(0), bb = T(0);
@@ -388,33 +411,18 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
           bt = Sc[qk * kLD + pl];
           bb = Sc[qk * kLD + ql];
         }
-        // E items of this lane: rows er[0..ne-1], pair pe.
-        int er[3], ne;
-        if (t < kBlockLanes) {
-          er[0] = t >> 5;
-          er[1] = (kBlockLanes + t) >> 5;
-          er[2] = 0;
-          ne = 2;
-        } else {
-          const int t2 = kEPairLo + (t - kBlockLanes);
-          const int stride = kWorkLanes - kBlockLanes;
-          er[0] = t2 >> 5;
-          er[1] = (t2 + stride) >> 5;
-          er[2] = (t2 + 2 * stride) >> 5;
-          ne = t2 + 2 * stride < kEItems ? 3 : 2;
-        }
-        const int pe = t & (kH - 1);
         const Ang<T> ae = ac[pe];
         int pp, qp;
         pair_at(pe, ri, pp, qp);
         const bool rot_e = ae.applied != T(0);
-        T ex[3], ey[3];
-        if (rot_e) {
+        if constexpr (!BIP) {
+          if (rot_e) {
 #pragma unroll
-          for (int q = 0; q < 3; ++q) {
-            if (q < ne) {
-              ex[q] = E[er[q] * kLD + pp];
-              ey[q] = E[er[q] * kLD + qp];
+            for (int q = 0; q < 3; ++q) {
+              if (q < ne) {
+                ex[q] = E[er[q] * kLD + pp];
+                ey[q] = E[er[q] * kLD + qp];
+              }
             }
           }
         }
@@ -450,10 +458,18 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
               const T dt = a == pp ? T(1) : T(0), db = a == qp ? T(1) : T(0);
               const T px = fmaT(ae.tau, x, y) + fmaT(ae.tau, dt, db);
               const T py = fmaT(-ae.tau, y, x) + fmaT(-ae.tau, db, dt);
-              E[a * kLD + pp] = fmaT(-ae.s, px, x);
-              E[a * kLD + qp] = fmaT(ae.s, py, y);
+              ex[q] = fmaT(-ae.s, px, x);
+              ey[q] = fmaT(ae.s, py, y);
+              if constexpr (!BIP) {
+                E[a * kLD + pp] = ex[q];
+                E[a * kLD + qp] = ey[q];
+              }
             }
           }
+        }
+        if constexpr (BIP) {
+#pragma unroll
+          for (int q = 0; q < 3; ++q) ey[q] = __shfl(ey[q], ey_src, 64);
         }
       }
       __syncthreads();
@@ -466,11 +482,24 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
       Tm[gidx(a) + (size_t)gidx(c) * ldt] = S[cur][a * kLD + c];
     }
   }
-  // E_k row-major: Eall[k][a * 2b + c] = E(a, c).
+  // E_k row-major: Eall[k][a * 2b + c] = E(a, c).  (Bipartite: after whole inner sweeps ey is
+  // back at column kH + pe.)
   T* Ek = Eall + (size_t)k * kB2 * kB2;
-  for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
-    const int c = e % kB2, a = e / kB2;
-    Ek[a * kB2 + c] = E[a * kLD + c];
+  if constexpr (BIP) {
+    if (tid >= 64) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        if (q < ne) {
+          Ek[er[q] * kB2 + pe] = ex[q];
+          Ek[er[q] * kB2 + kH + pe] = ey[q];
+        }
+      }
+    }
+  } else {
+    for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
+      const int c = e % kB2, a = e / kB2;
+      Ek[a * kB2 + c] = E[a * kLD + c];
+    }
   }
   if (tid == 0) {
     ident[k] = cnt == 0;
