@@ -5,14 +5,15 @@
 // even) is stored as the packed upper triangle of 2x2 "pair blocks" in
 // Brent-Luk slot order (see RR in common.h): block (k, l), k <= l, holds rows
 // (slot k, slot h+k) x columns (slot l, slot h+l), so every pair of the
-// current step is the diagonal block (k, k).  A step reads each stored block
-// once (32 B, coalesced), applies R_k^T B R_l (row pass with pair k, column
-// pass with pair l, tau form of the rotation; diagonal blocks use the t form of
-// Lemma offa-jr and get b_pq = 0), and scatters the four results to the slots
-// they occupy at the next step in the other ping-pong buffer.  Reads and
-// writes of T are therefore one pass over the stored triangle each, and the V
-// update (columns p, q of V in logical order, rotated in place) is one pass
-// over V: 8 n(n+1) + 16 n^2 bytes per step.
+// current step is the diagonal block (k, k).  A step applies R_k^T B R_l to
+// the old blocks (row pass with pair k, column pass with pair l, tau form of
+// the rotation; diagonal blocks use the t form of Lemma offa-jr and get
+// b_pq = 0) and writes every block of the next step (the other ping-pong
+// buffer) whole: each of its four entries is the rotated value of one old
+// entry, whose old block neighbouring threads read as well (from L2).  HBM
+// sees one pass over the stored triangle each way, and the V update (columns
+// p, q of V in logical order, rotated in place) is one pass over the rotated
+// columns: 8 n(n+1) + 32 n bytes per applied rotation per step.
 //
 // One launch per step.  Its grid has three roles: (1) pair-block updates of T,
 // (2) "band" threads that recompute the few rotated entries feeding each new
@@ -49,29 +50,9 @@ __device__ __forceinline__ void kl_from_g(long long g, int& k, int& l) {
   k = (int)(g - L * (L + 1) / 2);
 }
 
-// Store the new value of the element at (slot a, slot b) of the next step.
-template <typename T>
-__device__ __forceinline__ void put(T* base, int h, int a, int b, T v) {
-  int ka = a < h ? a : a - h, ra = a < h ? 0 : 1;
-  int kb = b < h ? b : b - h, rb = b < h ? 0 : 1;
-  if (ka == kb) {
-    long long o = bidx(ka, ka) * 4;
-    if (ra == rb) {
-      base[o + (ra ? 3 : 0)] = v;
-    } else {
-      base[o + 1] = v;
-      base[o + 2] = v;
-    }
-  } else if (ka < kb) {
-    base[bidx(ka, kb) * 4 + ra * 2 + rb] = v;
-  } else {
-    base[bidx(kb, ka) * 4 + rb * 2 + ra] = v;
-  }
-}
-
 // Rotated value (this step) of the element at old slots (a, b).
 template <typename T>
-__device__ T rotated_old(const Blk<T>* __restrict__ Told, const Ang<T>* __restrict__ ang, int h,
+__device__ __forceinline__ T rotated_old(const Blk<T>* __restrict__ Told, const Ang<T>* __restrict__ ang, int h,
                          int a, int b) {
   int ka = a < h ? a : a - h, ra = a < h ? 0 : 1;
   int kb = b < h ? b : b - h, rb = b < h ? 0 : 1;
@@ -89,12 +70,13 @@ __device__ T rotated_old(const Blk<T>* __restrict__ Told, const Ang<T>* __restri
 }
 
 constexpr int kThreads = 256;
+constexpr int kXcds = 8;   // accelerator complex dies of the MI355X (one L2 each)
 // Work per thread of the step kernel: pair blocks of T (bpt) and rows of the
 // two V columns (rpt, moved in 16-byte vectors of 2 FP64 / 4 FP32 rows).
-// Measured at n = 2048: FP64 4 / 8 and FP32 2 / 8 (more FP32 blocks per
-// thread slow its 4-byte scattered stores; fewer leave latency exposed).
+// Measured at n = 2048: FP64 1 / 8 and FP32 2 / 8 (each block gathers four
+// old blocks, so one or two per thread already keep enough loads in flight).
 template <typename T> struct ElemCfg;
-template <> struct ElemCfg<double> { static constexpr int bpt = 4, rpt = 8; };
+template <> struct ElemCfg<double> { static constexpr int bpt = 1, rpt = 8; };
 template <> struct ElemCfg<float> { static constexpr int bpt = 2, rpt = 8; };
 
 template <typename T> struct Vec16;
@@ -113,34 +95,27 @@ elem_step_kernel(const Blk<T>* __restrict__ Told, Blk<T>* __restrict__ Tnew,
   const int h = rr.h;
   const int wg = blockIdx.x;
   if (wg < nwgT) {
-    T* out = reinterpret_cast<T*>(Tnew);
-    const long long g0 = (long long)wg * kThreads * kBPT + threadIdx.x;
-    // all of the thread's loads first, then the rotations and scattered stores
-    Blk<T> bs[kBPT];
-#pragma unroll
-    for (int it = 0; it < kBPT; ++it)
-      if (g0 + it * kThreads < nblk) bs[it] = Told[g0 + it * kThreads];
+    // Gather: the thread owns stored blocks of the next step; each of a block's four entries is
+    // the rotated value of one old entry (slots srcslot(.)), read from its old block (which
+    // neighbouring threads read too, from L2) - so every block is written once, whole.
+    // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2: workgroup
+    // wg takes range (wg mod 8) * per + wg / 8, so that every XCD walks one contiguous part of
+    // the triangle and the neighbouring blocks it reads stay in its L2 (nwgT is a multiple of 8).
+    const int per = nwgT / kXcds;
+    const long long g0 = (long long)((wg % kXcds) * per + wg / kXcds) * kThreads * kBPT + threadIdx.x;
 #pragma unroll
     for (int it = 0; it < kBPT; ++it) {
       const long long g = g0 + it * kThreads;
       if (g >= nblk) break;
       int k, l;
       kl_from_g(g, k, l);
-      Blk<T> b = bs[it];
-      int nk = rr.newslot(k), nhk = rr.newslot(h + k);
-      if (k == l) {
-        rotate_diag(b, ang[k]);
-        put(out, h, nk, nk, b.tt);
-        put(out, h, nhk, nhk, b.bb);
-        put(out, h, nk, nhk, T(0));
-      } else {
-        rotate_block(b, ang[k], ang[l]);
-        int nl = rr.newslot(l), nhl = rr.newslot(h + l);
-        put(out, h, nk, nl, b.tt);
-        put(out, h, nk, nhl, b.tb);
-        put(out, h, nhk, nl, b.bt);
-        put(out, h, nhk, nhl, b.bb);
-      }
+      const int sk = rr.srcslot(k), shk = rr.srcslot(h + k), sl = rr.srcslot(l), shl = rr.srcslot(h + l);
+      Blk<T> b;
+      b.tt = rotated_old(Told, ang, h, sk, sl);
+      b.tb = rotated_old(Told, ang, h, sk, shl);
+      b.bt = k == l ? b.tb : rotated_old(Told, ang, h, shk, sl);
+      b.bb = rotated_old(Told, ang, h, shk, shl);
+      Tnew[g] = b;
     }
   } else if (wg < nwgT + nwgB) {
     int kp = (wg - nwgT) * kThreads + threadIdx.x;
@@ -362,7 +337,7 @@ int elem_init_angles(ElemState<T>& st, int r, hipStream_t s) {
 template <typename T>
 int elem_steps(ElemState<T>& st, long long gstep0, int nsteps, hipStream_t s) {
   const int per = st.ne - 1;
-  const int nwgT = cdiv(st.nblk, (long long)kThreads * ElemCfg<T>::bpt);
+  const int nwgT = cdiv(cdiv(st.nblk, (long long)kThreads * ElemCfg<T>::bpt), kXcds) * kXcds;
   const int nwgB = cdiv(st.h, kThreads);
   const int vchunks = cdiv(st.n, kThreads * ElemCfg<T>::rpt);
   const int nwg = nwgT + nwgB + st.h * vchunks;
