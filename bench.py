@@ -6,7 +6,8 @@ with lambda ~ U[-1,1], a signed geometric spectrum 10^(-8 i/(n-1)), and ten clus
 1e-6.  Inputs are resident in device memory before the timed region.  Printed beside it: plain
 FP64 Jacobi on the same matrices, sweep counts, residuals, the dominant kernel's roofline figure
 (HIP events around each run of one class's launches, in one more untimed pass), the learned start
-at n = 256 (the size where the network is feasible) and the CPU oracle timed on a bounded sample.
+at n = 256 (the size where the network is feasible), the batched path on 4096 matrices of sizes
+32..512 next to a per-matrix loop, and the CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 2048] [--variant auto]
 """
@@ -123,6 +124,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-Jacobi comparison")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-start row at n=256")
     ap.add_argument("--no-elem", action="store_true", help="skip the element-wise variant's step rooflines")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-path row (4096 matrices)")
     ap.add_argument("--mlp-train", type=int, default=8192, help="training solves for the learned-start row")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates the HBM byte counters)")
@@ -253,6 +255,11 @@ def main():
                               for c, v in ed["kernels"].items() if c.startswith("elem")}}
         log(f"[bench] element variant: {json.dumps(elem)}")
 
+    bat_row = None
+    if not args.no_batched:
+        bat_row = batched_row()
+        log(f"[bench] batched path: {json.dumps(bat_row)}")
+
     mlp_row = None
     if not args.no_mlp:
         mlp_row = learned_row(args.mlp_train)
@@ -283,7 +290,7 @@ def main():
                                   f"1e-8 / 10 clusters x 1e-6, one solve of each per step",
                       "n": n, "solves_per_step": len(mats), "variant": args.variant,
                       "tol": args.tol if args.tol > 0 else 20 * 2.0 ** -53},
-           "per_spectrum": per_spec, "plain": plain, "learned_n256": mlp_row, "element_variant": elem,
+           "per_spectrum": per_spec, "plain": plain, "learned_n256": mlp_row, "batched_4096": bat_row, "element_variant": elem,
            "roofline": roofline,
            "cpu_baseline": cpu,
            "kernels": kernels, "other_rooflines": others}
@@ -311,6 +318,80 @@ def learned_row(n_train: int, n_eval: int = 32, epochs: int = 8):
             "mean_sweeps": {m: ev[m]["mean_sweeps"] for m in ("mlp", "fp32", "plain", "mlp_forced")},
             "max_res": max(ev[m]["max_res"] for m in ("mlp", "fp32", "plain", "mlp_forced")),
             "learned_start": ev["learned_start"]}
+
+
+def batched_row(count: int = 4096, loop_sample: int = 256, reps: int = 3):
+    """The batched path on its own workload: `count` matrices A = Q diag(lambda) Q^T with sizes
+    32 * U{1..16} (seed 3), Haar Q, lambda ~ U[-1,1], solved by one replayed graph launch (after
+    the autotuner and a capturing first run), next to a per-matrix loop through the single-matrix
+    call on the first `loop_sample` matrices.  The inputs are built on the device (batched QR of
+    each size class, seeded) so that the bench does not spend minutes in host QRs."""
+    import torch
+    from paper_2211_03339_amd import jacobi
+    from paper_2211_03339_amd import testmats as tm
+    sizes = [int(x) for x in tm.batched_sizes(count, 3)]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3_000_003)
+    mats = [None] * count
+    lams = [None] * count
+    for nval in sorted(set(sizes)):
+        idx = [i for i, x in enumerate(sizes) if x == nval]
+        G = torch.randn((len(idx), nval, nval), dtype=torch.float64, device="cuda", generator=gen)
+        Q, R = torch.linalg.qr(G)
+        Q = Q * torch.sign(torch.diagonal(R, dim1=-2, dim2=-1)).unsqueeze(-2)
+        lam = torch.rand((len(idx), nval), dtype=torch.float64, device="cuda", generator=gen) * 2 - 1
+        A = torch.matmul(Q * lam.unsqueeze(-2), Q.transpose(-2, -1).contiguous())
+        A = 0.5 * (A + A.transpose(-2, -1).contiguous())
+        for j, i in enumerate(idx):
+            mats[i] = A[j].contiguous()
+            lams[i] = lam[j]
+        del G, Q, R, A
+    torch.cuda.synchronize()
+    b = jacobi.Batch(mats)
+    t0 = time.perf_counter()
+    b.autotune()
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    b.run()
+    torch.cuda.synchronize()
+    first_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.run()
+    torch.cuda.synchronize()
+    run_s = (time.perf_counter() - t0) / reps
+    W, V, sw, info = b.results()
+    # accuracy on every 16th matrix, against its known spectrum and by the defining properties
+    worst = {"res": 0.0, "orth": 0.0, "lam_err": 0.0}
+    for i in range(0, count, 16):
+        A, w, v = mats[i], W[i], V[i].contiguous()
+        nA = float(torch.linalg.norm(A))
+        worst["res"] = max(worst["res"], float(torch.linalg.norm(A @ v - v * w[None, :])) / nA)
+        eye = torch.eye(A.shape[0], dtype=torch.float64, device="cuda")
+        worst["orth"] = max(worst["orth"], float(torch.linalg.norm(v.t().contiguous() @ v - eye)))
+        lam_sorted = torch.sort(lams[i]).values
+        worst["lam_err"] = max(worst["lam_err"], float((w - lam_sorted).abs().max() / lam_sorted.abs().max()))
+    # the per-matrix loop on a sample
+    ns = min(loop_sample, count)
+    for i in range(2):   # warm the single-matrix path
+        jacobi.syev_jacobi_ex(mats[i], precond="none")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(ns):
+        jacobi.syev_jacobi_ex(mats[i], precond="none")
+    torch.cuda.synchronize()
+    loop_s = time.perf_counter() - t0
+    cube = sum(x ** 3 for x in sizes)
+    cube_s = sum(x ** 3 for x in sizes[:ns])
+    loop_proj = loop_s * cube / cube_s
+    return {"matrices": count, "sizes": "32*U{1..16}, seed 3", "mean_n": round(sum(sizes) / count, 1),
+            "autotune_s": round(tune_s, 3), "first_run_s": round(first_s, 3), "run_s": round(run_s, 4),
+            "matrices_per_s": round(count / run_s, 1), "unconverged": int((info != 0).sum()),
+            "mean_sweeps": round(float(sw.mean()), 2),
+            "loop_sample": ns, "loop_sample_s": round(loop_s, 4),
+            "loop_projected_s": round(loop_proj, 3), "speedup_vs_loop": round(loop_proj / run_s, 2),
+            "checked_every_16th": {k: float("%.3g" % v) for k, v in worst.items()}}
 
 
 def _cpu_model():
