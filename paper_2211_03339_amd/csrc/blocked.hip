@@ -149,25 +149,32 @@ __device__ __forceinline__ int block_pair_of(const RR& rrb, int B, int r) {
 // the workgroup reaches the same barriers, inactive ones skip the work.
 constexpr int kWT = 1024;   // threads of the 16-wave update paths
 
+constexpr int kPer16 = kB2 * kB2 / kWT;   // tile values per thread (4)
+
+// The thread's values of the tile T(P_k, P_l): tv[q] = T(P_k[e % 2b], P_l[e / 2b]), e = tid + q kWT.
 template <typename T>
-__device__ __forceinline__ void tile_product16(const T* __restrict__ Tm, int ldt, const T* __restrict__ Ek,
-                                               const T* __restrict__ El, int Ik, int Jk, int Il, int Jl,
-                                               T* __restrict__ Bs, bool active) {
+__device__ __forceinline__ void tile_vals16(const T* __restrict__ Tm, int ldt, int Ik, int Jk, int Il, int Jl,
+                                            T (&tv)[kPer16]) {
   constexpr int b = kB2 / 2;
-  constexpr int kPer = kB2 * kB2 / kWT;   // 4
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int bi = wave >> 2, bj = wave & 3, cc = lane & 15, kq = lane >> 4;
   auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };
   auto gl = [&](int a) { return a < b ? Il + a : Jl + a; };
+#pragma unroll
+  for (int q = 0; q < kPer16; ++q) {
+    const int e = threadIdx.x + q * kWT, kk = e % kB2, c = e / kB2;
+    tv[q] = Tm[gk(kk) + (size_t)gl(c) * ldt];
+  }
+}
+
+// The product of tile_product16 from the tile's values already in registers.
+template <typename T>
+__device__ __forceinline__ void tile_product16_vals(const T (&tv)[kPer16], const T* __restrict__ Ek,
+                                                    const T* __restrict__ El, T* __restrict__ Bs, bool active) {
+  constexpr int kPer = kPer16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bi = wave >> 2, bj = wave & 3, cc = lane & 15, kq = lane >> 4;
   typename Mfma<T>::acc_t acc;
   T fa[kB2 / 4], fb[kB2 / 4];
   if (active) {
-    T tv[kPer];
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kWT, kk = e % kB2, c = e / kB2;
-      tv[q] = Tm[gk(kk) + (size_t)gl(c) * ldt];
-    }
 #pragma unroll
     for (int q = 0; q < kB2 / 4; ++q) fa[q] = Ek[(q * 4 + kq) * kB2 + bi * 16 + cc];   // A(i, kk) = E_k(kk, i)
 #pragma unroll
@@ -205,6 +212,15 @@ __device__ __forceinline__ void tile_product16(const T* __restrict__ Tm, int ldt
     for (int rr = 0; rr < 4; ++rr) Bs[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)] = acc[rr];   // Y
   }
   __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_product16(const T* __restrict__ Tm, int ldt, const T* __restrict__ Ek,
+                                               const T* __restrict__ El, int Ik, int Jk, int Il, int Jl,
+                                               T* __restrict__ Bs, bool active) {
+  T tv[kPer16];
+  if (active) tile_vals16<T>(Tm, ldt, Ik, Jk, Il, Jl, tv);
+  tile_product16_vals<T>(tv, Ek, El, Bs, active);
 }
 
 template <typename T>
@@ -760,56 +776,76 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
   }
 }
 
-// Tile update by a 1024-thread workgroup: Y = W_k^T T(P_k, P_l) W_l written to
-// T(P_k, P_l) and mirrored into T(P_l, P_k).
+// Y (in Bs after tile_product16) written to T(P_k, P_l) and mirrored into T(P_l, P_k).
 template <typename T>
-__device__ __forceinline__ void tile_update16(T* __restrict__ Tm, int ldt, const T* __restrict__ Eall, const RR& rrb,
-                                              int r, int k, int l, T* __restrict__ Bs, bool active) {
+__device__ __forceinline__ void tile_store16(T* __restrict__ Tm, int ldt, int Ik, int Jk, int Il, int Jl,
+                                             const T* __restrict__ Bs, bool active) {
   constexpr int b = kB2 / 2;
-  constexpr int kPer = kB2 * kB2 / kWT;
   const int tid = threadIdx.x;
-  const int Ik = rrb.index(k, r) * b, Jk = rrb.index(rrb.h + k, r) * b - b;
-  const int Il = rrb.index(l, r) * b, Jl = rrb.index(rrb.h + l, r) * b - b;
   auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };
   auto gl = [&](int a) { return a < b ? Il + a : Jl + a; };
-  tile_product16<T>(Tm, ldt, Eall + (size_t)k * kB2 * kB2, Eall + (size_t)l * kB2 * kB2, Ik, Jk, Il, Jl, Bs, active);
   if (active) {
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
+    for (int q = 0; q < kPer16; ++q) {
       const int e = tid + q * kWT, i = e % kB2, j = e / kB2;
       Tm[gk(i) + (size_t)gl(j) * ldt] = Bs[j * kLD + i];
     }
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
+    for (int q = 0; q < kPer16; ++q) {
       const int e = tid + q * kWT, j = e % kB2, i = e / kB2;
       Tm[gl(j) + (size_t)gk(i) * ldt] = Bs[j * kLD + i];
     }
   }
 }
 
-// V chunk update by a 1024-thread workgroup (see tile_product16 for the wave layout).
+// Tile update by a 1024-thread workgroup: Y = W_k^T T(P_k, P_l) W_l written to
+// T(P_k, P_l) and mirrored into T(P_l, P_k).
 template <typename T>
-__device__ __forceinline__ void vchunk_update16(T* __restrict__ V, int ldv, int nvr, const T* __restrict__ Ek, int Ik,
-                                                int Jk, int row0, T* __restrict__ Bs, bool active) {
+__device__ __forceinline__ void tile_update16(T* __restrict__ Tm, int ldt, const T* __restrict__ Eall, const RR& rrb,
+                                              int r, int k, int l, T* __restrict__ Bs, bool active) {
   constexpr int b = kB2 / 2;
-  constexpr int kPer = kB2 * kB2 / kWT;
+  const int Ik = rrb.index(k, r) * b, Jk = rrb.index(rrb.h + k, r) * b - b;
+  const int Il = rrb.index(l, r) * b, Jl = rrb.index(rrb.h + l, r) * b - b;
+  tile_product16<T>(Tm, ldt, Eall + (size_t)k * kB2 * kB2, Eall + (size_t)l * kB2 * kB2, Ik, Jk, Il, Jl, Bs, active);
+  tile_store16<T>(Tm, ldt, Ik, Jk, Il, Jl, Bs, active);
+}
+
+// The thread's values of the V chunk: tv[q] = V(row0 + e % 2b, P_k[e / 2b]), e = tid + q kWT.
+template <typename T>
+__device__ __forceinline__ void vchunk_vals16(const T* __restrict__ V, int ldv, int nvr, int Ik, int Jk, int row0,
+                                              T (&tv)[kPer16]) {
+  constexpr int b = kB2 / 2;
+  auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };
+#pragma unroll
+  for (int q = 0; q < kPer16; ++q) {
+    const int e = threadIdx.x + q * kWT, i = e % kB2, kk = e / kB2;
+    const int row = row0 + i;
+    tv[q] = row < nvr ? V[row + (size_t)gk(kk) * ldv] : T(0);   // A(i, kk) = V(row, P_k[kk])
+  }
+}
+
+// The wave's fragment of E_k as the B operand: fb[q] = E_k(4 q + lane / 16, 16 (wave % 4) + lane % 16).
+template <typename T>
+__device__ __forceinline__ void efrag16(const T* __restrict__ Ek, T (&fb)[kB2 / 4]) {
+  const int lane = threadIdx.x & 63, bj = (threadIdx.x >> 6) & 3;
+#pragma unroll
+  for (int q = 0; q < kB2 / 4; ++q) fb[q] = Ek[(q * 4 + (lane >> 4)) * kB2 + bj * 16 + (lane & 15)];
+}
+
+// V(row0 .. row0+63, P_k) <- V + V E_k by a 1024-thread workgroup (wave layout as in
+// tile_product16) from the chunk's values and the E_k fragment already in registers.
+template <typename T>
+__device__ __forceinline__ void vchunk_update16_vals(const T (&tv)[kPer16], const T (&fb)[kB2 / 4],
+                                                     T* __restrict__ V, int ldv, int nvr, int Ik, int Jk, int row0,
+                                                     T* __restrict__ Bs, bool active) {
+  constexpr int b = kB2 / 2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int bi = wave >> 2, bj = wave & 3, cc = lane & 15, kq = lane >> 4;
   auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };
   typename Mfma<T>::acc_t acc;
-  T fb[kB2 / 4];
   if (active) {
-    T tv[kPer];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kWT, i = e % kB2, kk = e / kB2;
-      const int row = row0 + i;
-      tv[q] = row < nvr ? V[row + (size_t)gk(kk) * ldv] : T(0);   // A(i, kk) = V(row, P_k[kk])
-    }
-#pragma unroll
-    for (int q = 0; q < kB2 / 4; ++q) fb[q] = Ek[(q * 4 + kq) * kB2 + bj * 16 + cc];   // B(kk, j) = E_k(kk, j)
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
+    for (int q = 0; q < kPer16; ++q) {
       const int e = tid + q * kWT, i = e % kB2, kk = e / kB2;
       Bs[kk * kLD + i] = tv[q];
     }
@@ -830,12 +866,23 @@ __device__ __forceinline__ void vchunk_update16(T* __restrict__ V, int ldv, int 
   __syncthreads();
   if (active) {
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
+    for (int q = 0; q < kPer16; ++q) {
       const int e = tid + q * kWT, i = e % kB2, j = e / kB2;
       const int row = row0 + i;
       if (row < nvr) V[row + (size_t)gk(j) * ldv] = Bs[j * kLD + i];
     }
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void vchunk_update16(T* __restrict__ V, int ldv, int nvr, const T* __restrict__ Ek, int Ik,
+                                                int Jk, int row0, T* __restrict__ Bs, bool active) {
+  T tv[kPer16], fb[kB2 / 4];
+  if (active) {
+    vchunk_vals16<T>(V, ldv, nvr, Ik, Jk, row0, tv);
+    efrag16<T>(Ek, fb);
+  }
+  vchunk_update16_vals<T>(tv, fb, V, ldv, nvr, Ik, Jk, row0, Bs, active);
 }
 
 // Update of one whole block step of the single-matrix path by 1024-thread
@@ -898,36 +945,73 @@ blk_inner_v_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restr
   T* Bs = reinterpret_cast<T*>(smem);
   // The tiles of step rv that the inner solves of step r do not read (the inner workgroups
   // compute the others).  Every thread of a workgroup runs the same iterations (barriers).
+  // The next item's values are loaded before the current item is computed (items are
+  // disjoint, so the prefetch reads values no workgroup of this launch has written).
   const int ntile = npair * (npair - 1) / 2;
   const int per_t = (ntile + vwg - 1) / vwg;
-  for (int it = 0; it < per_t; ++it) {
+  struct TileRef { int k, l, Ik, Jk, Il, Jl; bool act; };
+  auto tile_at = [&](int it) {
+    TileRef t{0, 1, 0, 0, 0, 0, false};
     const int ti = wq + it * vwg;
-    int k = 0, l = 1;
-    bool active = ti < ntile;
-    if (active) {
-      stri_decode(ti, k, l);
-      active = !is_critical(rrb, rv, k, l) && !(identv[k] && identv[l]);
+    if (it < per_t && ti < ntile) {
+      stri_decode(ti, t.k, t.l);
+      t.act = !is_critical(rrb, rv, t.k, t.l) && !(identv[t.k] && identv[t.l]);
+      t.Ik = rrb.index(t.k, rv) * b;
+      t.Jk = rrb.index(rrb.h + t.k, rv) * b - b;
+      t.Il = rrb.index(t.l, rv) * b;
+      t.Jl = rrb.index(rrb.h + t.l, rv) * b - b;
     }
-    if (active && work && threadIdx.x == 0) atomicAdd(work, 1ull << 32);
+    return t;
+  };
+  T tv[kPer16], tn[kPer16];
+  TileRef tc = tile_at(0);
+  if (tc.act) tile_vals16<T>(Tm, ldt, tc.Ik, tc.Jk, tc.Il, tc.Jl, tv);
+  for (int it = 0; it < per_t; ++it) {
+    const TileRef tnx = tile_at(it + 1);
+    if (tnx.act) tile_vals16<T>(Tm, ldt, tnx.Ik, tnx.Jk, tnx.Il, tnx.Jl, tn);
+    if (tc.act && work && threadIdx.x == 0) atomicAdd(work, 1ull << 32);
     __syncthreads();   // the previous item's last phase still reads Bs
-    tile_update16<T>(Tm, ldt, Ev, rrb, rv, k, l, Bs, active);
+    tile_product16_vals<T>(tv, Ev + (size_t)tc.k * kB2 * kB2, Ev + (size_t)tc.l * kB2 * kB2, Bs, tc.act);
+    tile_store16<T>(Tm, ldt, tc.Ik, tc.Jk, tc.Il, tc.Jl, Bs, tc.act);
+#pragma unroll
+    for (int q = 0; q < kPer16; ++q) tv[q] = tn[q];
+    tc = tnx;
   }
-  // The V chunks of step rv.
+  // The V chunks of step rv, a contiguous range per workgroup: consecutive chunks of one pair
+  // share E_k, whose fragment is loaded only when the pair changes.
   const int total = npair * nvchunk;
   const int per = (total + vwg - 1) / vwg;
-  for (int it = 0; it < per; ++it) {
-    const int ci = wq + it * vwg;
-    int k = 0, chunk = 0;
-    bool active = ci < total;
-    if (active) {
-      k = ci / nvchunk;
-      chunk = ci % nvchunk;
-      active = identv[k] == 0;
+  const int c0 = wq * per;
+  struct ChunkRef { int k, row0, Ik, Jk; bool act; };
+  auto chunk_at = [&](int it) {
+    ChunkRef c{0, 0, 0, 0, false};
+    const int ci = c0 + it;
+    if (it < per && ci < total) {
+      c.k = ci / nvchunk;
+      c.row0 = (ci % nvchunk) * kB2;
+      c.act = identv[c.k] == 0;
+      c.Ik = rrb.index(c.k, rv) * b;
+      c.Jk = rrb.index(rrb.h + c.k, rv) * b - b;
     }
-    if (active && work && threadIdx.x == 0) atomicAdd(work, 1ull);
+    return c;
+  };
+  T fb[kB2 / 4];
+  int kfb = -1;
+  ChunkRef cc = chunk_at(0);
+  if (cc.act) vchunk_vals16<T>(V, ldv, nvr, cc.Ik, cc.Jk, cc.row0, tv);
+  for (int it = 0; it < per; ++it) {
+    const ChunkRef cnx = chunk_at(it + 1);
+    if (cnx.act) vchunk_vals16<T>(V, ldv, nvr, cnx.Ik, cnx.Jk, cnx.row0, tn);
+    if (cc.act && cc.k != kfb) {
+      efrag16<T>(Ev + (size_t)cc.k * kB2 * kB2, fb);
+      kfb = cc.k;
+    }
+    if (cc.act && work && threadIdx.x == 0) atomicAdd(work, 1ull);
     __syncthreads();
-    vchunk_update16<T>(V, ldv, nvr, Ev + (size_t)k * kB2 * kB2, rrb.index(k, rv) * b, rrb.index(rrb.h + k, rv) * b - b,
-                       chunk * kB2, Bs, active);
+    vchunk_update16_vals<T>(tv, fb, V, ldv, nvr, cc.Ik, cc.Jk, cc.row0, Bs, cc.act);
+#pragma unroll
+    for (int q = 0; q < kPer16; ++q) tv[q] = tn[q];
+    cc = cnx;
   }
 }
 
