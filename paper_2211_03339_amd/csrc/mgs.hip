@@ -116,12 +116,13 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds2, int par
 // later columns j; then q_c = v_c / ||v_c|| and v_j -= (q_c . v_j) q_c with
 // q_c . v_j = (v_c . v_j) / ||v_c||.  C is a compile-time column index so
 // that the register panel is never indexed dynamically.  Columns at or past
-// ncols (the short last panel) are zero and stay zero.
-template <int R, int P, int C>
+// ncols (the short last panel) are zero and stay zero; FULL panels (ncols = P)
+// are compiled without the column tests.
+template <int R, int P, int C, bool FULL>
 __device__ __forceinline__ void mgs_column(double (&v)[R][P], int ncols, const double* nrm0, double* lds2,
                                            int* flag) {
   if constexpr (C < P) {
-    if (C < ncols) {
+    if (FULL || C < ncols) {
       constexpr int NV = P - C;
       double part[NV];
 #pragma unroll
@@ -152,33 +153,33 @@ __device__ __forceinline__ void mgs_column(double (&v)[R][P], int ncols, const d
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r][C + j] = fma(-d, v[r][C], v[r][C + j]);
       }
-      mgs_column<R, P, C + 1>(v, ncols, nrm0, lds2, flag);
+      mgs_column<R, P, C + 1, FULL>(v, ncols, nrm0, lds2, flag);
     }
   }
 }
 
-template <int R, int P>
+template <int R, int P, bool FULL>
 __global__ void __launch_bounds__(kMT) mgs_panel_kernel(double* __restrict__ Q, int m, int ldq, int ncols,
                                                         const double* __restrict__ nrm0, int* __restrict__ flag) {
   __shared__ double lds2[2 * (kMT / 16) * 16];
   __shared__ double n0[P];   // original column norms, staged once (a global read per column would
                              // sit behind every column's reduction)
   double v[R][P];
-  if (threadIdx.x < P) n0[threadIdx.x] = (int)threadIdx.x < ncols ? nrm0[threadIdx.x] : 1.0;
+  if (threadIdx.x < P) n0[threadIdx.x] = (FULL || (int)threadIdx.x < ncols) ? nrm0[threadIdx.x] : 1.0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     int i = threadIdx.x + r * kMT;
 #pragma unroll
-    for (int c = 0; c < P; ++c) v[r][c] = (i < m && c < ncols) ? Q[i + (size_t)c * ldq] : 0.0;
+    for (int c = 0; c < P; ++c) v[r][c] = (i < m && (FULL || c < ncols)) ? Q[i + (size_t)c * ldq] : 0.0;
   }
   __syncthreads();
-  mgs_column<R, P, 0>(v, ncols, n0, lds2, flag);
+  mgs_column<R, P, 0, FULL>(v, ncols, n0, lds2, flag);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     int i = threadIdx.x + r * kMT;
 #pragma unroll
     for (int c = 0; c < P; ++c)
-      if (i < m && c < ncols) Q[i + (size_t)c * ldq] = v[r][c];
+      if (i < m && (FULL || c < ncols)) Q[i + (size_t)c * ldq] = v[r][c];
   }
 }
 
@@ -304,6 +305,15 @@ static int panel_width(int m) {
 }
 
 // nrm0 (n) and the partial W of the projection kernels (per 16-column block and 256-row block).
+template <bool FULL>
+static void launch_panel(int R, hipStream_t s, double* Qp, int m, int ldq, int w, const double* nrm0, int* flag) {
+  if (R <= 1) hipLaunchKernelGGL((mgs_panel_kernel<1, 16, FULL>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0, flag);
+  else if (R <= 2) hipLaunchKernelGGL((mgs_panel_kernel<2, 16, FULL>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0, flag);
+  else if (R <= 4) hipLaunchKernelGGL((mgs_panel_kernel<4, 16, FULL>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0, flag);
+  else if (R <= 8) hipLaunchKernelGGL((mgs_panel_kernel<8, 8, FULL>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0, flag);
+  else hipLaunchKernelGGL((mgs_panel_kernel<16, 4, FULL>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0, flag);
+}
+
 size_t mgs_scratch_elems(int m, int n) {
   return (size_t)n + 64 + (size_t)((n + kPW - 1) / kPW) * ((m + kRB - 1) / kRB) * kPW * kPW;
 }
@@ -322,11 +332,8 @@ int mgs_f64(double* Q, int m, int n, int ldq, double* W, int* flag, hipStream_t 
   for (int j0 = 0; j0 < n; j0 += P) {
     int w = n - j0 < P ? n - j0 : P;
     double* Qp = Q + (size_t)j0 * ldq;
-    if (R <= 1) hipLaunchKernelGGL((mgs_panel_kernel<1, 16>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0 + j0, flag);
-    else if (R <= 2) hipLaunchKernelGGL((mgs_panel_kernel<2, 16>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0 + j0, flag);
-    else if (R <= 4) hipLaunchKernelGGL((mgs_panel_kernel<4, 16>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0 + j0, flag);
-    else if (R <= 8) hipLaunchKernelGGL((mgs_panel_kernel<8, 8>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0 + j0, flag);
-    else hipLaunchKernelGGL((mgs_panel_kernel<16, 4>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0 + j0, flag);
+    if (w == P) launch_panel<true>(R, s, Qp, m, ldq, w, nrm0 + j0, flag);
+    else launch_panel<false>(R, s, Qp, m, ldq, w, nrm0 + j0, flag);
     JAC_CHECK_LAUNCH();
     const int rest = n - j0 - w;
     if (rest > 0) {
