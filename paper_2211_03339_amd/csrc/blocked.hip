@@ -403,8 +403,18 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
           const T dx = Sc[pkx * kLD + qkx], dy = Sc[pky * kLD + qky];
           const T sxx = x == pkx ? fmaT(-ax.t, dx, Sc[pkx * kLD + pkx]) : fmaT(ax.t, dx, Sc[qkx * kLD + qkx]);
           const T syy = y == pky ? fmaT(-ay.t, dy, Sc[pky * kLD + pky]) : fmaT(ay.t, dy, Sc[qky * kLD + qky]);
-          T tt = Sc[pkx * kLD + pky], tb = Sc[pkx * kLD + qky];
-          T bt = Sc[qkx * kLD + pky], bb = Sc[qkx * kLD + qky];
+          T tt, tb, bt, bb;
+          if constexpr (BIP) {   // canonical positions (see the work lanes)
+            tt = Sc[(pkx < pky ? pkx : pky) * kLD + (pkx < pky ? pky : pkx)];
+            tb = Sc[pkx * kLD + qky];
+            bt = Sc[pky * kLD + qkx];
+            bb = Sc[(qkx < qky ? qkx : qky) * kLD + (qkx < qky ? qky : qkx)];
+          } else {
+            tt = Sc[pkx * kLD + pky];
+            tb = Sc[pkx * kLD + qky];
+            bt = Sc[qkx * kLD + pky];
+            bb = Sc[qkx * kLD + qky];
+          }
           rotate_block(tt, tb, bt, bb, ax, ay, kx > ky);
           const T sxy = x == pkx ? (y == pky ? tt : tb) : (y == pky ? bt : bb);
           ang[cur ^ 1][lane] = make_angle(sxx, syy, sxy, gidx(x), gidx(y), n, skip_abs, rel);
@@ -422,10 +432,20 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
           pair_at(bl, ri, pl, ql);
           ak = ac[bk];
           al = ac[bl];
-          tt = Sc[pk * kLD + pl];
-          tb = Sc[pk * kLD + ql];
-          bt = Sc[qk * kLD + pl];
-          bb = Sc[qk * kLD + ql];
+          if constexpr (BIP) {
+            // Bipartite steps keep S only at canonical positions: the upper triangles of the
+            // two diagonal quadrants and the off-diagonal quadrant (rows < kH), each written
+            // once per step (pk <= pl always; qk, ql >= kH in either order).
+            tt = Sc[pk * kLD + pl];
+            tb = Sc[pk * kLD + ql];
+            bt = Sc[pl * kLD + qk];
+            bb = Sc[(qk < ql ? qk : ql) * kLD + (qk < ql ? ql : qk)];
+          } else {
+            tt = Sc[pk * kLD + pl];
+            tb = Sc[pk * kLD + ql];
+            bt = Sc[qk * kLD + pl];
+            bb = Sc[qk * kLD + ql];
+          }
         }
         const Ang<T> ae = ac[pe];
         int pp, qp;
@@ -448,18 +468,25 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
             bb = fmaT(ak.t, tb, bb);
             Sn[pk * kLD + pk] = tt;
             Sn[pk * kLD + qk] = T(0);
-            Sn[qk * kLD + pk] = T(0);
+            if constexpr (!BIP) Sn[qk * kLD + pk] = T(0);
             Sn[qk * kLD + qk] = bb;
           } else {
             rotate_block(tt, tb, bt, bb, ak, al, false);
-            Sn[pk * kLD + pl] = tt;
-            Sn[pk * kLD + ql] = tb;
-            Sn[qk * kLD + pl] = bt;
-            Sn[qk * kLD + ql] = bb;
-            Sn[pl * kLD + pk] = tt;
-            Sn[ql * kLD + pk] = tb;
-            Sn[pl * kLD + qk] = bt;
-            Sn[ql * kLD + qk] = bb;
+            if constexpr (BIP) {
+              Sn[pk * kLD + pl] = tt;
+              Sn[pk * kLD + ql] = tb;
+              Sn[pl * kLD + qk] = bt;
+              Sn[(qk < ql ? qk : ql) * kLD + (qk < ql ? ql : qk)] = bb;
+            } else {
+              Sn[pk * kLD + pl] = tt;
+              Sn[pk * kLD + ql] = tb;
+              Sn[qk * kLD + pl] = bt;
+              Sn[qk * kLD + ql] = bb;
+              Sn[pl * kLD + pk] = tt;
+              Sn[ql * kLD + pk] = tb;
+              Sn[pl * kLD + qk] = bt;
+              Sn[ql * kLD + qk] = bb;
+            }
           }
         }
         // E <- E R + (R - I) on columns (p, q): with x = E(a, p), y = E(a, q)
@@ -495,7 +522,12 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
   if (!Gpart) {
     for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
       const int a = e % kB2, c = e / kB2;
-      Tm[gidx(a) + (size_t)gidx(c) * ldt] = S[cur][a * kLD + c];
+      int ci = a * kLD + c;
+      if constexpr (BIP) {   // canonical position of S(a, c)
+        if ((a < kH) == (c < kH)) ci = (a < c ? a : c) * kLD + (a < c ? c : a);
+        else if (a >= kH) ci = c * kLD + a;
+      }
+      Tm[gidx(a) + (size_t)gidx(c) * ldt] = S[cur][ci];
     }
   }
   // E_k row-major: Eall[k][a * 2b + c] = E(a, c).  (Bipartite: after whole inner sweeps ey is
