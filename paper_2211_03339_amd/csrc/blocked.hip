@@ -943,6 +943,92 @@ blk_update16_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int
   }
 }
 
+// Helper-item forms with two LDS tiles (A and B), so that no barrier guards a
+// tile against the previous phase's readers: a T tile is staged in A, X goes
+// to B and Y back to A (3 barriers); consecutive tiles swap A and B, so the
+// next tile's staging never meets the last one's readers.  A V chunk is staged
+// in A and its result goes to B (2 barriers); the next chunk stages in A again,
+// which only this chunk's first product read.
+template <typename T>
+__device__ __forceinline__ void tile_update16_ab(const T (&tv)[kPer16], const T* __restrict__ Ek,
+                                                 const T* __restrict__ El, T* __restrict__ Tm, int ldt, int Ik,
+                                                 int Jk, int Il, int Jl, T* __restrict__ A, T* __restrict__ B,
+                                                 bool active) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bi = wave >> 2, bj = wave & 3, cc = lane & 15, kq = lane >> 4;
+  typename Mfma<T>::acc_t acc;
+  T fa[kB2 / 4], fb[kB2 / 4];
+  if (active) {
+#pragma unroll
+    for (int q = 0; q < kB2 / 4; ++q) fa[q] = Ek[(q * 4 + kq) * kB2 + bi * 16 + cc];   // A(i, kk) = E_k(kk, i)
+#pragma unroll
+    for (int q = 0; q < kB2 / 4; ++q) fb[q] = El[(q * 4 + kq) * kB2 + bj * 16 + cc];   // B(kk, j) = E_l(kk, j)
+#pragma unroll
+    for (int q = 0; q < kPer16; ++q) {
+      const int e = tid + q * kWT, kk = e % kB2, c = e / kB2;
+      A[kk * kLD + c] = tv[q];   // T tile
+    }
+  }
+  __syncthreads();
+  if (active) {
+    acc = typename Mfma<T>::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < kB2 / 4; ++q) acc = Mfma<T>::op(fa[q], A[(q * 4 + kq) * kLD + bj * 16 + cc], acc);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[rr] += A[(bi * 16 + Mfma<T>::row(lane, rr)) * kLD + bj * 16 + cc];   // + T
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) B[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)] = acc[rr];   // X, k-major
+  }
+  __syncthreads();
+  if (active) {
+    acc = typename Mfma<T>::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < kB2 / 4; ++q) acc = Mfma<T>::op(B[(q * 4 + kq) * kLD + bi * 16 + cc], fb[q], acc);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[rr] += B[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)];   // + X
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) A[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)] = acc[rr];   // Y
+  }
+  __syncthreads();
+  tile_store16<T>(Tm, ldt, Ik, Jk, Il, Jl, A, active);
+}
+
+template <typename T>
+__device__ __forceinline__ void vchunk_update16_ab(const T (&tv)[kPer16], const T (&fb)[kB2 / 4],
+                                                   T* __restrict__ V, int ldv, int nvr, int Ik, int Jk, int row0,
+                                                   T* __restrict__ A, T* __restrict__ B, bool active) {
+  constexpr int b = kB2 / 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bi = wave >> 2, bj = wave & 3, cc = lane & 15, kq = lane >> 4;
+  auto gk = [&](int a) { return a < b ? Ik + a : Jk + a; };
+  if (active) {
+#pragma unroll
+    for (int q = 0; q < kPer16; ++q) {
+      const int e = tid + q * kWT, i = e % kB2, kk = e / kB2;
+      A[kk * kLD + i] = tv[q];
+    }
+  }
+  __syncthreads();
+  if (active) {
+    typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < kB2 / 4; ++q) acc = Mfma<T>::op(A[(q * 4 + kq) * kLD + bi * 16 + cc], fb[q], acc);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[rr] += A[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)];   // + V
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) B[(bj * 16 + cc) * kLD + bi * 16 + Mfma<T>::row(lane, rr)] = acc[rr];
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int q = 0; q < kPer16; ++q) {
+      const int e = tid + q * kWT, i = e % kB2, j = e / kB2;
+      const int row = row0 + i;
+      if (row < nvr) V[row + (size_t)gk(j) * ldv] = B[j * kLD + i];
+    }
+  }
+}
+
 // Inner solves of block step r (workgroups 0 .. npair-1) together with the
 // update of block step rv = r - 1 (the other workgroups, one tile or 64-row
 // chunk at a time, by all 16 waves): the V chunks and, with merge_tiles, the
@@ -954,7 +1040,7 @@ blk_update16_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int
 // parity (Eall/ident for step r, Ev/identv for step rv).
 template <typename T>
 constexpr size_t inner_v_lds_bytes() {
-  return inner_lds_bytes<T>() > kB2 * kLD * sizeof(T) ? inner_lds_bytes<T>() : kB2 * kLD * sizeof(T);
+  return inner_lds_bytes<T>() > 2 * kB2 * kLD * sizeof(T) ? inner_lds_bytes<T>() : 2 * kB2 * kLD * sizeof(T);
 }
 
 template <typename T, bool BIP>
@@ -995,6 +1081,7 @@ blk_inner_v_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restr
     }
     return t;
   };
+  T* Bs2 = Bs + kB2 * kLD;
   T tv[kPer16], tn[kPer16];
   TileRef tc = tile_at(0);
   if (tc.act) tile_vals16<T>(Tm, ldt, tc.Ik, tc.Jk, tc.Il, tc.Jl, tv);
@@ -1002,13 +1089,15 @@ blk_inner_v_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restr
     const TileRef tnx = tile_at(it + 1);
     if (tnx.act) tile_vals16<T>(Tm, ldt, tnx.Ik, tnx.Jk, tnx.Il, tnx.Jl, tn);
     if (tc.act && work && threadIdx.x == 0) atomicAdd(work, 1ull << 32);
-    __syncthreads();   // the previous item's last phase still reads Bs
-    tile_product16_vals<T>(tv, Ev + (size_t)tc.k * kB2 * kB2, Ev + (size_t)tc.l * kB2 * kB2, Bs, tc.act);
-    tile_store16<T>(Tm, ldt, tc.Ik, tc.Jk, tc.Il, tc.Jl, Bs, tc.act);
+    T* ta = (it & 1) ? Bs2 : Bs;
+    T* tb = (it & 1) ? Bs : Bs2;
+    tile_update16_ab<T>(tv, Ev + (size_t)tc.k * kB2 * kB2, Ev + (size_t)tc.l * kB2 * kB2, Tm, ldt, tc.Ik, tc.Jk,
+                        tc.Il, tc.Jl, ta, tb, tc.act);
 #pragma unroll
     for (int q = 0; q < kPer16; ++q) tv[q] = tn[q];
     tc = tnx;
   }
+  __syncthreads();   // the last tile's stores still read its A tile
   // The V chunks of step rv, a contiguous range per workgroup: consecutive chunks of one pair
   // share E_k, whose fragment is loaded only when the pair changes.
   const int total = npair * nvchunk;
@@ -1039,8 +1128,7 @@ blk_inner_v_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restr
       kfb = cc.k;
     }
     if (cc.act && work && threadIdx.x == 0) atomicAdd(work, 1ull);
-    __syncthreads();
-    vchunk_update16_vals<T>(tv, fb, V, ldv, nvr, cc.Ik, cc.Jk, cc.row0, Bs, cc.act);
+    vchunk_update16_ab<T>(tv, fb, V, ldv, nvr, cc.Ik, cc.Jk, cc.row0, Bs, Bs2, cc.act);
 #pragma unroll
     for (int q = 0; q < kPer16; ++q) tv[q] = tn[q];
     cc = cnx;
