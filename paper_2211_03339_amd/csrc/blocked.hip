@@ -165,10 +165,14 @@ __device__ __forceinline__ void tile_vals16(const T* __restrict__ Tm, int ldt, i
   }
 }
 
-// The product of tile_product16 from the tile's values already in registers.
-template <typename T>
+struct NoHook { __device__ void operator()() const {} };
+
+// The product of tile_product16 from the tile's values already in registers.  staged() runs
+// once every thread's tile values are in LDS (the workgroup has read the tile).
+template <typename T, typename F = NoHook>
 __device__ __forceinline__ void tile_product16_vals(const T (&tv)[kPer16], const T* __restrict__ Ek,
-                                                    const T* __restrict__ El, T* __restrict__ Bs, bool active) {
+                                                    const T* __restrict__ El, T* __restrict__ Bs, bool active,
+                                                    F staged = F()) {
   constexpr int kPer = kPer16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int bi = wave >> 2, bj = wave & 3, cc = lane & 15, kq = lane >> 4;
@@ -186,6 +190,7 @@ __device__ __forceinline__ void tile_product16_vals(const T (&tv)[kPer16], const
     }
   }
   __syncthreads();
+  staged();
   if (active) {
     acc = typename Mfma<T>::acc_t{0, 0, 0, 0};
 #pragma unroll
@@ -214,13 +219,13 @@ __device__ __forceinline__ void tile_product16_vals(const T (&tv)[kPer16], const
   __syncthreads();
 }
 
-template <typename T>
+template <typename T, typename F = NoHook>
 __device__ __forceinline__ void tile_product16(const T* __restrict__ Tm, int ldt, const T* __restrict__ Ek,
                                                const T* __restrict__ El, int Ik, int Jk, int Il, int Jl,
-                                               T* __restrict__ Bs, bool active) {
+                                               T* __restrict__ Bs, bool active, F staged = F()) {
   T tv[kPer16];
   if (active) tile_vals16<T>(Tm, ldt, Ik, Jk, Il, Jl, tv);
-  tile_product16_vals<T>(tv, Ek, El, Bs, active);
+  tile_product16_vals<T>(tv, Ek, El, Bs, active, staged);
 }
 
 template <typename T>
@@ -251,12 +256,22 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
   auto pair_of = [&](int x, int ri) {
     return bip ? (x < kH ? x : ((x - kH - ri) & (kH - 1))) : ring_pair_of(x, ri);
   };
+  auto first_angles = [&]() {
+    if (tid < kH) {
+      int p, q;
+      pair_at(tid, 0, p, q);
+      ang[0][tid] = make_angle(S[0][p * kLD + p], S[0][q * kLD + q], S[0][p * kLD + q], gidx(p), gidx(q), n,
+                               skip_abs, rel);
+    }
+  };
   if (Ev) {
     // The update of block step r - 1 has not been applied to the tile that holds T(I, J):
     // compute that tile Y = W_ka^T T(P_ka, P_kb) W_kb here (ka < kb: the step r - 1 pairs of I
     // and J), take the quarter T(I, J) from it, and write back the quarters no inner solve of
     // this step reads.  A tile can hold the quarters of two pairs of this step; both compute it,
-    // and the later of the two (per-tile counter) writes, after both have read the old tile.
+    // and the later of the two (per-tile counter, counted as soon as the workgroup has read the
+    // tile) writes, after both have read the old tile.  The write-back runs while wave 0
+    // computes the first angles.
     // T(I, I) and T(J, J) lie in diagonal blocks of step r - 1, final since its inner solves.
     constexpr int kPer = kB2 * kB2 / kInnerThreads;
     const int rv = r - 1;
@@ -274,19 +289,20 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
       sv[q] = (id || (a < kH) == (c < kH)) ? Tm[gidx(a) + (size_t)gidx(c) * ldt] : T(0);
     }
     T* Y = S[1];
-    tile_product16<T>(Tm, ldt, Ev + (size_t)ka * kB2 * kB2, Ev + (size_t)kb * kB2 * kB2, A0 * kH, A1 * kH - kH,
-                      B0 * kH, B1 * kH - kH, Y, !id);
     int* flag = reinterpret_cast<int*>(ang);
     // quarters (x, y), x of pair ka, y of pair kb, that pairs of this step read
     auto read_now = [&](int x, int y) { return block_pair_of(rrb, x, r) == block_pair_of(rrb, y, r); };
     const int readers = (int)read_now(A0, B0) + (int)read_now(A0, B1) + (int)read_now(A1, B0) + (int)read_now(A1, B1);
+    const int ti = kb * (kb - 1) / 2 + ka;
+    int before = 0;   // thread 0: the tile's count before this workgroup's
+    auto mark_read = [&]() {
+      if (tid == 0 && !id && readers > 1) before = atomicAdd(tcount + ti, 1);
+    };
+    tile_product16<T>(Tm, ldt, Ev + (size_t)ka * kB2 * kB2, Ev + (size_t)kb * kB2 * kB2, A0 * kH, A1 * kH - kH,
+                      B0 * kH, B1 * kH - kH, Y, !id, mark_read);
     if (tid == 0 && !id) {
-      bool last = true;
-      if (readers > 1) {
-        const int ti = kb * (kb - 1) / 2 + ka;
-        last = atomicAdd(tcount + ti, 1) == readers - 1;
-        if (last) atomicExch(tcount + ti, 0);
-      }
+      const bool last = readers <= 1 || before == readers - 1;
+      if (last && readers > 1) atomicExch(tcount + ti, 0);
       flag[0] = last;
       if (last && work) atomicAdd(work, 1ull << 32);
     }
@@ -301,8 +317,10 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
         v = swap ? Y[(hI * kH + x) * kLD + hJ * kH + y] : Y[(hJ * kH + y) * kLD + hI * kH + x];
       }
       S[0][a * kLD + c] = v;
-      E[a * kLD + c] = T(0);
+      if constexpr (!BIP) E[a * kLD + c] = T(0);   // (bipartite steps keep E in registers)
     }
+    __syncthreads();
+    first_angles();
     if (write_rest) {
       auto gA = [&](int u) { return u < kH ? A0 * kH + u : A1 * kH + u - kH; };
       auto gB = [&](int v) { return v < kH ? B0 * kH + v : B1 * kH + v - kH; };
@@ -330,23 +348,21 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
         v = Tm[gidx(a) + (size_t)gidx(c) * ldt];
       }
       S[0][a * kLD + c] = v;
-      E[a * kLD + c] = T(0);
+      if constexpr (!BIP) E[a * kLD + c] = T(0);
     }
-  }
-  __syncthreads();
-  if (tid < kH) {   // angles of the first step
-    int p, q;
-    pair_at(tid, 0, p, q);
-    ang[0][tid] = make_angle(S[0][p * kLD + p], S[0][q * kLD + q], S[0][p * kLD + q], gidx(p), gidx(q), n, skip_abs,
-                             rel);
+    __syncthreads();
+    first_angles();
   }
   __syncthreads();
   // Block (bk, bl), bk <= bl, of work lane tid - 64 < kBlocks (fixed for all steps).
   int bk = -1, bl = -1;
   if (tid >= 64 && tid - 64 < kBlocks) {
+    // e = l (l + 1) / 2 + k: l from the root of l^2 + l - 2e, then one correction each way
+    // (e < 528, so the single-precision root is off by at most one)
     const int e = tid - 64;
-    int l = 0;
-    while ((l + 1) * (l + 2) / 2 <= e) ++l;
+    int l = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+    if ((l + 1) * (l + 2) / 2 <= e) ++l;
+    if (l * (l + 1) / 2 > e) --l;
     bl = l;
     bk = e - l * (l + 1) / 2;
   }
@@ -378,10 +394,18 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
   int cur = 0;
   for (int sw = 0; sw < max_inner; ++sw) {
     bool big = false;
-    for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
-      const int a = e % kB2, c = e / kB2;
-      if (a < c && (!bip || (a < kH && c >= kH)) && gidx(a) < n && gidx(c) < n)
-        big |= !negligible2(S[cur][a * kLD + a], S[cur][c * kLD + c], S[cur][a * kLD + c], skip_abs, rel);
+    if constexpr (bip) {
+      // only the b x b pairs between the two blocks rotate: one per thread
+      static_assert(kInnerThreads == kH * kH, "one cross pair per thread");
+      const int a = tid & (kH - 1), c = kH + (tid >> 5);
+      if (gidx(a) < n && gidx(c) < n)
+        big = !negligible2(S[cur][a * kLD + a], S[cur][c * kLD + c], S[cur][a * kLD + c], skip_abs, rel);
+    } else {
+      for (int e = tid; e < kB2 * kB2; e += kInnerThreads) {
+        const int a = e % kB2, c = e / kB2;
+        if (a < c && gidx(a) < n && gidx(c) < n)
+          big |= !negligible2(S[cur][a * kLD + a], S[cur][c * kLD + c], S[cur][a * kLD + c], skip_abs, rel);
+      }
     }
     if (!__syncthreads_or(big)) break;
     for (int ri = 0; ri < nsteps; ++ri) {
