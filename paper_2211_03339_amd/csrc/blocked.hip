@@ -42,6 +42,9 @@ __device__ __forceinline__ void stri_decode(int e, int& k, int& l) {
 
 constexpr int kH = kB2 / 2;
 
+// Two values read or written together in LDS.
+template <typename T> struct alignas(2 * sizeof(T)) Rs { T x, y; };
+
 // Inner solver: one workgroup diagonalises S = T(P_k, P_k) (2b x 2b) by
 // cyclic Jacobi and accumulates the product of its rotations as
 // E_k = W_k - I (the deviation from the identity is kept so that its rounding
@@ -242,7 +245,14 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
                                             unsigned long long* __restrict__ work = nullptr) {
   T (*S)[kB2 * kLD] = reinterpret_cast<T (*)[kB2 * kLD]>(smem);            // S[2][..]
   T* E = reinterpret_cast<T*>(smem) + 2 * kB2 * kLD;                         // E[a * kLD + c]
-  Ang<T> (*ang)[kH] = reinterpret_cast<Ang<T> (*)[kH]>(smem + 3 * kB2 * kLD * sizeof(T));   // ang[2][..]
+  // Angles (ping-pong), split so that the rotation lanes read only what they use:
+  // rs[.][k] = (s, tau) of pair k, rt[.][k] = (t, applied).
+  Rs<T> (*rs)[kH] = reinterpret_cast<Rs<T> (*)[kH]>(smem + 3 * kB2 * kLD * sizeof(T));
+  Rs<T> (*rt)[kH] = rs + 2;
+  auto put_angle = [&](int buf, int i, const Ang<T>& a) {
+    rs[buf][i] = Rs<T>{a.s, a.tau};
+    rt[buf][i] = Rs<T>{a.t, a.applied};
+  };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const RR rrb(m2);
   const int I = rrb.index(k, r), J = rrb.index(rrb.h + k, r);
@@ -260,8 +270,8 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
     if (tid < kH) {
       int p, q;
       pair_at(tid, 0, p, q);
-      ang[0][tid] = make_angle(S[0][p * kLD + p], S[0][q * kLD + q], S[0][p * kLD + q], gidx(p), gidx(q), n,
-                               skip_abs, rel);
+      put_angle(0, tid, make_angle(S[0][p * kLD + p], S[0][q * kLD + q], S[0][p * kLD + q], gidx(p), gidx(q), n,
+                                   skip_abs, rel));
     }
   };
   if (Ev) {
@@ -289,7 +299,7 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
       sv[q] = (id || (a < kH) == (c < kH)) ? Tm[gidx(a) + (size_t)gidx(c) * ldt] : T(0);
     }
     T* Y = S[1];
-    int* flag = reinterpret_cast<int*>(ang);
+    int* flag = reinterpret_cast<int*>(rs);
     // quarters (x, y), x of pair ka, y of pair kb, that pairs of this step read
     auto read_now = [&](int x, int y) { return block_pair_of(rrb, x, r) == block_pair_of(rrb, y, r); };
     const int readers = (int)read_now(A0, B0) + (int)read_now(A0, B1) + (int)read_now(A1, B0) + (int)read_now(A1, B1);
@@ -411,9 +421,14 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
     for (int ri = 0; ri < nsteps; ++ri) {
       const T* Sc = S[cur];
       T* Sn = S[cur ^ 1];
-      const Ang<T>* ac = ang[cur];
+      const Rs<T>* acs = rs[cur];
+      const Rs<T>* act = rt[cur];
+      auto angle_at = [&](int i) {
+        const Rs<T> a = acs[i], b = act[i];
+        return Ang<T>{a.x, a.y, b.x, b.y};
+      };
       if (wave == 0) {
-        const unsigned long long m = __ballot(lane < kH && ac[lane & (kH - 1)].applied != T(0));
+        const unsigned long long m = __ballot(lane < kH && act[lane & (kH - 1)].y != T(0));
         cnt += __popcll(m);
         if (lane < kH) {
           const int r1 = ri == nsteps - 1 ? 0 : ri + 1;
@@ -423,7 +438,7 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
           int pkx, qkx, pky, qky;
           pair_at(kx, ri, pkx, qkx);
           pair_at(ky, ri, pky, qky);
-          const Ang<T> ax = ac[kx], ay = ac[ky];
+          const Ang<T> ax = angle_at(kx), ay = angle_at(ky);
           const T dx = Sc[pkx * kLD + qkx], dy = Sc[pky * kLD + qky];
           const T sxx = x == pkx ? fmaT(-ax.t, dx, Sc[pkx * kLD + pkx]) : fmaT(ax.t, dx, Sc[qkx * kLD + qkx]);
           const T syy = y == pky ? fmaT(-ay.t, dy, Sc[pky * kLD + pky]) : fmaT(ay.t, dy, Sc[qky * kLD + qky]);
@@ -441,7 +456,7 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
           }
           rotate_block(tt, tb, bt, bb, ax, ay, kx > ky);
           const T sxy = x == pkx ? (y == pky ? tt : tb) : (y == pky ? bt : bb);
-          ang[cur ^ 1][lane] = make_angle(sxx, syy, sxy, gidx(x), gidx(y), n, skip_abs, rel);
+          put_angle(cur ^ 1, lane, make_angle(sxx, syy, sxy, gidx(x), gidx(y), n, skip_abs, rel));
         }
       } else {
         // Loads of all the lane's items first (S and E accesses share one array
@@ -454,8 +469,12 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
         if (has_blk) {
           pair_at(bk, ri, pk, qk);
           pair_at(bl, ri, pl, ql);
-          ak = ac[bk];
-          al = ac[bl];
+          const Rs<T> sk = acs[bk], sl = acs[bl];
+          ak.s = sk.x;
+          ak.tau = sk.y;
+          al.s = sl.x;
+          al.tau = sl.y;
+          if (bk == bl) ak.t = act[bk].x;   // the diagonal blocks use the t-form
           if constexpr (BIP) {
             // Bipartite steps keep S only at canonical positions: the upper triangles of the
             // two diagonal quadrants and the off-diagonal quadrant (rows < kH), each written
@@ -471,10 +490,13 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
             bb = Sc[qk * kLD + ql];
           }
         }
-        const Ang<T> ae = ac[pe];
+        const Rs<T> se = acs[pe];
+        Ang<T> ae{};
+        ae.s = se.x;
+        ae.tau = se.y;
         int pp, qp;
         pair_at(pe, ri, pp, qp);
-        const bool rot_e = ae.applied != T(0);
+        const bool rot_e = ae.s != T(0);   // (s = 0 leaves E exactly as it is)
         if constexpr (!BIP) {
           if (rot_e) {
 #pragma unroll
@@ -1123,10 +1145,18 @@ blk_inner_v_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restr
   }
   __syncthreads();   // the last tile's stores still read its A tile
   // The V chunks of step rv, a contiguous range per workgroup: consecutive chunks of one pair
-  // share E_k, whose fragment is loaded only when the pair changes.
+  // share E_k, whose fragment is loaded only when the pair changes.  A tile costs about two
+  // chunks, so the ranges even out tiles + chunks: the trem workgroups that took one tile more
+  // (tb + 1 instead of tb) take x - 2 chunks, the others x, with x the least count that covers
+  // every chunk.
   const int total = npair * nvchunk;
-  const int per = (total + vwg - 1) / vwg;
-  const int c0 = wq * per;
+  const int trem = ntile % vwg;
+  int x = (total + 2 * trem + vwg - 1) / vwg;   // covers total when x >= 2: vwg x - 2 trem >= total
+  if (x < 2) x = vwg - trem >= total ? (total > 0 ? 1 : 0) : 2;
+  const int cA = x > 2 ? x - 2 : 0, cB = x;
+  const bool more = wq < trem;
+  const int per = more ? cA : cB;
+  const int c0 = more ? wq * cA : trem * cA + (wq - trem) * cB;
   struct ChunkRef { int k, row0, Ik, Jk; bool act; };
   auto chunk_at = [&](int it) {
     ChunkRef c{0, 0, 0, 0, false};
