@@ -1400,10 +1400,11 @@ int blk_sweep(BlkState<T>& st, int max_inner, hipStream_t s) {
     cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
               ? prop.multiProcessorCount : 256;
   }
-  // (FP64: the inner solve's LDS allows one workgroup per CU; FP32: two.)
-  const int per_cu = sizeof(T) == 4 ? 2 : 1;
+  // One helper per free CU: the kernel's registers (over 64 per lane for 16 waves) leave room
+  // for one 1024-thread workgroup per CU, so a second helper per CU would only start once the
+  // first has finished; the helpers loop over their share of the items instead.
   int vwg = m * nvchunk;
-  const int free_wgs = (cus - m > 16 ? cus - m : 16) * per_cu;
+  const int free_wgs = cus - m > 16 ? cus - m : 16;
   if (vwg > free_wgs) vwg = free_wgs;
   // E and the identity flags alternate by step parity: step r's inner solve
   // writes buffer r & 1 while the V update of step r - 1 still reads the other.
