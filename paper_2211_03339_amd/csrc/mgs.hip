@@ -41,6 +41,29 @@ __device__ __forceinline__ double xor_lane(double x, int lane) {
   } else return dpp_mov<0x128>(x);
 }
 
+// The 64-bit value of lane (lane ^ 16) (BIT = 16) or (lane ^ 32) (BIT = 32): the row swaps exchange
+// the odd 16-lane rows (upper 32-lane half) of their first operand with the even rows (lower
+// half) of their second; with the same value in both, the two results hold a lane's own value and
+// its partner's, in an order set by the lane's bit.
+template <int BIT>
+__device__ __forceinline__ double swap_lane(double x, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+  unsigned plo, phi;
+  if constexpr (BIT == 16) {
+    const auto rl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto rh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    plo = (lane & 16) ? rl[0] : rl[1];
+    phi = (lane & 16) ? rh[0] : rh[1];
+  } else {
+    const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    plo = (lane & 32) ? rl[0] : rl[1];
+    phi = (lane & 32) ? rh[0] : rh[1];
+  }
+  return __longlong_as_double((long long)(((unsigned long long)phi << 32) | plo));
+}
+
 // One halving level: each lane keeps one half of its NP values (by bit LVL of
 // its lane) and adds the partner's copy of that half.
 template <int LVL, int NP>
@@ -64,11 +87,11 @@ __device__ __forceinline__ void halve(double (&w)[NP], int lane) {
 // barrier; every thread gets the totals in tot[] (uniform values).  Inside a
 // 16-lane row the values are summed by halving exchanges (NP = next_pow2(NV)
 // values cost NP - 1 + 4 - log2(NP) exchanges; lane l then holds the value
-// whose index is the bit reversal of l's low log2(NP) bits); the 4 row sums
-// of each of the kMT / 64 waves go to lds[par] (par alternates by column, so a
-// wave one column ahead writes the other half), and after the barrier lane
-// j < NV of every wave adds the kMT / 16 row sums of value j and readlane
-// broadcasts the totals.
+// whose index is the bit reversal of l's low log2(NP) bits); two row swaps add
+// the wave's 4 row sums, row 0 of each of the kMT / 64 waves writes them to
+// lds[par] (par alternates by column, so a wave one column ahead writes the
+// other half), and after the barrier lane j < NV of every wave adds the
+// kMT / 64 wave sums of value j and readlane broadcasts the totals.
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds2, int par, double (&tot)[NV]) {
   constexpr int NP = next_pow2(NV);
@@ -88,18 +111,20 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds2, int par
   if constexpr (K <= 1) x += xor_lane<1>(x, lane);
   if constexpr (K <= 2) x += xor_lane<2>(x, lane);
   if constexpr (K <= 3) x += xor_lane<3>(x, lane);
-  if ((lane & 15) < NP) {
+  x += swap_lane<16>(x, lane);
+  x += swap_lane<32>(x, lane);
+  if (lane < NP) {
     int idx = 0;
 #pragma unroll
     for (int lvl = 0; lvl < K; ++lvl)
       if (lane & (1 << lvl)) idx += NP >> (lvl + 1);
-    if (idx < NV) lds[(wave * 4 + (lane >> 4)) * 16 + idx] = x;
+    if (idx < NV) lds[wave * 16 + idx] = x;
   }
   __syncthreads();
   double s[4] = {0, 0, 0, 0};
   if (lane < NV) {
 #pragma unroll
-    for (int q = 0; q < kMT / 16; ++q) s[q & 3] += lds[q * 16 + lane];
+    for (int q = 0; q < kMT / 64; ++q) s[q & 3] += lds[q * 16 + lane];
   }
   const double t = (s[0] + s[1]) + (s[2] + s[3]);
   const unsigned long long tb = (unsigned long long)__double_as_longlong(t);
