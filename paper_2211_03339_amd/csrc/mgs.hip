@@ -142,10 +142,11 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds2, int par
 // q_c . v_j = (v_c . v_j) / ||v_c||.  C is a compile-time column index so
 // that the register panel is never indexed dynamically.  Columns at or past
 // ncols (the short last panel) are zero and stay zero; FULL panels (ncols = P)
-// are compiled without the column tests.
+// are compiled without the column tests.  q_c is final once normalised and is
+// stored right away, so its stores drain while the later columns are worked.
 template <int R, int P, int C, bool FULL>
 __device__ __forceinline__ void mgs_column(double (&v)[R][P], int ncols, const double* nrm0, double* lds2,
-                                           int* flag) {
+                                           int* flag, double* __restrict__ Q, int m, int ldq) {
   if constexpr (C < P) {
     if (FULL || C < ncols) {
       constexpr int NV = P - C;
@@ -171,14 +172,18 @@ __device__ __forceinline__ void mgs_column(double (&v)[R][P], int ncols, const d
       // (within an ulp of the quotients; FP64 division is a long instruction sequence).
       const double inv = 1.0 / nrm;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r][C] = v[r][C] * inv;
+      for (int r = 0; r < R; ++r) {
+        v[r][C] = v[r][C] * inv;
+        const int i = threadIdx.x + r * kMT;
+        if (i < m) Q[i + (size_t)C * ldq] = v[r][C];
+      }
 #pragma unroll
       for (int j = 1; j < NV; ++j) {
         const double d = tot[j] * inv;
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r][C + j] = fma(-d, v[r][C], v[r][C + j]);
       }
-      mgs_column<R, P, C + 1, FULL>(v, ncols, nrm0, lds2, flag);
+      mgs_column<R, P, C + 1, FULL>(v, ncols, nrm0, lds2, flag, Q, m, ldq);
     }
   }
 }
@@ -198,14 +203,7 @@ __global__ void __launch_bounds__(kMT) mgs_panel_kernel(double* __restrict__ Q, 
     for (int c = 0; c < P; ++c) v[r][c] = (i < m && (FULL || c < ncols)) ? Q[i + (size_t)c * ldq] : 0.0;
   }
   __syncthreads();
-  mgs_column<R, P, 0, FULL>(v, ncols, n0, lds2, flag);
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    int i = threadIdx.x + r * kMT;
-#pragma unroll
-    for (int c = 0; c < P; ++c)
-      if (i < m && (FULL || c < ncols)) Q[i + (size_t)c * ldq] = v[r][c];
-  }
+  mgs_column<R, P, 0, FULL>(v, ncols, n0, lds2, flag, Q, m, ldq);
 }
 
 // Z_R -= Q_P (Q_P^T Z_R) in two launches over a grid of (16-column block,
