@@ -171,21 +171,25 @@ __device__ __forceinline__ void tile_vals16(const T* __restrict__ Tm, int ldt, i
 struct NoHook { __device__ void operator()() const {} };
 
 // The product of tile_product16 from the tile's values already in registers.  staged() runs
-// once every thread's tile values are in LDS (the workgroup has read the tile).
+// once every thread's tile values are in LDS (the workgroup has read the tile).  With
+// load_always the E operands are loaded even when the product is skipped, so that their loads
+// need not wait for what decides active.
 template <typename T, typename F = NoHook>
 __device__ __forceinline__ void tile_product16_vals(const T (&tv)[kPer16], const T* __restrict__ Ek,
                                                     const T* __restrict__ El, T* __restrict__ Bs, bool active,
-                                                    F staged = F()) {
+                                                    F staged = F(), bool load_always = false) {
   constexpr int kPer = kPer16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int bi = wave >> 2, bj = wave & 3, cc = lane & 15, kq = lane >> 4;
   typename Mfma<T>::acc_t acc;
   T fa[kB2 / 4], fb[kB2 / 4];
-  if (active) {
+  if (active || load_always) {
 #pragma unroll
     for (int q = 0; q < kB2 / 4; ++q) fa[q] = Ek[(q * 4 + kq) * kB2 + bi * 16 + cc];   // A(i, kk) = E_k(kk, i)
 #pragma unroll
     for (int q = 0; q < kB2 / 4; ++q) fb[q] = El[(q * 4 + kq) * kB2 + bj * 16 + cc];   // B(kk, j) = E_l(kk, j)
+  }
+  if (active) {
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int e = tid + q * kWT, kk = e % kB2, c = e / kB2;
@@ -291,13 +295,16 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
     const int A0 = rrb.index(ka, rv), A1 = rrb.index(rrb.h + ka, rv);
     const int B0 = rrb.index(kb, rv), B1 = rrb.index(rrb.h + kb, rv);
     const int hI = I == (swap ? B0 : A0) ? 0 : 1, hJ = J == (swap ? A0 : B0) ? 0 : 1;
-    const bool id = identv[ka] && identv[kb];
-    T sv[kPer];
+    // Every load is issued before the identity flags are known (all addresses are valid; when
+    // both pairs are the identity the tile is already current and only the product is skipped).
+    T sv[kPer], tv[kPer16];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int e = tid + q * kInnerThreads, a = e % kB2, c = e / kB2;
-      sv[q] = (id || (a < kH) == (c < kH)) ? Tm[gidx(a) + (size_t)gidx(c) * ldt] : T(0);
+      sv[q] = Tm[gidx(a) + (size_t)gidx(c) * ldt];
     }
+    tile_vals16<T>(Tm, ldt, A0 * kH, A1 * kH - kH, B0 * kH, B1 * kH - kH, tv);
+    const bool id = identv[ka] && identv[kb];
     T* Y = S[1];
     int* flag = reinterpret_cast<int*>(rs);
     // quarters (x, y), x of pair ka, y of pair kb, that pairs of this step read
@@ -308,8 +315,7 @@ __device__ __forceinline__ void inner_solve(int k, T* __restrict__ Tm, int ldt, 
     auto mark_read = [&]() {
       if (tid == 0 && !id && readers > 1) before = atomicAdd(tcount + ti, 1);
     };
-    tile_product16<T>(Tm, ldt, Ev + (size_t)ka * kB2 * kB2, Ev + (size_t)kb * kB2 * kB2, A0 * kH, A1 * kH - kH,
-                      B0 * kH, B1 * kH - kH, Y, !id, mark_read);
+    tile_product16_vals<T>(tv, Ev + (size_t)ka * kB2 * kB2, Ev + (size_t)kb * kB2 * kB2, Y, !id, mark_read, true);
     if (tid == 0 && !id) {
       const bool last = readers <= 1 || before == readers - 1;
       if (last && readers > 1) atomicExch(tcount + ti, 0);
