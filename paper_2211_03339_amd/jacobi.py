@@ -251,6 +251,24 @@ def syev_jacobi_warm(A: torch.Tensor, Q0: torch.Tensor, tol: float = 0.0, max_sw
     return W, Vb.t(), st.as_dict(), code
 
 
+def gesvd_jacobi(A: torch.Tensor, tol: float = 0.0):
+    """Algorithm 5.2 (FP32 Gram start) with default options on the null stream: returns
+    (S descending, U, V, sweeps, info)."""
+    L = load()
+    A = _dev(A)
+    m, n = A.shape
+    Ac = _colmajor(A)
+    S = torch.empty(n, dtype=torch.float64, device=A.device)
+    Ub = torch.empty((n, m), dtype=torch.float64, device=A.device)
+    Vb = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    sw = ctypes.c_int(0)
+    torch.cuda.synchronize()
+    code = L.gesvd_jacobi(_vp(Ac.data_ptr()), m, n, max(m, 1), _vp(S.data_ptr()), _vp(Ub.data_ptr()), max(m, 1),
+                          _vp(Vb.data_ptr()), max(n, 1), tol, ctypes.byref(sw))
+    _check("gesvd_jacobi", code, ok=(0, 1))
+    return S, Ub.t(), Vb.t(), sw.value, code
+
+
 def gesvd_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", max_sweeps=0, variant="auto",
                     allow_unconverged=False):
     """Thin SVD A = U diag(S) V^T (m >= n): returns (S descending, U, V, stats, info)."""

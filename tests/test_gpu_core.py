@@ -324,3 +324,36 @@ def test_blocked_n512_spectra(kind):
         W, V, st, info = jacobi.syev_jacobi_ex(dev(A), precond=pre, variant="blocked")
         errs = check_eig(A, host(W), host(V), lam, plain=pre == "none")
         print(f"[blocked n=512 {kind} {pre}] sweeps={st['sweeps']} {errs}", flush=True)
+
+
+def test_syev_jacobi_default_entry_point():
+    """The plain C entry point syev_jacobi (Algorithm 4.1, library defaults, null stream) against the
+    known spectrum and the oracle's eigenvalues."""
+    n = 150
+    A, lam = tm.sym_matrix(n, "geometric", seed=1001)
+    print(f"[syev_jacobi] n={n}", flush=True)
+    W, V, sweeps, info = jacobi.syev_jacobi(dev(A))
+    assert info == 0 and sweeps >= 1
+    W, V = host(W), host(V)
+    check_eig(A, W, V, lam)
+    ref = oracle.syev(A)
+    assert np.abs(W - ref.W).max() <= 1e-13 * np.abs(lam).max()
+
+
+@pytest.mark.parametrize("n", [256, 1024])
+def test_theorem_evd_ubd_at_fp32_convergence(n):
+    """Theorem evd-ubd with the paper's proxy bd = n ||A||_2 upsilon (Section 6, Table 6.1
+    discussion): when step 1 runs to FP32 convergence (off(T32) <= 1e-6 ||A||_F, or its sweep cap
+    where FP32 rounding stops it first), the start T0 = Q^T A Q has off(T0) within a small
+    multiple of bd.  The library's default stop (1e-4 ||A||_F) is a truncated start and is not
+    held to this bound."""
+    A, lam = tm.sym_matrix(n, "uniform", seed=1100 + n)
+    print(f"[evd-ubd] n={n}", flush=True)
+    W, V, st, info = jacobi.syev_jacobi_ex(dev(A), precond="fp32", fp32_tol=1e-6)
+    check_eig(A, host(W), host(V), lam)
+    bd = n * np.abs(lam).max() * 2.0 ** -24
+    print(f"  fp32_sweeps={st['fp32_sweeps']} off0={st['off0']:.3e} bd={bd:.3e} sweeps={st['sweeps']}",
+          flush=True)
+    assert st["off0"] <= 2 * bd
+    # and the FP64 stage is then in the paper's regime of a few sweeps (Tables 6.1, 6.3)
+    assert st["sweeps"] <= 4

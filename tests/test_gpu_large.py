@@ -89,3 +89,27 @@ def test_svd_8192_by_2048():
     assert dmax <= 1e-14, dmax
     assert cmax <= 4 * m * 2.0 ** -53, cmax
     assert s_err <= 1e-12, s_err
+
+
+@pytest.mark.parametrize("n", [1024, 2048])
+@pytest.mark.parametrize("kind", ["uniform", "geometric"])
+def test_element_variant_full_sizes(n, kind):
+    """The element-wise variant (n/2 disjoint 2x2 rotations per launch, T and V streamed through
+    HBM) end to end at full size, preconditioned: the path whose step kernel is placed on the HBM
+    roofline."""
+    print(f"[large element] n={n} {kind}", flush=True)
+    A, lam = tm.precond_case(n, kind)
+    Ad = torch.from_numpy(A).cuda()
+    W, V, st, _ = jacobi.syev_jacobi_ex(Ad, precond="fp32", variant="element")
+    res, orth, le = check_eig_dev(Ad, W, V, lam, raw_orth=n <= 1024)
+    print(f"  sweeps={st['sweeps']} fp32_sweeps={st['fp32_sweeps']} res={res:.2e} orth={orth:.2e} "
+          f"lam_err={le:.2e} ms={st['stage_ms']['total']:.1f}", flush=True)
+
+
+def test_element_variant_plain_n1024():
+    A, lam = tm.precond_case(1024, "uniform")
+    Ad = torch.from_numpy(A).cuda()
+    print("[large element] plain n=1024", flush=True)
+    W, V, st, _ = jacobi.syev_jacobi_ex(Ad, precond="none", variant="element")
+    res, orth, le = check_eig_dev(Ad, W, V, lam, raw_orth=False)
+    print(f"  sweeps={st['sweeps']} res={res:.2e} orth={orth:.2e} lam_err={le:.2e}", flush=True)

@@ -75,3 +75,17 @@ def test_svd_error_codes():
     with pytest.raises(jacobi.JacobiError) as e:
         jacobi.gesvd_jacobi_ex(dev(bad))
     assert e.value.code == 2
+
+
+def test_gesvd_jacobi_default_entry_point():
+    """The plain C entry point gesvd_jacobi (Algorithm 5.2, default options, null stream) against
+    the known singular values and the oracle's one-sided Jacobi."""
+    m, n = 300, 130
+    A, sig = tm.svd_case(m, n, decades=5.0, seed=77)
+    print(f"[gesvd_jacobi] {m}x{n}", flush=True)
+    S, U, V, sweeps, info = jacobi.gesvd_jacobi(dev(A))
+    assert info == 0 and sweeps >= 1
+    S, U, V = host(S), host(U), host(V)
+    check_svd(A, S, U, V, sig)
+    ref = oracle.gesvd(A)
+    assert np.abs(S - ref.S).max() <= 1e-12 * sig.max()

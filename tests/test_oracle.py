@@ -338,6 +338,45 @@ def test_mlp_oracle_adamw_closed_form():
     np.testing.assert_allclose(p1, p - 0.01 * (np.sign(gr) + 0.1 * p), rtol=1e-14)
 
 
+def test_mlp_oracle_adamw_constant_gradient_many_steps():
+    """AdamW at t >= 2.  With the same gradient g at every step the moments are m_t = (1 - b1^t) g
+    and v_t = (1 - b2^t) g^2 exactly, so the bias-corrected ratio m_hat / sqrt(v_hat) is sign(g) at
+    every step and the parameter follows p_t = (1 - lr wd) p_(t-1) - lr sign(g) (eps = 0).  A bias
+    correction written with b^t replaced by anything else (b t, b^(t-1), none) breaks m_hat = g
+    from t = 2 on and fails the moment checks; a decay that is not decoupled fails the path."""
+    from oracle import mlp
+    p0 = np.array([1.0, -2.0, 0.5, 3.0])
+    gr = np.array([0.3, -0.1, 2.0, -7.5])
+    lr, wd, b1, b2 = 0.01, 0.1, 0.9, 0.999
+    p, m, v = p0.copy(), np.zeros(4), np.zeros(4)
+    want = p0.copy()
+    for t in range(1, 8):
+        p, m, v = mlp.adamw(p, gr, m, v, t, lr=lr, wd=wd, b1=b1, b2=b2, eps=0.0)
+        want = (1 - lr * wd) * want - lr * np.sign(gr)
+        np.testing.assert_allclose(m, (1 - b1 ** t) * gr, rtol=1e-14)
+        np.testing.assert_allclose(v, (1 - b2 ** t) * gr * gr, rtol=1e-13)
+        np.testing.assert_allclose(m / (1 - b1 ** t), gr, rtol=1e-13)
+        np.testing.assert_allclose(p, want, rtol=1e-13, atol=1e-15)
+    # closed form of the whole path: p_t = c^t p_0 - lr sign(g) (1 - c^t) / (1 - c), c = 1 - lr wd
+    c = 1 - lr * wd
+    np.testing.assert_allclose(p, c ** 7 * p0 - lr * np.sign(gr) * (1 - c ** 7) / (1 - c), rtol=1e-13)
+
+
+def test_mlp_oracle_adamw_two_gradients_by_hand():
+    """Two steps with different gradients, worked by hand: t = 1 with g1, t = 2 with g2."""
+    from oracle import mlp
+    g1, g2 = 0.5, -0.25
+    b1, b2, lr = 0.9, 0.999, 0.1
+    p, m, v = mlp.adamw(np.array([0.0]), np.array([g1]), np.zeros(1), np.zeros(1), 1, lr=lr, wd=0.0,
+                        b1=b1, b2=b2, eps=0.0)
+    p, m, v = mlp.adamw(p, np.array([g2]), m, v, 2, lr=lr, wd=0.0, b1=b1, b2=b2, eps=0.0)
+    m2 = b1 * (1 - b1) * g1 + (1 - b1) * g2            # 0.045 - 0.025 = 0.02
+    v2 = b2 * (1 - b2) * g1 ** 2 + (1 - b2) * g2 ** 2
+    step2 = (m2 / (1 - b1 ** 2)) / np.sqrt(v2 / (1 - b2 ** 2))
+    assert abs(m[0] - 0.02) < 1e-15
+    np.testing.assert_allclose(p[0], -lr * 1.0 - lr * step2, rtol=1e-14)
+
+
 def test_canonical_signs():
     from oracle import mlp
     V = np.array([[0.6, -0.8], [-0.8, -0.6]])
