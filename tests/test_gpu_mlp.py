@@ -112,14 +112,21 @@ def test_gradients_at_full_size():
     net.close()
 
 
+def f32(x: float) -> float:
+    """x rounded to FP32 (as ctypes passes a float argument)."""
+    return float(np.float32(x))
+
+
 def test_adamw_steps_match_reference():
     """Four AdamW steps with the same gradients on both sides (set through the C-ABI, so the
     optimiser is compared alone), default eps: parameters and both moments entry by entry against
     the FP64 reference within the FP32 evaluation bound of mlp_bounds.adamw_bound."""
     I, H, n = SMALL
     net, p = make_net(I, H, n, 16)
-    net.set_adam(0.9, 0.999, 1e-8, 0)
-    lr, wd = 1e-2, 0.1
+    # the C-ABI takes the hyper-parameters as FP32: the reference runs at those same values (1 - b2
+    # magnifies the FP32 rounding of b2 = 0.999 about a thousandfold)
+    b1, b2, eps, lr, wd = (f32(x) for x in (0.9, 0.999, 1e-8, 1e-2, 0.1))
+    net.set_adam(b1, b2, eps, 0)
     g0 = tm.rng(33)
     P = net.P
     pr, mr, vr = p.astype(np.float64), np.zeros(P), np.zeros(P)
@@ -128,8 +135,8 @@ def test_adamw_steps_match_reference():
         gr = (g0.standard_normal(P) * 10.0 ** g0.uniform(-3, 1, P)).astype(np.float32)
         net.set(gr, jacobi.MLP_GRADS)
         net.adamw(lr, wd)
-        pr, mr, vr, ep, em, ev = mb.adamw_bound(pr, mr, vr, gr.astype(np.float64), t, lr, wd, 0.9, 0.999,
-                                                1e-8, ep, em, ev)
+        pr, mr, vr, ep, em, ev = mb.adamw_bound(pr, mr, vr, gr.astype(np.float64), t, lr, wd, b1, b2,
+                                                eps, ep, em, ev)
         p1 = net.get(jacobi.MLP_PARAMS).astype(np.float64)
         m1 = net.get(jacobi.MLP_MOMENT1).astype(np.float64)
         v1 = net.get(jacobi.MLP_MOMENT2).astype(np.float64)
@@ -149,19 +156,19 @@ def test_adamw_step_matches_reference():
     O = n * n
     B = 9
     net, p = make_net(I, H, n, 16)
-    net.set_adam(0.9, 0.999, 1.0, 0)
+    b1, b2, lr, wd = (f32(x) for x in (0.9, 0.999, 1e-2, 0.1))   # the FP32 values the C-ABI uses
+    net.set_adam(b1, b2, 1.0, 0)
     X = tm.mlp_inputs(B, I, seed=31)
     Tb = tm.bf16_bits((B, O), seed=32)
-    lr, wd = 1e-2, 0.1
     net.train_step(dev(X), dev(Tb), lr, wd)
     p1 = net.get(jacobi.MLP_PARAMS).astype(np.float64)
     assert net.shape()[4] == 1
     _, _, gr, eg = mb.grads(p.astype(np.float64), X.astype(np.float64), tm.bf16_value(Tb), I, H, O)
     z = np.zeros_like(gr)
-    pr, mr, vr = ref.adamw(p.astype(np.float64), gr, z, z, 1, lr, wd, eps=1.0)
+    pr, mr, vr = ref.adamw(p.astype(np.float64), gr, z, z, 1, lr, wd, b1=b1, b2=b2, eps=1.0)
     # t = 1: update = g / (|g| + 1), whose derivative in g is at most 1, so a gradient error eg moves
     # the parameter by at most lr eg (plus the FP32 evaluation of the step itself)
-    _, _, _, ep, _, _ = mb.adamw_bound(p.astype(np.float64), z, z, gr, 1, lr, wd, 0.9, 0.999, 1.0, z, z, z)
+    _, _, _, ep, _, _ = mb.adamw_bound(p.astype(np.float64), z, z, gr, 1, lr, wd, b1, b2, 1.0, z, z, z)
     assert np.all(np.abs(p1 - pr) <= lr * eg + 2 * ep)
     net.close()
 
