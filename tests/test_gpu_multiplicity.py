@@ -61,7 +61,10 @@ def test_multiple_eigenvalues_n1024(mode, kappa, variant):
     for pre in ("fp32", "none"):
         print(f"[ex6.2 n={n} mode={mode} kappa={kappa:g} {variant} {pre}]", flush=True)
         W, V, st, info = jacobi.syev_jacobi_ex(Ad, precond=pre, variant=variant)
-        res, orth, le = _check(A, W.cpu().numpy(), V.cpu().numpy(), lam, raw_orth=pre == "fp32")
+        # raw bar for the preconditioned blocked variant only: the element variant applies every
+        # rotation to V on its own and is held to the normalised form from n = 1024 on
+        res, orth, le = _check(A, W.cpu().numpy(), V.cpu().numpy(), lam,
+                               raw_orth=pre == "fp32" and variant == "blocked")
         sweeps[pre] = st["sweeps"]
         print(f"  sweeps={st['sweeps']} fp32_sweeps={st['fp32_sweeps']} res={res:.2e} orth={orth:.2e} "
               f"lam_err={le:.2e}", flush=True)
