@@ -111,6 +111,26 @@ int syev_jacobi(const double* A, int n, int lda, double* W, double* V, double to
 int syev_jacobi_ex(const double* A, int n, int lda, double* W, double* V, int ldv, double tol,
                    const jac_opts* opts, jac_stats* stats, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid allocation): syev_jacobi_ex with the
+ * library's pooled workspace replaced by a fixed device array of
+ * JAC_NOALLOC_BYTES, one per device, held from the library's load until the
+ * process ends.  The call allocates nothing (no device memory, no events):
+ *  - opts NULL or precond NONE / FP32 (other starts return -8);
+ *  - returns -2 ("n too large") when jac_workspace_bytes(n, opts) exceeds
+ *    JAC_NOALLOC_BYTES (about n <= 560 preconditioned, n <= 980 plain);
+ *  - stats (may be NULL): sweeps, rotations, norms and the off history are
+ *    filled; stage_ms, step_ms and kern_* stay zero (timing needs events);
+ *  - the GEMMs of Q^T A Q run without split-K (same sums, other order than
+ *    syev_jacobi_ex for small n).
+ * Every call on a device uses that device's one array and leaves its contents
+ * there; each call initialises what it reads.  Calls that overlap on one device
+ * (other host threads, other streams) race and must be serialised by the
+ * caller.  Synchronous like syev_jacobi_ex. */
+#define JAC_NOALLOC_BYTES ((size_t)32 << 20)
+int syev_jacobi_noalloc(const double* A, int n, int lda, double* W, double* V, int ldv, double tol,
+                        const jac_opts* opts, jac_stats* stats, void* stream);
+
 /* Resume / custom start (Algorithm 4.1 steps 2-4 from a given Q0): Q = MGS(Q0),
  * T = Q^T A Q, sweeps.  Q0: n x n, ldq >= n, read only. */
 int syev_jacobi_warm(const double* A, int n, int lda, const double* Q0, int ldq, double* W, double* V,

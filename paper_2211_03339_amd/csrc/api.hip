@@ -3,6 +3,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "../../include/jacobi.h"
@@ -214,8 +215,8 @@ static int elem_run(ElemState<T>& st, double tol, double nrm, int max_sweeps, hi
     if (!(off == off)) break;
   }
   if (rot_out) {
-    std::vector<unsigned long long> cnt(kRotSlots);
-    JAC_HIP(hipMemcpyAsync(cnt.data(), st.rot, kRotSlots * 8, hipMemcpyDeviceToHost, s));
+    unsigned long long cnt[kRotSlots];
+    JAC_HIP(hipMemcpyAsync(cnt, st.rot, kRotSlots * 8, hipMemcpyDeviceToHost, s));
     JAC_HIP(hipStreamSynchronize(s));
     long long tot = 0;
     for (int i = 0; i < sweeps; ++i) tot += (long long)cnt[i];
@@ -424,13 +425,15 @@ __global__ void transpose_kernel(const double* __restrict__ A, int n, int lda, d
   }
 }
 
+// no_split: the GEMMs take no split-K partial buffer (which the library allocates on demand).
 static int similarity(const double* A, int n, int lda, const double* Q, int ldq, double* T, int ldt, double* W,
-                      hipStream_t s) {
+                      hipStream_t s, bool no_split = false) {
   hipLaunchKernelGGL(transpose_kernel, dim3(cdiv(n, 32), cdiv(n, 32)), dim3(256), 0, s, Q, n, ldq, T, ldt);
   JAC_CHECK_LAUNCH();
-  int e = gemm<double>(false, false, n, n, n, 1.0, T, ldt, A, lda, 0.0, W, n, s);
+  const int ms = no_split ? 1 : 0;
+  int e = gemm<double>(false, false, n, n, n, 1.0, T, ldt, A, lda, 0.0, W, n, s, ms);
   if (e) return e;
-  e = gemm<double>(false, false, n, n, n, 1.0, W, n, Q, ldq, 0.0, T, ldt, s);
+  e = gemm<double>(false, false, n, n, n, 1.0, W, n, Q, ldq, 0.0, T, ldt, s, ms);
   if (e) return e;
   hipLaunchKernelGGL(mirror_upper_kernel, dim3(cdiv(n, 256), n), dim3(256), 0, s, T, n, ldt);
   JAC_CHECK_LAUNCH();
@@ -440,11 +443,16 @@ static int similarity(const double* A, int n, int lda, const double* Q, int ldq,
 static double default_tol(double tol) { return tol > 0 ? tol : 20.0 * 1.1102230246251565e-16; }
 
 // Shared driver of syev_jacobi_ex / syev_jacobi_warm.
+// fixed_ws (device, fixed_cap bytes): use it instead of the library's pooled workspace and create
+// no events (no stage or kernel timing), so that the call allocates nothing.
 static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq, double* W, double* V, int ldv,
-                     double tol, const jac_opts* opts, jac_stats* stats, hipStream_t s) {
+                     double tol, const jac_opts* opts, jac_stats* stats, hipStream_t s, void* fixed_ws = nullptr,
+                     size_t fixed_cap = 0) {
   jac_opts o{};
   if (opts) o = *opts;
   if (Q0) o.precond = -1;  // custom start
+  const bool fixed = fixed_ws != nullptr;
+  if (fixed) o.profile = 0;
   const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : kMaxSweepsDefault;
   tol = default_tol(tol);
   if (stats) {
@@ -461,10 +469,16 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
       return -8;
     }
   }
-  Timer tm(s, stats != nullptr);
+  Timer tm(s, stats != nullptr && !fixed);
   tm.mark(0);
   const int pre = o.precond;
-  void* ws = workspace(syev_bytes(n, pre == JAC_PRECOND_NONE ? 0 : 1));
+  const size_t need = syev_bytes(n, pre == JAC_PRECOND_NONE ? 0 : 1);
+  if (fixed && need > fixed_cap) {
+    set_error("syev_jacobi_noalloc: order n needs " + std::to_string(need) + " bytes of workspace, more than the " +
+              std::to_string(fixed_cap) + " of the fixed device array");
+    return -2;
+  }
+  void* ws = fixed ? fixed_ws : workspace(need);
   if (!ws) {
     set_error("syev_jacobi: workspace allocation failed");
     return 4;
@@ -568,7 +582,7 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
       double ms32 = 0;
       long long l32 = 0;
       e = fp32_stage(A, true, n, lda, nrm, tol32, max32, Vw, n, nullptr, c, hd, s, &sw32, &r32,
-                     stats ? &ms32 : nullptr, &l32, o.variant, o.inner_sweeps, pf);
+                     stats && !fixed ? &ms32 : nullptr, &l32, o.variant, o.inner_sweeps, pf);
       if (e) return e;
       if (stats) {
         stats->fp32_sweeps = sw32;
@@ -585,7 +599,7 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
       e = mgs_f64(Vw, n, n, n, mscr, hd.flag, s);
       if (e) return e;
       tm.mark(3);
-      e = similarity(A, n, lda, Vw, n, T0, n, Wg, s);
+      e = similarity(A, n, lda, Vw, n, T0, n, Wg, s, fixed);
       if (e) return e;
     }
     e = elem_pack<double>(st, T0, n, 0, s);
@@ -623,10 +637,11 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
     if (e) return e;
     info = blk_run<double>(bst, tol, nrm, max_sweeps, o.inner_sweeps > 0 ? o.inner_sweeps : kMaxInner64, s,
                            &sweeps, &off,
-                           stats ? stats->off_hist : nullptr, JAC_HIST, &rots, stats ? &ms64 : nullptr, &l64);
+                           stats ? stats->off_hist : nullptr, JAC_HIST, &rots, stats && !fixed ? &ms64 : nullptr,
+                           &l64);
   } else {
     info = elem_run<double>(st, tol, nrm, max_sweeps, s, &sweeps, &off, stats ? stats->off_hist : nullptr,
-                            JAC_HIST, &rots, stats ? &ms64 : nullptr, &l64);
+                            JAC_HIST, &rots, stats && !fixed ? &ms64 : nullptr, &l64);
   }
   if (info < 0 || info > 1) return info;
   tm.mark(5);
@@ -896,6 +911,55 @@ int syev_jacobi(const double* A, int n, int lda, double* W, double* V, double to
   e = syev_impl(A, n, lda, nullptr, 0, W, V, n > 1 ? n : 1, tol, &o, &st, nullptr);
   if (sweeps_out) *sweeps_out = st.sweeps;
   return e;
+}
+
+}  // extern "C"
+
+// Fixed device array of the allocation-free entry point.  In host code `scratch` names a host-side
+// stand-in: its device address (one copy per device) comes from hipGetSymbolAddress, taken once per
+// device with that device current, and only that address is handed to kernels and copies.
+static __device__ __align__(256) unsigned char scratch[JAC_NOALLOC_BYTES];
+static void* g_scratch_addr[256];
+static std::mutex g_scratch_mu;
+
+static int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 256) {
+    set_error("syev_jacobi_noalloc: no current device");
+    return 4;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    hipError_t rc = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (rc != hipSuccess || !p) {
+      set_error(std::string("syev_jacobi_noalloc: hipGetSymbolAddress failed: ") + hipGetErrorString(rc));
+      return 4;
+    }
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return 0;
+}
+
+extern "C" {
+
+int syev_jacobi_noalloc(const double* A, int n, int lda, double* W, double* V, int ldv, double tol,
+                        const jac_opts* opts, jac_stats* stats, void* stream) {
+  int e = check_syev_args(A, n, lda, W, V, ldv, tol);
+  if (e) return e;
+  if (opts && opts->precond != JAC_PRECOND_NONE && opts->precond != JAC_PRECOND_FP32) {
+    set_error("syev_jacobi_noalloc: only the plain and FP32-preconditioned starts are available");
+    return -8;
+  }
+  if (n == 0) {
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    return 0;
+  }
+  void* ws = nullptr;
+  e = scratch_address(&ws);
+  if (e) return e;
+  return syev_impl(A, n, lda, nullptr, 0, W, V, ldv, tol, opts, stats, as_stream(stream), ws, JAC_NOALLOC_BYTES);
 }
 
 int syev_jacobi_warm(const double* A, int n, int lda, const double* Q0, int ldq, double* W, double* V, int ldv,

@@ -336,10 +336,11 @@ template <typename T>
 int svd_sweep(T* C, int ldc, int mrows, T* V, int ldv, int n, int np, T* Ebuf, int* ident, T* Gpart, int gsplit,
               T rel, int max_inner, unsigned long long* rot, hipStream_t s);
 
-// GEMM (gemm.hip): C = alpha * op(A) * op(B) + beta * C, column-major.
+// GEMM (gemm.hip): C = alpha * op(A) * op(B) + beta * C, column-major.  max_split = 1 keeps K
+// whole (no split-K partial buffer, which is allocated on first need); 0 lets the GEMM choose.
 template <typename T>
 int gemm(bool ta, bool tb, int m, int n, int k, T alpha, const T* A, int lda, const T* B, int ldb,
-         T beta, T* C, int ldc, hipStream_t s);
+         T beta, T* C, int ldc, hipStream_t s, int max_split = 0);
 
 // Block modified Gram-Schmidt in place (mgs.hip).  Returns 0 or 3 on breakdown.
 int mgs_f64(double* Q, int m, int n, int ldq, double* scratch, int* flag, hipStream_t s);

@@ -164,9 +164,10 @@ static void launch_cfg(bool ta, bool tb, dim3 grid, hipStream_t s, int m, int n,
 static void* g_part = nullptr;
 static size_t g_part_bytes = 0;
 
+// max_split = 1: never split K (no partial-sum buffer, so nothing is allocated).
 template <typename T>
 int gemm(bool ta, bool tb, int m, int n, int k, T alpha, const T* A, int lda, const T* B, int ldb, T beta,
-         T* C, int ldc, hipStream_t s) {
+         T* C, int ldc, hipStream_t s, int max_split) {
   if (m <= 0 || n <= 0) return 0;
   if (k <= 0) {
     // C = beta C
@@ -185,7 +186,7 @@ int gemm(bool ta, bool tb, int m, int n, int k, T alpha, const T* A, int lda, co
   if (n <= 32) BN = 32;
   int tiles = cdiv(m, BM) * cdiv(n, BN);
   int S = 1;
-  if (tiles < cus && k >= 512) {
+  if (tiles < cus && k >= 512 && max_split != 1) {
     S = cdiv(2 * cus, tiles);
     int maxS = k / 256;
     if (S > maxS) S = maxS;
@@ -220,8 +221,8 @@ int gemm(bool ta, bool tb, int m, int n, int k, T alpha, const T* A, int lda, co
 }
 
 template int gemm<double>(bool, bool, int, int, int, double, const double*, int, const double*, int, double,
-                          double*, int, hipStream_t);
+                          double*, int, hipStream_t, int);
 template int gemm<float>(bool, bool, int, int, int, float, const float*, int, const float*, int, float, float*,
-                         int, hipStream_t);
+                         int, hipStream_t, int);
 
 }  // namespace jac

@@ -85,6 +85,8 @@ def load():
         "syev_jacobi": (_i, [_vp, _i, _i, _vp, _vp, _d, ctypes.POINTER(_i)]),
         "syev_jacobi_ex": (_i, [_vp, _i, _i, _vp, _vp, _i, _d, ctypes.POINTER(JacOpts),
                                 ctypes.POINTER(JacStats), _vp]),
+        "syev_jacobi_noalloc": (_i, [_vp, _i, _i, _vp, _vp, _i, _d, ctypes.POINTER(JacOpts),
+                                     ctypes.POINTER(JacStats), _vp]),
         "syev_jacobi_warm": (_i, [_vp, _i, _i, _vp, _i, _vp, _vp, _i, _d, ctypes.POINTER(JacOpts),
                                   ctypes.POINTER(JacStats), _vp]),
         "gesvd_jacobi": (_i, [_vp, _i, _i, _i, _vp, _vp, _i, _vp, _i, _d, ctypes.POINTER(_i)]),
@@ -222,6 +224,31 @@ def syev_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", variant="a
     code = L.syev_jacobi_ex(_vp(Ac.data_ptr()), n, max(n, 1), _vp(W.data_ptr()), _vp(Vb.data_ptr()),
                             max(n, 1), tol, ctypes.byref(o), ctypes.byref(st), _stream())
     _check("syev_jacobi_ex", code, ok=(0, 1) if allow_unconverged else (0,))
+    return W, Vb.t(), st.as_dict(), code
+
+
+def noalloc_bytes() -> int:
+    """JAC_NOALLOC_BYTES of include/jacobi.h: the fixed device array of syev_jacobi_noalloc."""
+    m = re.search(r"#define\s+JAC_NOALLOC_BYTES\s+\(\(size_t\)(\d+)\s*<<\s*(\d+)\)", open(HEADER).read())
+    return int(m.group(1)) << int(m.group(2))
+
+
+def syev_jacobi_noalloc(A: torch.Tensor, tol: float = 0.0, precond="fp32", variant="auto", max_sweeps=0,
+                        fp32_tol=0.0, inner_sweeps=0, check=True):
+    """The allocation-free variant of syev_jacobi_ex (workspace in the library's fixed device array).
+    Returns (W, V, stats dict, info); with check=False the return code is passed back unchecked."""
+    L = load()
+    A = _dev(A)
+    n = A.shape[0]
+    Ac = _colmajor(A)
+    W = torch.empty(n, dtype=torch.float64, device=A.device)
+    Vb = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    o = _opts(precond, variant, 0, max_sweeps, fp32_tol, inner_sweeps=inner_sweeps)
+    st = JacStats()
+    code = L.syev_jacobi_noalloc(_vp(Ac.data_ptr()), n, max(n, 1), _vp(W.data_ptr()), _vp(Vb.data_ptr()),
+                                 max(n, 1), tol, ctypes.byref(o), ctypes.byref(st), _stream())
+    if check:
+        _check("syev_jacobi_noalloc", code)
     return W, Vb.t(), st.as_dict(), code
 
 
