@@ -4,9 +4,12 @@ TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
 CPU-baseline leg are the only callers.  The product library never imports,
 links or executes anything here, and nothing here imports the product.
 
-The arithmetic lives in plain C (``oracle.c``, FP64, single-threaded); this
-module compiles it with gcc on first use and wraps it with ctypes and numpy.
-See ``oracle.c`` for the paper passage each routine follows.  ``mlp.py``
+The arithmetic lives in plain C (``oracle.c``: the Jacobi methods, MGS, GEMM,
+one-sided SVD; ``tridiag.c``: Householder tridiagonalization, Sturm bisection,
+inverse iteration and the back-transformation, the parts of the tridiagonal
+eigensolver the paper takes for step 1), FP64, single-threaded; this module
+compiles it with gcc on first use and wraps it with ctypes and numpy.  See the
+two C files for the paper passage each routine follows.  ``mlp.py``
 holds the FP64 reference of the learned warm-start network.
 """
 from __future__ import annotations
@@ -19,7 +22,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "jacobi_body.h")]
+_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "tridiag.c"), os.path.join(_HERE, "jacobi_body.h")]
 
 U64 = 2.0 ** -53
 U32 = 2.0 ** -24
@@ -33,7 +36,7 @@ def build(force: bool = False) -> str:
     if force or not fresh:
         tmp = _SO + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c99", "-ffp-contract=off",
-               "-fno-fast-math", "-o", tmp, _SRC[0], "-lm"]
+               "-fno-fast-math", "-o", tmp, _SRC[0], _SRC[1], "-lm"]
         subprocess.check_call(cmd, cwd=_HERE)
         os.replace(tmp, _SO)
     return _SO
@@ -78,6 +81,16 @@ def lib():
         L.or_svd_onesided.restype = c_int
         L.or_svd_finish.argtypes = [c_int, c_int, dp, c_int, dp, c_int, dp, dp, c_int, dp, c_int]
         L.or_svd_finish.restype = None
+        L.or_sytrd.argtypes = [c_int, dp, c_int, dp, dp, dp, dp, c_int]
+        L.or_sytrd.restype = c_int
+        L.or_sturm_count.argtypes = [c_int, dp, dp, c_d]
+        L.or_sturm_count.restype = c_int
+        L.or_tridiag_eigvals.argtypes = [c_int, dp, dp, dp]
+        L.or_tridiag_eigvals.restype = None
+        L.or_tridiag_vector.argtypes = [c_int, dp, dp, c_d, dp]
+        L.or_tridiag_vector.restype = c_int
+        L.or_apply_reflectors.argtypes = [c_int, dp, c_int, dp, dp, c_int, c_int]
+        L.or_apply_reflectors.restype = None
         _lib = L
     return _lib
 
@@ -248,3 +261,68 @@ def gesvd(A, tol: float = U64, ratio_stop: float = 2e-4, max_sweeps: int = 64,
     r = svd_onesided(A, np.eye(n), tol, ratio_stop, max_sweeps, order)
     S, U, V = svd_finish(r.C, r.V)
     return Result(S=S, U=U, V=V, info=r.info, sweeps=r.sweeps, rotations=r.rotations)
+
+
+# ---------------------------------------------------------------- tridiagonal route (tridiag.c)
+def sytrd(A):
+    """Householder tridiagonalization A = Q T Q^T: returns (d, e, tau, U) with U's column k the
+    reflector vector u_k (u_k(k+1) = 1, zero above) and Q = H_0 ... H_{n-3}."""
+    A = _colmajor(A)
+    n = A.shape[0]
+    d = np.zeros(n)
+    e = np.zeros(max(n - 1, 0) + 1)
+    tau = np.zeros(max(n, 1))
+    U = np.zeros((n, n), order="F")
+    if n:
+        lib().or_sytrd(n, _dp(A), max(n, 1), _dp(d), _dp(e), _dp(tau), _dp(U), max(n, 1))
+    return d, e[: max(n - 1, 0)], tau[: max(n - 2, 0)], U
+
+
+def _de(d, e):
+    d = np.ascontiguousarray(d, np.float64)
+    e = np.ascontiguousarray(np.append(np.asarray(e, np.float64), 0.0))
+    return d, e
+
+
+def sturm_count(d, e, x: float) -> int:
+    d, e = _de(d, e)
+    return lib().or_sturm_count(d.size, _dp(d), _dp(e), x)
+
+
+def tridiag_eigvals(d, e):
+    """All eigenvalues of the symmetric tridiagonal (d, e), ascending, by bisection."""
+    d, e = _de(d, e)
+    w = np.zeros(d.size)
+    lib().or_tridiag_eigvals(d.size, _dp(d), _dp(e), _dp(w))
+    return w
+
+
+def tridiag_vectors(d, e, w):
+    """Eigenvectors (columns) of (d, e) for the eigenvalues w, by inverse iteration."""
+    d, e = _de(d, e)
+    n = d.size
+    Z = np.zeros((n, len(w)), order="F")
+    z = np.zeros(n)
+    for k, lam in enumerate(w):
+        lib().or_tridiag_vector(n, _dp(d), _dp(e), float(lam), _dp(z))
+        Z[:, k] = z
+    return Z
+
+
+def apply_reflectors(U, tau, Y):
+    """Z = H_0 H_1 ... H_{n-3} Y (reflectors from sytrd)."""
+    U = _colmajor(U)
+    Z = _colmajor(Y).copy(order="F")
+    n, ncol = Z.shape
+    t = np.zeros(max(n, 1))
+    t[: len(tau)] = tau
+    lib().or_apply_reflectors(n, _dp(U), max(n, 1), _dp(t), _dp(Z), max(n, 1), ncol)
+    return Z
+
+
+def syev_tridiag(A):
+    """Eigendecomposition through the three parts: tridiagonalization, bisection and inverse
+    iteration on T, back-transformation.  Returns (W ascending, Z)."""
+    d, e, tau, U = sytrd(A)
+    w = tridiag_eigvals(d, e)
+    return w, apply_reflectors(U, tau, tridiag_vectors(d, e, w))
