@@ -46,12 +46,24 @@ typedef enum {
   JAC_VARIANT_BLOCKED = 2  /* 2b x 2b block rotations applied as GEMMs */
 } jac_variant_t;
 
+/* Solver of the low-precision step 1 (Algorithm 4.1 step 1; the paper uses a
+ * LAPACK-style tridiagonal FP32 eigensolver there, Section 6 setup, and needs
+ * only its backward stability, Lemma symeig). */
+typedef enum {
+  JAC_STAGE1_AUTO = 0,     /* tridiagonal for 16 <= n <= 2048, else Jacobi */
+  JAC_STAGE1_JACOBI = 1,   /* FP32 cyclic Jacobi (the same sweep kernels in float), stopped at
+                              fp32_tol ||A||_F: a truncated start (default fp32_tol 1e-4) */
+  JAC_STAGE1_TRIDIAG = 2   /* FP32 Householder tridiagonalization, FP64 bisection and
+                              twisted-factorization eigenvectors of T, FP32 back-transformation;
+                              n <= 8192 (larger orders use Jacobi) */
+} jac_stage1_t;
+
 struct jac_mlp;
 
 typedef struct jac_opts {
   int precond;         /* jac_precond_t; default (zeroed struct) = NONE */
   int variant;         /* jac_variant_t */
-  int block_b;         /* block size b of the blocked variant; 0 = library choice */
+  int block_b;         /* reserved, must be 0 (the blocked variant uses 2b = 64) */
   int max_sweeps;      /* FP64 sweeps; <= 0 means 64 */
   double fp32_tol;     /* FP32 stage stops at off(T32) <= fp32_tol ||A||_F; <= 0: default
                           (1e-4 for syev_jacobi_ex, 1e-6 for the Gram matrix of gesvd_jacobi_ex) */
@@ -61,6 +73,7 @@ typedef struct jac_opts {
   double fallback_tol; /* MLP start rejected if off(Q^T A Q)_F / ||A||_F > this; <= 0: 1e-2 */
   int inner_sweeps;    /* blocked variant: cap on the sweeps of each 2b x 2b subproblem; <= 0: default */
   int profile;         /* nonzero: time every sweep launch with HIP events into jac_stats.kern_* */
+  int stage1;          /* jac_stage1_t: solver of the FP32 step 1 (FP32 start and fallback) */
 } jac_opts;
 
 #define JAC_HIST 65
@@ -95,6 +108,7 @@ typedef struct jac_stats {
   long long kern_launches[6];
   long long kern_work[6];
   double start_resid;      /* precond MLP: ||off(Q^T A Q)||_F / ||A||_F of the predicted start */
+  int fp32_method;         /* step 1 that ran: 0 none, 1 FP32 Jacobi, 2 tridiagonal */
 } jac_stats;
 
 /* Symmetric eigendecomposition A = V diag(W) V^T by Algorithm 4.1
@@ -118,7 +132,7 @@ int syev_jacobi_ex(const double* A, int n, int lda, double* W, double* V, int ld
  * process ends.  The call allocates nothing (no device memory, no events):
  *  - opts NULL or precond NONE / FP32 (other starts return -8);
  *  - returns -2 ("n too large") when jac_workspace_bytes(n, opts) exceeds
- *    JAC_NOALLOC_BYTES (about n <= 560 preconditioned, n <= 980 plain);
+ *    JAC_NOALLOC_BYTES (n <= 640 preconditioned, n <= 995 plain);
  *  - stats (may be NULL): sweeps, rotations, norms and the off history are
  *    filled; stage_ms, step_ms and kern_* stay zero (timing needs events);
  *  - the GEMMs of Q^T A Q run without split-K (same sums, other order than
@@ -270,12 +284,32 @@ int jac_mgs(double* Q, int m, int n, int ldq, void* stream);
 int jac_similarity(const double* A, int n, int lda, const double* Q, int ldq, double* T, int ldt,
                    void* stream);
 
-/* Low-precision step 1: FP32 eigenvectors of A (demoted to FP32), stored in
- * FP64.  Z: n x n (ldz >= n); W (may be NULL): FP32 eigenvalues promoted,
+/* Low-precision step 1 by the FP32 Jacobi stage (JAC_STAGE1_JACOBI): FP32
+ * eigenvectors of A (demoted to FP32), stored in FP64.  Z: n x n (ldz >= n); W (may be NULL): FP32 eigenvalues promoted,
  * ascending, with Z's columns in the same order.  tol <= 0: default.
  * sweeps (host, may be NULL). */
 int jac_eig_fp32(const double* A, int n, int lda, double* Z, int ldz, double* W, double tol,
                  int max_sweeps, int* sweeps, void* stream);
+
+/* Parts of the tridiagonal step 1 (JAC_STAGE1_TRIDIAG), each as the pipeline
+ * runs it:
+ * jac_sytrd_f32: Householder tridiagonalization of fl32(A) in FP32 (A n x n
+ *   FP64, lda): Q^T A Q = T with d (n), e (n - 1) holding T's FP32 entries in
+ *   FP64, and the reflectors H_k = I - tau(k) u_k u_k^T, k < n - 2, as tau
+ *   (FP32, n - 2) and U (FP32, n x (n - 2), ldu >= n; column k = u_k with
+ *   u_k(k+1) = 1 and zeros above), Q = H_0 ... H_{n-3}.  One cooperative
+ *   launch; returns 4 if the device cannot run it.  n <= 8192.
+ * jac_tridiag_eig: eigenvalues w (FP64, ascending) of the symmetric
+ *   tridiagonal (d, e) by bisection, and if Z is not NULL the eigenvectors
+ *   (FP64, n x n, ldz) by twisted factorization.  All pointers device.
+ * jac_tridiag_backtransform: Y <- H_0 ... H_{n-3} Y (Y FP64 n x n, ldy,
+ *   computed in FP32) for reflectors as returned by jac_sytrd_f32.
+ * jac_eig_fp32_tridiag: the whole step: Z (FP64, ldz) eigenvectors of fl32(A)
+ *   in ascending order of W (FP64, may be NULL). */
+int jac_sytrd_f32(const double* A, int n, int lda, double* d, double* e, float* tau, float* U, int ldu, void* stream);
+int jac_tridiag_eig(const double* d, const double* e, int n, double* w, double* Z, int ldz, void* stream);
+int jac_tridiag_backtransform(const float* U, int ldu, const float* tau, int n, double* Y, int ldy, void* stream);
+int jac_eig_fp32_tridiag(const double* A, int n, int lda, double* Z, int ldz, double* W, void* stream);
 
 /* C = alpha op(A) op(B) + beta C on the matrix cores (FP64 / FP32). */
 int jac_gemm_f64(int transa, int transb, int m, int n, int k, double alpha, const double* A, int lda,

@@ -116,9 +116,18 @@ static size_t blk_bytes(int n) {
   return b;
 }
 
+// Workspace of the FP32 step 1: the larger of the Jacobi stage (blocked or element) and the
+// tridiagonal route, plus an FP64 eigenvalue buffer.
+static size_t stage1_bytes(int n) {
+  size_t jac32 = blk_bytes<float>(n) + elem_bytes<float>(n) + 2 * align_up((size_t)n * n * 4, 256) +
+                 align_up((size_t)n * 4, 256);
+  size_t tri = tridiag_bytes(n);
+  return (jac32 > tri ? jac32 : tri) + align_up((size_t)n * 8, 256) + 4 * 256;
+}
+
 static size_t syev_bytes(int n, int precond) {
   size_t b = 0;
-  b += blk_bytes<double>(n) + (precond != JAC_PRECOND_NONE ? blk_bytes<float>(n) : 0);
+  b += blk_bytes<double>(n);
   b += 4096 + 1024 * 8 + 2 * kRotSlots * 8 + align_up((size_t)n * 4, 256) + 256;
   b += elem_bytes<double>(n);
   b += align_up((size_t)n * n * 8, 256);           // Vw
@@ -126,10 +135,7 @@ static size_t syev_bytes(int n, int precond) {
   if (precond != JAC_PRECOND_NONE) {
     b += 2 * align_up((size_t)n * n * 8, 256);     // GEMM scratch W, T0
     b += align_up(mgs_scratch_elems(n, n) * 8, 256);
-    b += elem_bytes<float>(n);
-    b += align_up((size_t)n * n * 4, 256);         // V32
-    b += align_up((size_t)n * n * 4, 256);         // A32
-    b += align_up((size_t)n * 4, 256);
+    b += stage1_bytes(n);
   }
   return b + 64 * 256;
 }
@@ -338,10 +344,39 @@ struct Timer {
 // FP32 stage (Algorithm 4.1 step 1): eigenvectors of fl32(A) by the FP32
 // element-wise round-robin Jacobi.  Z (FP64, n x n, ldz) receives them in
 // working (unsorted) order; d32 (device, may be NULL) the FP32 diagonal.
+// The library's choice: the tridiagonal route where its reduction keeps the working rows in the
+// registers of 256-thread workgroups (16 <= n <= 2048), the FP32 Jacobi stage elsewhere.
+static bool use_tridiag(int stage1, int n) {
+  if (!tridiag_supported(n)) return false;
+  if (stage1 == JAC_STAGE1_TRIDIAG) return true;
+  return stage1 == JAC_STAGE1_AUTO && n >= 16 && n <= 2048;
+}
+
+// stage1: jac_stage1_t; *method receives the solver that ran (1 Jacobi, 2 tridiagonal).  The
+// tridiagonal route returns Z in ascending order of the eigenvalues of T (no sweeps); no_split
+// keeps its GEMMs free of split-K buffers.
 static int fp32_stage(const void* A, bool a_dbl, int n, int lda, double nrmA, double tol32, int max32, double* Z,
                       int ldz, float* d32, Carve& c, Head& hd, hipStream_t s, int* sweeps, long long* rots,
                       double* step_ms = nullptr, long long* launches = nullptr, int variant = 0,
-                      int inner = 0, Prof* prof = nullptr) {
+                      int inner = 0, Prof* prof = nullptr, int stage1 = JAC_STAGE1_JACOBI, int* method = nullptr,
+                      bool no_split = false) {
+  if (use_tridiag(stage1, n)) {
+    if (method) *method = 2;
+    if (sweeps) *sweeps = 0;
+    if (rots) *rots = 0;
+    if (launches) *launches = 0;
+    if (step_ms) *step_ms = 0;
+    double* w = d32 ? c.take<double>(n) : nullptr;
+    int e = a_dbl ? eig_tridiag_f32<double>((const double*)A, n, lda, Z, ldz, w, c, s, no_split)
+                  : eig_tridiag_f32<float>((const float*)A, n, lda, Z, ldz, w, c, s, no_split);
+    if (e) return e;
+    if (d32) {
+      e = copy_convert<double, float>(w, n, 1, n, d32, n, s);
+      if (e) return e;
+    }
+    return 0;
+  }
+  if (method) *method = 1;
   if (use_blocked(variant, n)) {
     BlkState<float> st;
     carve_blk(c, st, n);
@@ -458,6 +493,14 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
   }
+  if (o.block_b != 0) {
+    set_error("syev_jacobi_ex: opts.block_b is reserved and must be 0");
+    return -8;
+  }
+  if (o.stage1 < JAC_STAGE1_AUTO || o.stage1 > JAC_STAGE1_TRIDIAG) {
+    set_error("syev_jacobi_ex: opts.stage1 must be a jac_stage1_t");
+    return -8;
+  }
   if (n == 0) return 0;
   if (o.precond == JAC_PRECOND_MLP) {
     if (!o.mlp || !o.theta) {
@@ -538,6 +581,8 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
     T0p = T0;
     double* mscr = c.take<double>(mgs_scratch_elems(n, n));
     bool accepted = false;
+    bool mgs_done = false;   // the tridiagonal start is orthogonalised inside the stage-1 block
+    int method1 = 0;
     if (pre == JAC_PRECOND_MLP) {
       // Learned start: Z -> MGS -> T = Q^T A Q; kept when ||off(T)||_F / ||A||_F <= fallback_tol
       // and MGS met no zero column, else replaced by the FP32 start.
@@ -581,23 +626,46 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
       long long r32 = 0;
       double ms32 = 0;
       long long l32 = 0;
+      Carve c1 = c;   // the FP32 stage's carve, reused if it has to run again
       e = fp32_stage(A, true, n, lda, nrm, tol32, max32, Vw, n, nullptr, c, hd, s, &sw32, &r32,
-                     stats && !fixed ? &ms32 : nullptr, &l32, o.variant, o.inner_sweeps, pf);
+                     stats && !fixed ? &ms32 : nullptr, &l32, o.variant, o.inner_sweeps, pf, o.stage1, &method1,
+                     fixed);
       if (e) return e;
+      if (method1 == 2) {
+        // A tridiagonal start whose columns MGS cannot orthogonalise (a zero column: eigenvectors of
+        // T computed for numerically equal eigenvalues) is replaced by the FP32 Jacobi start.
+        tm.mark(2);
+        e = mgs_f64(Vw, n, n, n, mscr, hd.flag, s);
+        if (e) return e;
+        JAC_HIP(hipMemcpyAsync(&hflag, hd.flag, 4, hipMemcpyDeviceToHost, s));
+        JAC_HIP(hipStreamSynchronize(s));
+        mgs_done = hflag == 0;
+        if (hflag) {
+          JAC_HIP(hipMemsetAsync(hd.flag, 0, 16 * sizeof(int), s));
+          c = c1;
+          e = fp32_stage(A, true, n, lda, nrm, tol32, max32, Vw, n, nullptr, c, hd, s, &sw32, &r32,
+                         stats && !fixed ? &ms32 : nullptr, &l32, o.variant, o.inner_sweeps, pf,
+                         JAC_STAGE1_JACOBI, &method1, fixed);
+          if (e) return e;
+        }
+      }
       if (stats) {
         stats->fp32_sweeps = sw32;
         stats->fp32_rotations = r32;
         stats->fp32_step_ms = ms32;
         stats->fp32_step_launches = l32;
+        stats->fp32_method = method1;
       }
     } else {
       e = copy_convert<double, double>(Q0, n, n, ldq, Vw, n, s);
       if (e) return e;
     }
     if (!accepted) {
-      tm.mark(2);
-      e = mgs_f64(Vw, n, n, n, mscr, hd.flag, s);
-      if (e) return e;
+      if (!mgs_done) {
+        tm.mark(2);
+        e = mgs_f64(Vw, n, n, n, mscr, hd.flag, s);
+        if (e) return e;
+      }
       tm.mark(3);
       e = similarity(A, n, lda, Vw, n, T0, n, Wg, s, fixed);
       if (e) return e;
@@ -710,6 +778,7 @@ static size_t gesvd_bytes(int m, int n, int precond) {
     b += align_up((size_t)n * n * 8, 256);                                      // Z / Q
     b += align_up(mgs_scratch_elems(n, n) * 8, 256);
     b += syev_bytes(n, 1);                                                      // FP32 eig work
+    b += stage1_bytes(n);
   }
   return b;
 }
@@ -731,6 +800,11 @@ static int gesvd_impl(const double* A, int m, int n, int lda, double* S, double*
   tm.mark(0);
   const int pre = o.precond;
   if (pre == JAC_PRECOND_MLP) { set_error("gesvd_jacobi: no learned start for the SVD"); return -10; }
+  if (o.block_b != 0) { set_error("gesvd_jacobi_ex: opts.block_b is reserved and must be 0"); return -11; }
+  if (o.stage1 < JAC_STAGE1_AUTO || o.stage1 > JAC_STAGE1_TRIDIAG) {
+    set_error("gesvd_jacobi_ex: opts.stage1 must be a jac_stage1_t");
+    return -11;
+  }
   void* ws = workspace(gesvd_bytes(m, n, pre));
   if (!ws) { set_error("gesvd_jacobi: workspace allocation failed"); return 4; }
   Carve c(ws);
@@ -781,10 +855,11 @@ static int gesvd_impl(const double* A, int m, int n, int lda, double* S, double*
     int max32 = o.fp32_max_sweeps > 0 ? o.fp32_max_sweeps : 30;
     int sw32 = 0;
     long long r32 = 0;
+    int method1 = 0;
     e = fp32_stage(G32, false, n, n, nrm * nrm, tol32, max32, Z, n, nullptr, c, hd, s, &sw32, &r32, nullptr,
-                   nullptr, o.variant, o.inner_sweeps);
+                   nullptr, o.variant, o.inner_sweeps, nullptr, o.stage1, &method1);
     if (e) return e;
-    if (stats) { stats->fp32_sweeps = sw32; stats->fp32_rotations = r32; }
+    if (stats) { stats->fp32_sweeps = sw32; stats->fp32_rotations = r32; stats->fp32_method = method1; }
     tm.mark(2);
     e = mgs_f64(Z, n, n, n, mscr, hd.flag, s);   // step 2
     if (e) return e;
@@ -1174,6 +1249,61 @@ int jac_eig_fp32(const double* A, int n, int lda, double* Z, int ldz, double* W,
   }
   JAC_HIP(hipStreamSynchronize(s));
   if (sweeps) *sweeps = sw;
+  return 0;
+}
+
+int jac_sytrd_f32(const double* A, int n, int lda, double* d, double* e, float* tau, float* U, int ldu, void* stream) {
+  g_err.clear();
+  if (!A && n > 0) { set_error("A is NULL"); return -1; }
+  if (n < 0 || n > 8192) { set_error("need 0 <= n <= 8192"); return -2; }
+  if (lda < (n > 1 ? n : 1)) { set_error("lda < max(1,n)"); return -3; }
+  if (!d && n > 0) { set_error("d is NULL"); return -4; }
+  if (!e && n > 1) { set_error("e is NULL"); return -5; }
+  if (!tau && n > 2) { set_error("tau is NULL"); return -6; }
+  if (!U && n > 2) { set_error("U is NULL"); return -7; }
+  if (ldu < (n > 1 ? n : 1)) { set_error("ldu < max(1,n)"); return -8; }
+  if (n == 0) return 0;
+  return tridiag_reduce_entry(A, n, lda, d, e, tau, U, ldu, as_stream(stream));
+}
+
+int jac_tridiag_eig(const double* d, const double* e, int n, double* w, double* Z, int ldz, void* stream) {
+  g_err.clear();
+  if (!d && n > 0) { set_error("d is NULL"); return -1; }
+  if (!e && n > 1) { set_error("e is NULL"); return -2; }
+  if (n < 0) { set_error("n < 0"); return -3; }
+  if (!w && n > 0) { set_error("w is NULL"); return -4; }
+  if (Z && ldz < (n > 1 ? n : 1)) { set_error("ldz < max(1,n)"); return -6; }
+  if (n == 0) return 0;
+  return tridiag_eig_entry(d, e, n, w, Z, ldz, as_stream(stream));
+}
+
+int jac_tridiag_backtransform(const float* U, int ldu, const float* tau, int n, double* Y, int ldy, void* stream) {
+  g_err.clear();
+  if (!U && n > 2) { set_error("U is NULL"); return -1; }
+  if (ldu < (n > 1 ? n : 1)) { set_error("ldu < max(1,n)"); return -2; }
+  if (!tau && n > 2) { set_error("tau is NULL"); return -3; }
+  if (n < 0 || n > 8192) { set_error("need 0 <= n <= 8192"); return -4; }
+  if (!Y && n > 0) { set_error("Y is NULL"); return -5; }
+  if (ldy < (n > 1 ? n : 1)) { set_error("ldy < max(1,n)"); return -6; }
+  if (n == 0) return 0;
+  return tridiag_backtransform_entry(U, ldu, tau, n, Y, ldy, as_stream(stream));
+}
+
+int jac_eig_fp32_tridiag(const double* A, int n, int lda, double* Z, int ldz, double* W, void* stream) {
+  g_err.clear();
+  if (!A && n > 0) { set_error("A is NULL"); return -1; }
+  if (n < 0 || n > 8192) { set_error("need 0 <= n <= 8192"); return -2; }
+  if (lda < (n > 1 ? n : 1)) { set_error("lda < max(1,n)"); return -3; }
+  if (!Z && n > 0) { set_error("Z is NULL"); return -4; }
+  if (ldz < (n > 1 ? n : 1)) { set_error("ldz < max(1,n)"); return -5; }
+  if (n == 0) return 0;
+  hipStream_t s = as_stream(stream);
+  void* ws = workspace(tridiag_bytes(n) + 4096);
+  if (!ws) { set_error("workspace allocation failed"); return 4; }
+  Carve c(ws);
+  int e = eig_tridiag_f32<double>(A, n, lda, Z, ldz, W, c, s, false);
+  if (e) return e;
+  JAC_HIP(hipStreamSynchronize(s));
   return 0;
 }
 

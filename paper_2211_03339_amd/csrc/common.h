@@ -342,6 +342,18 @@ template <typename T>
 int gemm(bool ta, bool tb, int m, int n, int k, T alpha, const T* A, int lda, const T* B, int ldb,
          T beta, T* C, int ldc, hipStream_t s, int max_split = 0);
 
+// Tridiagonal FP32 eigensolver (tridiag.hip): step 1 of Algorithm 4.1 through Householder
+// tridiagonalization, bisection, twisted-factorization eigenvectors and the back-transformation.
+size_t tridiag_bytes(int n);
+bool tridiag_supported(int n);
+template <typename TA>
+int eig_tridiag_f32(const TA* A, int n, int lda, double* Z, int ldz, double* w_out, Carve& c, hipStream_t s,
+                    bool no_split);
+int tridiag_reduce_entry(const double* A, int n, int lda, double* d, double* e, float* tau, float* U, int ldu,
+                         hipStream_t s);
+int tridiag_eig_entry(const double* d, const double* e, int n, double* w, double* Z, int ldz, hipStream_t s);
+int tridiag_backtransform_entry(const float* U, int ldu, const float* tau, int n, double* Y, int ldy, hipStream_t s);
+
 // Block modified Gram-Schmidt in place (mgs.hip).  Returns 0 or 3 on breakdown.
 int mgs_f64(double* Q, int m, int n, int ldq, double* scratch, int* flag, hipStream_t s);
 size_t mgs_scratch_elems(int m, int n);

@@ -25,6 +25,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "jacobi.h")
 
 PRECOND = {"none": 0, "fp32": 1, "mlp": 2}
 VARIANT = {"auto": 0, "element": 1, "blocked": 2}
+STAGE1 = {"auto": 0, "jacobi": 1, "tridiag": 2}
 JAC_HIST = 65
 
 
@@ -33,7 +34,7 @@ class JacOpts(ctypes.Structure):
                 ("max_sweeps", ctypes.c_int), ("fp32_tol", ctypes.c_double),
                 ("fp32_max_sweeps", ctypes.c_int), ("mlp", ctypes.c_void_p),
                 ("theta", ctypes.c_void_p), ("fallback_tol", ctypes.c_double),
-                ("inner_sweeps", ctypes.c_int), ("profile", ctypes.c_int)]
+                ("inner_sweeps", ctypes.c_int), ("profile", ctypes.c_int), ("stage1", ctypes.c_int)]
 
 
 class JacStats(ctypes.Structure):
@@ -45,7 +46,8 @@ class JacStats(ctypes.Structure):
                 ("step_ms", ctypes.c_double), ("step_launches", ctypes.c_longlong),
                 ("fp32_step_ms", ctypes.c_double), ("fp32_step_launches", ctypes.c_longlong),
                 ("kern_ms", ctypes.c_double * 6), ("kern_launches", ctypes.c_longlong * 6),
-                ("kern_work", ctypes.c_longlong * 6), ("start_resid", ctypes.c_double)]
+                ("kern_work", ctypes.c_longlong * 6), ("start_resid", ctypes.c_double),
+                ("fp32_method", ctypes.c_int)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_
@@ -103,6 +105,10 @@ def load():
         "jac_mgs": (_i, [_vp, _i, _i, _i, _vp]),
         "jac_similarity": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp]),
         "jac_eig_fp32": (_i, [_vp, _i, _i, _vp, _i, _vp, _d, _i, ctypes.POINTER(_i), _vp]),
+        "jac_sytrd_f32": (_i, [_vp, _i, _i, _vp, _vp, _vp, _vp, _i, _vp]),
+        "jac_tridiag_eig": (_i, [_vp, _vp, _i, _vp, _vp, _i, _vp]),
+        "jac_tridiag_backtransform": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp]),
+        "jac_eig_fp32_tridiag": (_i, [_vp, _i, _i, _vp, _i, _vp, _vp]),
         "jac_gemm_f64": (_i, [_i, _i, _i, _i, _i, _d, _vp, _i, _vp, _i, _d, _vp, _i, _vp]),
         "jac_gemm_f32": (_i, [_i, _i, _i, _i, _i, ctypes.c_float, _vp, _i, _vp, _i, ctypes.c_float,
                               _vp, _i, _vp]),
@@ -171,8 +177,9 @@ def _colmajor(M: torch.Tensor) -> torch.Tensor:
 
 
 def _opts(precond="fp32", variant="auto", block_b=0, max_sweeps=0, fp32_tol=0.0, fp32_max_sweeps=0,
-          fallback_tol=0.0, inner_sweeps=0, profile=0, mlp=None, theta=None):
+          fallback_tol=0.0, inner_sweeps=0, profile=0, mlp=None, theta=None, stage1="auto"):
     o = JacOpts()
+    o.stage1 = STAGE1[stage1] if isinstance(stage1, str) else int(stage1)
     if mlp is not None:
         o.mlp = mlp.h.value
     if theta is not None:
@@ -207,7 +214,7 @@ def syev_jacobi(A: torch.Tensor, tol: float = 0.0):
 
 def syev_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", variant="auto", max_sweeps=0,
                    fp32_tol=0.0, fp32_max_sweeps=0, block_b=0, allow_unconverged=False, inner_sweeps=0,
-                   mlp=None, theta=None, fallback_tol=0.0, profile=0):
+                   mlp=None, theta=None, fallback_tol=0.0, profile=0, stage1="auto"):
     """Returns (W, V, stats dict, info).  precond="mlp" takes the network `mlp` (Mlp) and its
     input `theta` (device float32 tensor of n_in values)."""
     if theta is not None:
@@ -219,7 +226,7 @@ def syev_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", variant="a
     W = torch.empty(n, dtype=torch.float64, device=A.device)
     Vb = torch.empty((n, n), dtype=torch.float64, device=A.device)
     o = _opts(precond, variant, block_b, max_sweeps, fp32_tol, fp32_max_sweeps, fallback_tol=fallback_tol,
-              inner_sweeps=inner_sweeps, profile=profile, mlp=mlp, theta=theta)
+              inner_sweeps=inner_sweeps, profile=profile, mlp=mlp, theta=theta, stage1=stage1)
     st = JacStats()
     code = L.syev_jacobi_ex(_vp(Ac.data_ptr()), n, max(n, 1), _vp(W.data_ptr()), _vp(Vb.data_ptr()),
                             max(n, 1), tol, ctypes.byref(o), ctypes.byref(st), _stream())
@@ -234,7 +241,7 @@ def noalloc_bytes() -> int:
 
 
 def syev_jacobi_noalloc(A: torch.Tensor, tol: float = 0.0, precond="fp32", variant="auto", max_sweeps=0,
-                        fp32_tol=0.0, inner_sweeps=0, check=True):
+                        fp32_tol=0.0, inner_sweeps=0, check=True, stage1="auto"):
     """The allocation-free variant of syev_jacobi_ex (workspace in the library's fixed device array).
     Returns (W, V, stats dict, info); with check=False the return code is passed back unchecked."""
     L = load()
@@ -243,7 +250,7 @@ def syev_jacobi_noalloc(A: torch.Tensor, tol: float = 0.0, precond="fp32", varia
     Ac = _colmajor(A)
     W = torch.empty(n, dtype=torch.float64, device=A.device)
     Vb = torch.empty((n, n), dtype=torch.float64, device=A.device)
-    o = _opts(precond, variant, 0, max_sweeps, fp32_tol, inner_sweeps=inner_sweeps)
+    o = _opts(precond, variant, 0, max_sweeps, fp32_tol, inner_sweeps=inner_sweeps, stage1=stage1)
     st = JacStats()
     code = L.syev_jacobi_noalloc(_vp(Ac.data_ptr()), n, max(n, 1), _vp(W.data_ptr()), _vp(Vb.data_ptr()),
                                  max(n, 1), tol, ctypes.byref(o), ctypes.byref(st), _stream())
@@ -297,7 +304,7 @@ def gesvd_jacobi(A: torch.Tensor, tol: float = 0.0):
 
 
 def gesvd_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", max_sweeps=0, variant="auto",
-                    allow_unconverged=False):
+                    allow_unconverged=False, stage1="auto"):
     """Thin SVD A = U diag(S) V^T (m >= n): returns (S descending, U, V, stats, info)."""
     L = load()
     A = _dev(A)
@@ -306,7 +313,7 @@ def gesvd_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", max_sweep
     S = torch.empty(n, dtype=torch.float64, device=A.device)
     Ub = torch.empty((n, m), dtype=torch.float64, device=A.device)
     Vb = torch.empty((n, n), dtype=torch.float64, device=A.device)
-    o = _opts(precond, variant, 0, max_sweeps)
+    o = _opts(precond, variant, 0, max_sweeps, stage1=stage1)
     st = JacStats()
     code = L.gesvd_jacobi_ex(_vp(Ac.data_ptr()), m, n, max(m, 1), _vp(S.data_ptr()), _vp(Ub.data_ptr()),
                              max(m, 1), _vp(Vb.data_ptr()), max(n, 1), tol, ctypes.byref(o), ctypes.byref(st),
@@ -417,6 +424,64 @@ def jac_eig_fp32(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 0):
                           _vp(W.data_ptr()), tol, max_sweeps, ctypes.byref(sw), _stream())
     _check("jac_eig_fp32", code)
     return W, Zb.t(), sw.value
+
+
+def jac_sytrd_f32(A: torch.Tensor):
+    """FP32 Householder tridiagonalization of the symmetric A: returns (d, e, tau, U) with U's
+    column k the reflector u_k (device tensors; d, e FP64, tau, U FP32)."""
+    L = load()
+    A = _dev(A)
+    n = A.shape[0]
+    Ac = _colmajor(A)
+    d = torch.empty(n, dtype=torch.float64, device=A.device)
+    e = torch.empty(max(n - 1, 1), dtype=torch.float64, device=A.device)
+    tau = torch.empty(max(n - 2, 1), dtype=torch.float32, device=A.device)
+    Ub = torch.zeros((max(n - 2, 1), n), dtype=torch.float32, device=A.device)
+    code = L.jac_sytrd_f32(_vp(Ac.data_ptr()), n, max(n, 1), _vp(d.data_ptr()), _vp(e.data_ptr()),
+                           _vp(tau.data_ptr()), _vp(Ub.data_ptr()), max(n, 1), _stream())
+    _check("jac_sytrd_f32", code)
+    torch.cuda.synchronize()
+    return d, e[: max(n - 1, 0)], tau[: max(n - 2, 0)], Ub[: max(n - 2, 0)].t()
+
+
+def jac_tridiag_eig(d: torch.Tensor, e: torch.Tensor, vectors: bool = True):
+    """Eigenvalues (ascending) and, with vectors=True, eigenvectors of the tridiagonal (d, e)."""
+    L = load()
+    d = _dev(d).contiguous()
+    n = d.shape[0]
+    e = _dev(e).contiguous() if n > 1 else torch.zeros(1, dtype=torch.float64, device=d.device)
+    w = torch.empty(n, dtype=torch.float64, device=d.device)
+    Zb = torch.empty((n, n), dtype=torch.float64, device=d.device) if vectors else None
+    code = L.jac_tridiag_eig(_vp(d.data_ptr()), _vp(e.data_ptr()), n, _vp(w.data_ptr()),
+                             _vp(Zb.data_ptr()) if vectors else None, max(n, 1), _stream())
+    _check("jac_tridiag_eig", code)
+    return (w, Zb.t()) if vectors else w
+
+
+def jac_tridiag_backtransform(U: torch.Tensor, tau: torch.Tensor, Y: torch.Tensor):
+    """H_0 ... H_{n-3} Y for reflectors (U, tau) as from jac_sytrd_f32 (FP32 arithmetic)."""
+    L = load()
+    n = Y.shape[0]
+    Uc = _colmajor(_dev(U, torch.float32)) if n > 2 else torch.zeros(1, dtype=torch.float32, device=Y.device)
+    tau = _dev(tau, torch.float32).contiguous() if n > 2 else Uc
+    Yb = _colmajor(_dev(Y)).clone()
+    code = L.jac_tridiag_backtransform(_vp(Uc.data_ptr()), max(n, 1), _vp(tau.data_ptr()), n,
+                                       _vp(Yb.data_ptr()), max(n, 1), _stream())
+    _check("jac_tridiag_backtransform", code)
+    return Yb.t()
+
+
+def jac_eig_fp32_tridiag(A: torch.Tensor):
+    """The tridiagonal FP32 step 1: returns (W ascending, Z with matching columns)."""
+    L = load()
+    n = A.shape[0]
+    Ac = _colmajor(_dev(A))
+    W = torch.empty(n, dtype=torch.float64, device=A.device)
+    Zb = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    code = L.jac_eig_fp32_tridiag(_vp(Ac.data_ptr()), n, max(n, 1), _vp(Zb.data_ptr()), max(n, 1),
+                                  _vp(W.data_ptr()), _stream())
+    _check("jac_eig_fp32_tridiag", code)
+    return W, Zb.t()
 
 
 def jac_gemm(A: torch.Tensor, B: torch.Tensor, transa=False, transb=False):

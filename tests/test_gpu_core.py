@@ -282,7 +282,8 @@ def test_preconditioned_n256(kind):
     n = 256
     A, lam = tm.sym_matrix(n, kind, seed=600 + n)
     print(f"[precond n={n} {kind}]", flush=True)
-    W, V, st, info = jacobi.syev_jacobi_ex(dev(A), tol=1e-15, precond="fp32", variant="element")
+    W, V, st, info = jacobi.syev_jacobi_ex(dev(A), tol=1e-15, precond="fp32", variant="element",
+                                           stage1="jacobi")
     check_eig(A, host(W), host(V), lam)
     plain = jacobi.syev_jacobi_ex(dev(A), tol=1e-15, precond="none", variant="element")[2]
     assert st["sweeps"] < plain["sweeps"]
@@ -349,7 +350,7 @@ def test_theorem_evd_ubd_at_fp32_convergence(n):
     held to this bound."""
     A, lam = tm.sym_matrix(n, "uniform", seed=1100 + n)
     print(f"[evd-ubd] n={n}", flush=True)
-    W, V, st, info = jacobi.syev_jacobi_ex(dev(A), precond="fp32", fp32_tol=1e-6)
+    W, V, st, info = jacobi.syev_jacobi_ex(dev(A), precond="fp32", fp32_tol=1e-6, stage1="jacobi")
     check_eig(A, host(W), host(V), lam)
     bd = n * np.abs(lam).max() * 2.0 ** -24
     print(f"  fp32_sweeps={st['fp32_sweeps']} off0={st['off0']:.3e} bd={bd:.3e} sweeps={st['sweeps']}",

@@ -281,11 +281,11 @@ def test_syev_learned_start_accept_and_fallback(kind):
           f"sweeps={st['sweeps']} fp32_sweeps={st['fp32_sweeps']}", flush=True)
     _check_solution(A, W, V, lam)
     if kind == "exact":
-        assert st["used_fallback"] == 0 and st["fp32_sweeps"] == 0
+        assert st["used_fallback"] == 0 and st["fp32_method"] == 0
         assert st["start_resid"] <= 1e-5
         assert st["sweeps"] <= 3
     else:
-        assert st["used_fallback"] == 1 and st["fp32_sweeps"] > 0
+        assert st["used_fallback"] == 1 and st["fp32_method"] in (1, 2)   # the FP32 step 1 ran
         assert st["start_resid"] > 1e-2
     net.close()
 
