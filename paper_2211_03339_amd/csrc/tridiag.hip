@@ -69,9 +69,9 @@ struct TdArgs {
   double* d;                      // n diagonal entries of T
   double* e;                      // n - 1 subdiagonal entries
   float* tau;                     // n - 2 reflector scalars
-  float* U;                       // n x ldu... column k = u_k (zero above row k + 1)
+  double* U;                      // n x ldu... column k = u_k (zero above row k + 1), FP32 values
   int ldu;
-  float* Ut;                      // row k = u_k (Ut[k + j * ldut])
+  double* Ut;                     // row k = u_k (Ut[k + j * ldut])
   int ldut;
   int* abort;                     // nonzero: some workgroup gave up waiting
 };
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kTdThreads) void sytrd_kernel(const TA* __restrict_
       td_reflector(rk, vL, n, k + 1, red, slot, tauk, beta);
       if (wg == 0) {
         if (t == 0) { a.d[k + 1] = rk[k + 1]; a.e[k + 1] = beta; a.tau[k + 1] = tauk; }
-        float* Uc = a.U + (size_t)(k + 1) * a.ldu;
+        double* Uc = a.U + (size_t)(k + 1) * a.ldu;
         for (int j = t; j < n; j += kTdThreads) {
           const float u = j >= k + 2 ? vL[j] : 0.f;
           Uc[j] = u;
@@ -375,15 +375,15 @@ __device__ __forceinline__ double lane_swap(double x, int lane) {
 constexpr int td_pow2(int x) { return x <= 1 ? 1 : 2 * td_pow2((x + 1) / 2); }
 constexpr int td_log2(int x) { return x <= 1 ? 0 : 1 + td_log2(x / 2); }
 
-template <int LVL, int NP>
-__device__ __forceinline__ void td_halve(float (&w)[NP], int lane) {
+template <int LVL, int NP, typename T>
+__device__ __forceinline__ void td_halve(T (&w)[NP], int lane) {
   constexpr int half = NP >> (LVL + 1);
   const bool up = (lane & (1 << LVL)) != 0;
 #pragma unroll
   for (int j = 0; j < half; ++j) {
-    float lo = w[j], hi = w[j + half];
+    T lo = w[j], hi = w[j + half];
     asm volatile("" : "+v"(lo), "+v"(hi));   // keep both halves in registers (no runtime index into w)
-    const float send = up ? lo : hi, keep = up ? hi : lo;
+    const T send = up ? lo : hi, keep = up ? hi : lo;
     w[j] = keep + lane_xor<LVL>(send, lane);
   }
 }
@@ -392,21 +392,21 @@ __device__ __forceinline__ void td_halve(float (&w)[NP], int lane) {
 // the totals.  Inside a 16-lane row the NV values are summed by halving exchanges (lane l then
 // holds value bitrev(l)), the row swaps add the wave's four rows, row 0 of each wave writes its
 // sums to lds[par], and after the barrier every thread adds the waves' sums in wave order.
-template <int NV, int kThr>
-__device__ __forceinline__ void td_block_sum(float (&v)[NV], float* lds2, int& par, float (&tot)[NV]) {
+template <int NV, int kThr, typename T>
+__device__ __forceinline__ void td_block_sum(T (&v)[NV], T* lds2, int& par, T (&tot)[NV]) {
   constexpr int NP = td_pow2(NV), K = td_log2(NP), kW = kThr / 64;
   static_assert(NP <= 16, "at most 16 values");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  float* lds = lds2 + par * kW * 16;
+  T* lds = lds2 + par * kW * 16;
   par ^= 1;
-  float w[NP];
+  T w[NP];
 #pragma unroll
-  for (int j = 0; j < NP; ++j) w[j] = j < NV ? v[j] : 0.f;
+  for (int j = 0; j < NP; ++j) w[j] = j < NV ? v[j] : T(0);
   if constexpr (K > 0) td_halve<0, NP>(w, lane);
   if constexpr (K > 1) td_halve<1, NP>(w, lane);
   if constexpr (K > 2) td_halve<2, NP>(w, lane);
   if constexpr (K > 3) td_halve<3, NP>(w, lane);
-  float x = w[0];
+  T x = w[0];
   if constexpr (K <= 0) x += lane_xor<0>(x, lane);
   if constexpr (K <= 1) x += lane_xor<1>(x, lane);
   if constexpr (K <= 2) x += lane_xor<2>(x, lane);
@@ -423,7 +423,7 @@ __device__ __forceinline__ void td_block_sum(float (&v)[NV], float* lds2, int& p
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
-    float sacc = 0.f;
+    T sacc = T(0);
 #pragma unroll
     for (int q = 0; q < kW; ++q) sacc += lds[q * 16 + j];
     tot[j] = sacc;
@@ -457,26 +457,27 @@ __device__ __forceinline__ double td_block_sum_d(double x, double* lds2, int& pa
 // p(k+1)).  Per column: the owner of row k+1 publishes it, one workgroup sum gives the own entries
 // of p, the gather brings p and the row, one sum gives p^T v, the rank-2 update runs in registers,
 // and one sum gives the norm of the next reflector's vector.
-template <typename TA, int kThr, int kRows, int kCols>
+template <typename TA, int kThr, int kRows, int kCols, typename TS>
 __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ A, int lda, TdArgs a) {
   constexpr int kW = kThr / 64;
   __shared__ float vL[kCols * kThr];
   __shared__ float pL[kCols * kThr];
-  __shared__ float redf[2 * kW * 16];
+  __shared__ TS redf[2 * kW * 16];
   __shared__ double redd[2 * kW];
   __shared__ float bc[2];
   __shared__ int bad_any[2];
   const int n = a.n, G = a.G, wg = blockIdx.x, t = threadIdx.x;
   const int nr = (n - wg + G - 1) / G;
   int fpar = 0, dpar = 0;
-  float R[kRows][kCols], vq[kCols], pq[kCols], rq[kCols];
+  TS R[kRows][kCols];
+  float vq[kCols], pq[kCols], rq[kCols];
 #pragma unroll
   for (int r = 0; r < kRows; ++r) {
     const int i = wg + r * G;
 #pragma unroll
     for (int q = 0; q < kCols; ++q) {
       const int j = q * kThr + t;
-      R[r][q] = (r < nr && j < n) ? (float)A[j + (size_t)i * lda] : 0.f;
+      R[r][q] = (r < nr && j < n) ? (TS)(float)A[j + (size_t)i * lda] : TS(0);
     }
   }
 #pragma unroll
@@ -516,16 +517,13 @@ __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ 
       vq[q] = j == k + 1 ? 1.f : (j > k + 1 && j < n ? rq[q] * scal : 0.f);
       vL[q * kThr + t] = vq[q];
     }
-    if (wg == 0) {
+    if (wg == k % G) {   // the write-out rotates over the workgroups (none lags behind the others)
       if (t == 0) { a.e[k] = beta; a.tau[k] = tauk; }
-      float* Uc = a.U + (size_t)k * a.ldu;
+      double* Uc = a.U + (size_t)k * a.ldu;
 #pragma unroll
       for (int q = 0; q < kCols; ++q) {
         const int j = q * kThr + t;
-        if (j < n) {
-          Uc[j] = vq[q];
-          a.Ut[k + (size_t)j * a.ldut] = vq[q];
-        }
+        if (j < n) Uc[j] = vq[q];
         if (j == k) a.d[k] = rq[q];
       }
     }
@@ -547,24 +545,25 @@ __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ 
           for (int q = 0; q < kCols; ++q) {
             const int j = q * kThr + t;
             if (j > k && j < n)
-              __hip_atomic_store(rb + j, td_pack(tag, R[r][q]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              __hip_atomic_store(rb + j, td_pack(tag, (float)R[r][q]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
     }
     // (1) p(i) = tau B(i, :) v for the own rows (v is zero at j <= k)
-    float acc[kRows], tot[kRows];
+    TS acc[kRows], tot[kRows];
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
-      acc[r] = 0.f;
+      acc[r] = TS(0);
 #pragma unroll
-      for (int q = 0; q < kCols; ++q) acc[r] = fmaf(R[r][q], vq[q], acc[r]);
+      for (int q = 0; q < kCols; ++q) acc[r] = fma(R[r][q], (TS)vq[q], acc[r]);
     }
-    td_block_sum<kRows, kThr>(acc, redf, fpar, tot);
+    td_block_sum<kRows, kThr, TS>(acc, redf, fpar, tot);
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
       const int i = wg + r * G;
       if (t == r && r < nr && i > k)
-        __hip_atomic_store(pb + i, td_pack(tag, tauk * tot[r]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(pb + i, td_pack(tag, (float)((TS)tauk * tot[r])), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
     if (t == 0) __hip_atomic_store(a.hb + wg, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // (2) gather p(k+1:) and row k+1: every load issued before any tag is tested
@@ -594,11 +593,11 @@ __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ 
     if (t < G) td_wait_hb(a.hb + t, tag, a.abort, bad);
     if (bad) bad_any[par] = 1;
     // (3) s = p^T v (one workgroup sum), w = p - (tau s / 2) v
-    float sv[1] = {spart}, st[1];
-    td_block_sum<1, kThr>(sv, redf, fpar, st);
+    TS sv[1] = {(TS)spart}, st[1];
+    td_block_sum<1, kThr, TS>(sv, redf, fpar, st);
     if (bad_any[par]) break;
     if (t == 0) bad_any[par ^ 1] = 0;
-    const float c = 0.5f * tauk * st[0];
+    const float c = (float)(TS(0.5f * tauk) * st[0]);
     // (4) own rows i > k:  B(i, j) -= v(i) w(j) + w(i) v(j)
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
@@ -608,7 +607,8 @@ __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ 
 #pragma unroll
         for (int q = 0; q < kCols; ++q) {
           const float wj = pq[q] - c * vq[q];
-          R[r][q] = R[r][q] - (vi * wj + wi * vq[q]);
+          // FP32 operands; in FP64 storage their products are exact and the update rounds once
+          R[r][q] = R[r][q] - ((TS)vi * (TS)wj + (TS)wi * (TS)vq[q]);
         }
       }
     }
@@ -619,7 +619,7 @@ __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ 
     if (k + 3 < n) {
       reflect(k + 1);
     } else {
-      if (wg == 0) {
+      if (wg == (n - 2) % G) {
 #pragma unroll
         for (int q = 0; q < kCols; ++q) {
           const int j = q * kThr + t;
@@ -633,7 +633,7 @@ __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ 
         for (int r = 0; r < kRows; ++r)
 #pragma unroll
           for (int q = 0; q < kCols; ++q)
-            if (r == r1 && q * kThr + t == n - 1) a.d[n - 1] = R[r][q];
+            if (r == r1 && q * kThr + t == n - 1) a.d[n - 1] = (float)R[r][q];
       }
     }
   }
@@ -677,25 +677,38 @@ __global__ __launch_bounds__(256) void tri_bounds_kernel(const double* d, const 
   }
 }
 
-// Number of eigenvalues below x: negative pivots of T - x I (d, e^2 in LDS).
+// Number of eigenvalues below x: the sign changes of the Sturm sequence of T - x I, i.e. of the
+// leading principal minors m_i = (d_i - x) m_(i-1) - e_(i-1)^2 m_(i-2) (m_0 = 1, m_(-1) = 0); the
+// ratio m_i / m_(i-1) is the i-th pivot of the LDL^T factorization, so a sign change is a
+// negative pivot.  No division: every 16 steps both kept minors are scaled by the same power of
+// two (exact), and a zero minor is replaced by -pivmin times its predecessor (a pivot of -pivmin).
 __device__ __forceinline__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int n,
                                            double x, double pivmin) {
+  double m1 = 1.0, m0 = 0.0;   // m_(i-1), m_(i-2)
   int c = 0;
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  c += q < 0.0;
-  for (int i = 1; i < n; ++i) {
-    q = (d[i] - x) - e2[i - 1] / q;
-    if (fabs(q) < pivmin) q = -pivmin;
-    c += q < 0.0;
+  for (int i0 = 0; i0 < n; i0 += 16) {
+    const int i1 = i0 + 16 < n ? i0 + 16 : n;
+    for (int i = i0; i < i1; ++i) {
+      double m = fma(d[i] - x, m1, i > 0 ? -e2[i - 1] * m0 : 0.0);
+      if (m == 0.0) m = -pivmin * m1;
+      c += (m < 0.0) != (m1 < 0.0);
+      m0 = m1;
+      m1 = m;
+    }
+    int ex;
+    (void)frexp(fabs(m1) + fabs(m0), &ex);
+    m1 = ldexp(m1, -ex);
+    m0 = ldexp(m0, -ex);
   }
   return c;
 }
 
-constexpr int kBisThreads = 1024;   // 16 eigenvalues per workgroup, sharing one LDS copy of d, e^2
+constexpr int kBisThreads = 256;    // 8 eigenvalues per workgroup (one per 32 lanes), sharing one LDS copy of d, e^2
+constexpr int kBisLanes = 32;       // points per eigenvalue and round
 
-// One wave per eigenvalue index k: 64 Sturm counts per round narrow the interval holding the k-th
-// smallest eigenvalue 65-fold, until it spans no more than a few units of roundoff.
+// kBisLanes lanes per eigenvalue index k: their Sturm counts narrow the interval holding the k-th
+// smallest eigenvalue (kBisLanes + 1)-fold per round, until it spans no more than a few units of
+// roundoff.
 __global__ __launch_bounds__(kBisThreads) void tri_bisect_kernel(const double* __restrict__ d,
                                                                 const double* __restrict__ e, int n,
                                                                 const double* __restrict__ bnd,
@@ -708,27 +721,32 @@ __global__ __launch_bounds__(kBisThreads) void tri_bisect_kernel(const double* _
     se2[i] = i + 1 < n ? e[i] * e[i] : 0.0;
   }
   __syncthreads();
-  const int k = blockIdx.x * (kBisThreads / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (k >= n) return;
+  const int k = blockIdx.x * (kBisThreads / kBisLanes) + (threadIdx.x / kBisLanes);
+  const int lane = threadIdx.x & (kBisLanes - 1);
+  const int half = (threadIdx.x & 63) & ~(kBisLanes - 1);   // first lane of this group in the wave
+  const bool live = k < n;
   double lo = bnd[0], hi = bnd[1];
   const double pivmin = bnd[2];
-  for (int round = 0; round < 16; ++round) {
+  bool done = !live;
+  for (int round = 0; round < 24; ++round) {
     const double width = hi - lo;
-    if (width <= 4.0 * 1.1102230246251565e-16 * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-    const double x = lo + width * (double)(lane + 1) / 65.0;
-    const bool below = sturm_count(sd, se2, n, x, pivmin) <= k;   // the k-th eigenvalue is >= x
-    const unsigned long long m = __ballot(below);
+    if (width <= 4.0 * 1.1102230246251565e-16 * fmax(fabs(lo), fabs(hi)) + pivmin) done = true;
+    // both groups of a wave run every round (ballot / shuffle span the wave); finished ones idle
+    if (__all(done)) break;
+    const double x = lo + width * (double)(lane + 1) / (double)(kBisLanes + 1);
+    const bool below = !done && sturm_count(sd, se2, n, x, pivmin) <= k;   // the k-th eigenvalue is >= x
+    const unsigned long long m = (__ballot(below) >> half) & ((1ull << kBisLanes) - 1);
     const int hb = m ? 63 - __clzll(m) : -1;                       // last point with count <= k
-    const double xl = __shfl(x, hb < 0 ? 0 : hb, 64);
-    const double xh = __shfl(x, hb + 1 > 63 ? 63 : hb + 1, 64);
-    const double nlo = hb < 0 ? lo : xl;
-    const double nhi = hb >= 63 ? hi : xh;
-    if (!(nlo > lo || nhi < hi)) break;   // the points no longer split the interval
-    lo = nlo;
-    hi = nhi;
+    const double xl = __shfl(x, half + (hb < 0 ? 0 : hb), 64);
+    const double xh = __shfl(x, half + (hb + 1 > kBisLanes - 1 ? kBisLanes - 1 : hb + 1), 64);
+    if (!done) {
+      const double nlo = hb < 0 ? lo : xl;
+      const double nhi = hb >= kBisLanes - 1 ? hi : xh;
+      if (!(nlo > lo || nhi < hi)) done = true;   // the points no longer split the interval
+      else { lo = nlo; hi = nhi; }
+    }
   }
-  if (lane == 0) w[k] = 0.5 * (lo + hi);
+  if (live && lane == 0) w[k] = 0.5 * (lo + hi);
 }
 
 // ---------------------------------------------------------------- eigenvectors
@@ -837,66 +855,31 @@ __global__ __launch_bounds__(kVecThreads) void tri_vectors_kernel(const double* 
 }
 
 // ---------------------------------------------------------------- back-transformation
-// For reflector block b (columns k0 = b kBtNb .. of U), the triangular factor Tb with
-// H_k0 ... H_(k0+NB-1) = I - Ub Tb Ub^T.  The Gram G = Ub^T Ub over rows k0+1 .. n-1 is summed
-// in 8 x 8 register tiles (one per thread) from 32-row chunks of Ub staged in LDS.  The four
-// diagonal 32 x 32 blocks of Tb follow column by column from Tb(i,i) = tau_i,
-// Tb(0:i, i) = -tau_i Tb(0:i, 0:i) G(0:i, i) (all four at once); the off-diagonal blocks from
-// joining two factors, [[Ta, -Ta Gab Tb], [0, Tb]], first pairwise (32 | 32) then (64 | 64).
-__global__ __launch_bounds__(256) void bt_tfactor_kernel(const float* __restrict__ U, int ldu, const float* __restrict__ tau,
-                                                        int n, int nref, float* __restrict__ Tall) {
+// For reflector block b (reflectors k0 = b kBtNb ...), the triangular factor Tb with
+// H_k0 ... H_(k0+NB-1) = I - Ub Tb Ub^T, from the block's Gram G = Ub^T Ub (computed beforehand on
+// the matrix cores, column-major NB x NB per block).  The four diagonal 32 x 32 blocks of Tb follow
+// column by column from Tb(i,i) = tau_i, Tb(0:i, i) = -tau_i Tb(0:i, 0:i) G(0:i, i) (all four at
+// once); the off-diagonal blocks from joining two factors, [[Ta, -Ta Gab Tb], [0, Tb]], first
+// pairwise (32 | 32) then (64 | 64), each product formed in the still-zero upper-right block.
+__global__ __launch_bounds__(256) void bt_tfactor_kernel(const double* __restrict__ Gall, const float* __restrict__ tau,
+                                                        int nref, double* __restrict__ Tall) {
   constexpr int NB = kBtNb, LD = NB + 1;
-  static_assert(NB == 128, "tile layout assumes 128 reflectors per block");
+  static_assert(NB == 128, "block layout assumes 128 reflectors per block");
   extern __shared__ __align__(16) unsigned char bt_smem[];
-  float* Gs = reinterpret_cast<float*>(bt_smem);   // NB x LD: Gram, Gs[a * LD + b]
-  float* Ts = Gs + NB * LD;                         // NB x LD: Tb, Ts[a * LD + c]
-  float* Ms = Ts + NB * LD;                         // 64 x 65 scratch product (also the 32-row chunk)
+  double* Ts = reinterpret_cast<double*>(bt_smem);   // NB x LD, Ts[a * LD + c]
   const int b = blockIdx.x, t = threadIdx.x, k0 = b * NB;
-  const int r0 = k0 + 1;
-  const int ta = t >> 4, tb = t & 15;
-  float g[8][8];
-#pragma unroll
-  for (int x = 0; x < 8; ++x)
-#pragma unroll
-    for (int y = 0; y < 8; ++y) g[x][y] = 0.f;
-  float* ch = Ms;   // 32 x LD
-  for (int rs = r0; rs < n; rs += 32) {
-    for (int q = t; q < 32 * NB; q += 256) {
-      const int rr = q % 32, cc = q / 32;
-      const int i = rs + rr, col = k0 + cc;
-      ch[rr * LD + cc] = (i < n && col < nref) ? U[i + (size_t)col * ldu] : 0.f;
-    }
-    __syncthreads();
-    for (int rr = 0; rr < 32; ++rr) {
-      float ua[8], ub[8];
-#pragma unroll
-      for (int x = 0; x < 8; ++x) {
-        ua[x] = ch[rr * LD + 8 * ta + x];
-        ub[x] = ch[rr * LD + 8 * tb + x];
-      }
-#pragma unroll
-      for (int x = 0; x < 8; ++x)
-#pragma unroll
-        for (int y = 0; y < 8; ++y) g[x][y] = fmaf(ua[x], ub[y], g[x][y]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int x = 0; x < 8; ++x)
-#pragma unroll
-    for (int y = 0; y < 8; ++y) Gs[(8 * ta + x) * LD + 8 * tb + y] = g[x][y];
-  for (int q = t; q < NB * LD; q += 256) Ts[q] = 0.f;
+  const double* G = Gall + (size_t)b * NB * NB;     // G(a, c) = G[a + c * NB]
+  for (int q = t; q < NB * LD; q += 256) Ts[q] = 0.0;
   __syncthreads();
-  // diagonal blocks: thread (blk, l) = (t / 32 for t < 128, t % 32) owns row l of block blk
   const int blk = t >> 5, l = t & 31;
   for (int i = 0; i < 32; ++i) {
-    float yv = 0.f;
+    double yv = 0.0;
     if (t < 128) {
       const int base = blk * 32, col = base + i;
-      const float ti = (k0 + col < nref) ? tau[k0 + col] : 0.f;
+      const double ti = (k0 + col < nref) ? (double)tau[k0 + col] : 0.0;
       if (l < i) {
-        float sacc = 0.f;
-        for (int cc = l; cc < i; ++cc) sacc = fmaf(Ts[(base + l) * LD + base + cc], Gs[(base + cc) * LD + col], sacc);
+        double sacc = 0.0;
+        for (int cc = l; cc < i; ++cc) sacc = fma(Ts[(base + l) * LD + base + cc], G[(base + cc) + (size_t)col * NB], sacc);
         yv = -ti * sacc;
       } else if (l == i) {
         yv = ti;
@@ -906,41 +889,49 @@ __global__ __launch_bounds__(256) void bt_tfactor_kernel(const float* __restrict
     if (t < 128 && l <= i) Ts[(blk * 32 + l) * LD + blk * 32 + i] = yv;
     __syncthreads();
   }
-  // join factors: X = -Ta Gab Tb for (a, b) = (0,1), (2,3) with p = 32, then ((01), (23)) with p = 64
   for (int lvl = 0; lvl < 2; ++lvl) {
     const int p = lvl == 0 ? 32 : 64;
     const int npairs = lvl == 0 ? 2 : 1;
     for (int pr = 0; pr < npairs; ++pr) {
       const int oa = pr * 2 * p, ob = oa + p;
-      // M = Gab Tb (p x p), Tb upper triangular
+      // M = Gab Tb into the (zero) upper-right block
       for (int q = t; q < p * p; q += 256) {
         const int x = q / p, y = q % p;
-        float sacc = 0.f;
-        for (int cc = 0; cc <= y; ++cc) sacc = fmaf(Gs[(oa + x) * LD + ob + cc], Ts[(ob + cc) * LD + ob + y], sacc);
-        Ms[x * 65 + y] = sacc;
+        double sacc = 0.0;
+        for (int cc = 0; cc <= y; ++cc) sacc = fma(G[(oa + x) + (size_t)(ob + cc) * NB], Ts[(ob + cc) * LD + ob + y], sacc);
+        Ts[(oa + x) * LD + ob + y] = sacc;
       }
       __syncthreads();
-      // X = -Ta M, Ta upper triangular
-      for (int q = t; q < p * p; q += 256) {
-        const int x = q / p, y = q % p;
-        float sacc = 0.f;
-        for (int cc = x; cc < p; ++cc) sacc = fmaf(Ts[(oa + x) * LD + oa + cc], Ms[cc * 65 + y], sacc);
-        Ts[(oa + x) * LD + ob + y] = -sacc;
+      // X = -Ta M, through registers (every entry of X reads a column of M)
+      double xr[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int q = t + u * 256;
+        xr[u] = 0.0;
+        if (q < p * p) {
+          const int x = q / p, y = q % p;
+          double sacc = 0.0;
+          for (int cc = x; cc < p; ++cc) sacc = fma(Ts[(oa + x) * LD + oa + cc], Ts[(oa + cc) * LD + ob + y], sacc);
+          xr[u] = -sacc;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int q = t + u * 256;
+        if (q < p * p) Ts[(oa + q / p) * LD + ob + q % p] = xr[u];
       }
       __syncthreads();
     }
   }
-  float* Tb = Tall + (size_t)b * NB * NB;   // column-major NB x NB
-  for (int q = t; q < NB * NB; q += 256) {
-    const int a2 = q % NB, c2 = q / NB;
-    Tb[q] = Ts[a2 * LD + c2];
-  }
+  double* Tb = Tall + (size_t)b * NB * NB;   // column-major NB x NB
+  for (int q = t; q < NB * NB; q += 256) Tb[q] = Ts[(q % NB) * LD + q / NB];
 }
 
 // B (cols x rows block, ldb) = A^T for an m x n block of A (lda), 32 x 32 tiles through LDS.
-__global__ void td_transpose_f32_kernel(const float* __restrict__ A, int lda, int m, int n, float* __restrict__ B,
-                                        int ldb) {
-  __shared__ float tl[32][33];
+template <typename T>
+__global__ void td_transpose_kernel(const T* __restrict__ A, int lda, int m, int n, T* __restrict__ B, int ldb) {
+  __shared__ T tl[32][33];
   const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int r = ty; r < 32; r += 8) {
@@ -982,7 +973,8 @@ struct TdWork {
   unsigned* hb;
   int* abort;
   double *bnd, *d, *e, *w;
-  float *tau, *U, *Ut, *Y, *Tf, *Wb, *W2, *rows;
+  float *tau, *rows;
+  double *U, *Ut, *Y, *G, *Tf, *Wb, *W2;
   double *dp, *dm;
   int nbp, nc;
 };
@@ -1000,14 +992,15 @@ static TdWork td_carve(Carve& c, int n) {
   k.e = c.take<double>(n);
   k.w = c.take<double>(n);
   k.tau = c.take<float>(k.nbp);
-  k.U = c.take<float>((size_t)k.nbp * n);
-  k.Ut = c.take<float>((size_t)k.nbp * n);
-  k.Y = c.take<float>((size_t)n * n);
+  k.U = c.take<double>((size_t)k.nbp * n);
+  k.Ut = c.take<double>((size_t)k.nbp * n);
+  k.Y = c.take<double>((size_t)n * n);
   k.dp = c.take<double>((size_t)n * k.nc);
   k.dm = c.take<double>((size_t)n * k.nc);
-  k.Tf = c.take<float>((size_t)k.nbp * kBtNb);
-  k.Wb = c.take<float>((size_t)kBtNb * n);
-  k.W2 = c.take<float>((size_t)kBtNb * n);
+  k.G = c.take<double>((size_t)k.nbp * kBtNb);
+  k.Tf = c.take<double>((size_t)k.nbp * kBtNb);
+  k.Wb = c.take<double>((size_t)kBtNb * n);
+  k.W2 = c.take<double>((size_t)kBtNb * n);
   k.rows = td_rows_in_lds(n) ? nullptr : c.take<float>((size_t)n * n);
   return k;
 }
@@ -1021,10 +1014,10 @@ size_t tridiag_bytes(int n) {
 
 bool tridiag_supported(int n) { return n >= 1 && n <= kTdMaxN; }
 
-template <typename TA, int kThr, int kRows, int kCols>
+template <typename TA, int kThr, int kRows, int kCols, typename TS>
 static int td_launch_reg(const TA* A, int lda, TdArgs& a, hipStream_t s) {
   void* args[] = {(void*)&A, (void*)&lda, (void*)&a};
-  auto kern = sytrd_reg_kernel<TA, kThr, kRows, kCols>;
+  auto kern = sytrd_reg_kernel<TA, kThr, kRows, kCols, TS>;
   JAC_HIP(hipLaunchCooperativeKernel((const void*)kern, dim3(a.G), dim3(kThr), args, 0u, s));
   return 0;
 }
@@ -1052,9 +1045,11 @@ static int td_reduce(const TA* A, int n, int lda, TdWork& k, hipStream_t s) {
   hipLaunchKernelGGL(td_fill_u64_kernel, dim3(1), dim3(256), 0, s, reinterpret_cast<unsigned long long*>(k.hb),
                      (long long)kTdMaxG / 2);
   JAC_CHECK_LAUNCH();
-  hipLaunchKernelGGL(td_fill_f32_kernel, dim3(1024), dim3(256), 0, s, k.U, (long long)k.nbp * n);
+  hipLaunchKernelGGL(td_fill_u64_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<unsigned long long*>(k.U),
+                     (long long)k.nbp * n);
   JAC_CHECK_LAUNCH();
-  hipLaunchKernelGGL(td_fill_f32_kernel, dim3(1024), dim3(256), 0, s, k.Ut, (long long)k.nbp * n);
+  hipLaunchKernelGGL(td_fill_u64_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<unsigned long long*>(k.Ut),
+                     (long long)k.nbp * n);
   JAC_CHECK_LAUNCH();
   hipLaunchKernelGGL(td_fill_f32_kernel, dim3(1), dim3(256), 0, s, k.tau, (long long)k.nbp);
   JAC_CHECK_LAUNCH();
@@ -1078,10 +1073,17 @@ static int td_reduce(const TA* A, int n, int lda, TdWork& k, hipStream_t s) {
   a.Ut = k.Ut;
   a.ldut = k.nbp;
   a.abort = k.abort;
-  if (n <= 1024) return td_launch_reg<TA, 256, 4, 4>(A, lda, a, s);
-  if (n <= 2048) return td_launch_reg<TA, 256, 8, 8>(A, lda, a, s);
-  if (n <= 4096) return td_launch_reg<TA, 512, 16, 8>(A, lda, a, s);
-  return td_launch<TA, false, kTdGlbRows>(A, lda, a, s);
+  int rc;
+  if (n <= 1024) rc = td_launch_reg<TA, 256, 4, 4, double>(A, lda, a, s);
+  else if (n <= 2048) rc = td_launch_reg<TA, 256, 8, 8, double>(A, lda, a, s);
+  else if (n <= 4096) rc = td_launch_reg<TA, 512, 16, 8, float>(A, lda, a, s);
+  else return td_launch<TA, false, kTdGlbRows>(A, lda, a, s);   // writes Ut itself
+  if (rc) return rc;
+  // Ut = U^T for the back-transformation's untransposed products
+  hipLaunchKernelGGL(td_transpose_kernel<double>, dim3(tcdiv(n, 32), tcdiv(n - 2, 32)), dim3(256), 0, s, k.U, n, n,
+                     n - 2, k.Ut, k.nbp);
+  JAC_CHECK_LAUNCH();
+  return 0;
 }
 
 static int td_abort_check(const TdWork& k, hipStream_t s) {
@@ -1105,7 +1107,8 @@ static int td_eigvals(const double* d, const double* e, int n, double* bnd, doub
   JAC_CHECK_LAUNCH();
   const size_t bsh = (size_t)2 * n * sizeof(double);
   JAC_HIP(hipFuncSetAttribute((const void*)tri_bisect_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bsh));
-  hipLaunchKernelGGL(tri_bisect_kernel, dim3(tcdiv(n, kBisThreads / 64)), dim3(kBisThreads), bsh, s, d, e, n, bnd, w);
+  hipLaunchKernelGGL(tri_bisect_kernel, dim3(tcdiv(n, kBisThreads / kBisLanes)), dim3(kBisThreads), bsh, s, d, e, n, bnd,
+                     w);
   JAC_CHECK_LAUNCH();
   return 0;
 }
@@ -1125,27 +1128,34 @@ static int td_vectors(const double* d, const double* e, int n, const double* w, 
   return 0;
 }
 
-// Step 1d: Y (n x n FP32, ld n) <- H_0 ... H_{n-3} Y.
-static int td_backtransform(const float* U, const float* Ut, int nbp, const float* tau, int n, float* Tf, float* Wb,
-                            float* W2, float* Y, hipStream_t s, bool no_split) {
+// Step 1d: Y (n x n, ld n) <- H_0 ... H_{n-3} Y, in FP64 on the matrix cores: per block of kBtNb
+// reflectors its Gram Ub^T Ub and triangular factor Tb, then Y -= Ub (Tb (Ub^T Y)).
+static int td_backtransform(const double* U, const double* Ut, int nbp, const float* tau, int n, double* Gb,
+                            double* Tf, double* Wb, double* W2, double* Y, hipStream_t s, bool no_split) {
   const int nref = n > 2 ? n - 2 : 0;
   if (nref == 0) return 0;
   const int nblk = tcdiv(nref, kBtNb);
-  const size_t tsh = ((size_t)2 * kBtNb * (kBtNb + 1) + 64 * 65) * sizeof(float);
-  JAC_HIP(hipFuncSetAttribute((const void*)bt_tfactor_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tsh));
-  hipLaunchKernelGGL(bt_tfactor_kernel, dim3(nblk), dim3(256), tsh, s, U, n, tau, n, nref, Tf);
-  JAC_CHECK_LAUNCH();
   const int msplit = no_split ? 1 : 0;
+  for (int b = 0; b < nblk; ++b) {
+    const int k0 = b * kBtNb, r0 = k0 + 1, m = n - r0;
+    int e1 = gemm<double>(false, false, kBtNb, kBtNb, m, 1.0, Ut + k0 + (size_t)r0 * nbp, nbp, U + r0 + (size_t)k0 * n,
+                          n, 0.0, Gb + (size_t)b * kBtNb * kBtNb, kBtNb, s, msplit);
+    if (e1) return e1;
+  }
+  const size_t tsh = (size_t)kBtNb * (kBtNb + 1) * sizeof(double);
+  JAC_HIP(hipFuncSetAttribute((const void*)bt_tfactor_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tsh));
+  hipLaunchKernelGGL(bt_tfactor_kernel, dim3(nblk), dim3(256), tsh, s, Gb, tau, nref, Tf);
+  JAC_CHECK_LAUNCH();
   for (int b = nblk - 1; b >= 0; --b) {
     const int k0 = b * kBtNb, r0 = k0 + 1, m = n - r0;
-    int e1 = gemm<float>(false, false, kBtNb, n, m, 1.f, Ut + k0 + (size_t)r0 * nbp, nbp, Y + r0, n, 0.f, Wb, kBtNb,
-                         s, msplit);
+    int e1 = gemm<double>(false, false, kBtNb, n, m, 1.0, Ut + k0 + (size_t)r0 * nbp, nbp, Y + r0, n, 0.0, Wb, kBtNb,
+                          s, msplit);
     if (e1) return e1;
-    e1 = gemm<float>(false, false, kBtNb, n, kBtNb, 1.f, Tf + (size_t)b * kBtNb * kBtNb, kBtNb, Wb, kBtNb, 0.f, W2,
-                     kBtNb, s, msplit);
+    e1 = gemm<double>(false, false, kBtNb, n, kBtNb, 1.0, Tf + (size_t)b * kBtNb * kBtNb, kBtNb, Wb, kBtNb, 0.0, W2,
+                      kBtNb, s, msplit);
     if (e1) return e1;
-    e1 = gemm<float>(false, false, m, n, kBtNb, -1.f, U + r0 + (size_t)k0 * n, n, W2, kBtNb, 1.f, Y + r0, n, s,
-                     msplit);
+    e1 = gemm<double>(false, false, m, n, kBtNb, -1.0, U + r0 + (size_t)k0 * n, n, W2, kBtNb, 1.0, Y + r0, n, s,
+                      msplit);
     if (e1) return e1;
   }
   return 0;
@@ -1164,11 +1174,11 @@ int eig_tridiag_f32(const TA* A, int n, int lda, double* Z, int ldz, double* w_o
   if (e) return e;
   e = td_eigvals(k.d, k.e, n, k.bnd, k.w, s);
   if (e) return e;
-  e = td_vectors<float>(k.d, k.e, n, k.w, k.bnd, k.dp, k.dm, k.nc, k.Y, n, s);
+  e = td_vectors<double>(k.d, k.e, n, k.w, k.bnd, k.dp, k.dm, k.nc, k.Y, n, s);
   if (e) return e;
-  e = td_backtransform(k.U, k.Ut, k.nbp, k.tau, n, k.Tf, k.Wb, k.W2, k.Y, s, no_split);
+  e = td_backtransform(k.U, k.Ut, k.nbp, k.tau, n, k.G, k.Tf, k.Wb, k.W2, k.Y, s, no_split);
   if (e) return e;
-  e = copy_convert<float, double>(k.Y, n, n, n, Z, ldz, s);
+  e = copy_convert<double, double>(k.Y, n, n, n, Z, ldz, s);
   if (e) return e;
   if (w_out) {
     e = copy_convert<double, double>(k.w, n, 1, n, w_out, n, s);
@@ -1200,7 +1210,7 @@ int tridiag_reduce_entry(const double* A, int n, int lda, double* d, double* e, 
   if (n > 2) {
     r = copy_convert<float, float>(k.tau, n - 2, 1, n, tau, n, s);
     if (r) return r;
-    r = copy_convert<float, float>(k.U, n, n - 2, n, U, ldu, s);
+    r = copy_convert<double, float>(k.U, n, n - 2, n, U, ldu, s);
     if (r) return r;
   }
   return td_abort_check(k, s);
@@ -1235,27 +1245,29 @@ int tridiag_backtransform_entry(const float* U, int ldu, const float* tau, int n
   if (!ws) { set_error("workspace allocation failed"); return 4; }
   Carve c(ws);
   TdWork k = td_carve(c, n);
-  hipLaunchKernelGGL(td_fill_f32_kernel, dim3(1024), dim3(256), 0, s, k.U, (long long)k.nbp * n);
+  hipLaunchKernelGGL(td_fill_u64_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<unsigned long long*>(k.U),
+                     (long long)k.nbp * n);
   JAC_CHECK_LAUNCH();
-  hipLaunchKernelGGL(td_fill_f32_kernel, dim3(1024), dim3(256), 0, s, k.Ut, (long long)k.nbp * n);
+  hipLaunchKernelGGL(td_fill_u64_kernel, dim3(1024), dim3(256), 0, s, reinterpret_cast<unsigned long long*>(k.Ut),
+                     (long long)k.nbp * n);
   JAC_CHECK_LAUNCH();
   hipLaunchKernelGGL(td_fill_f32_kernel, dim3(1), dim3(256), 0, s, k.tau, (long long)k.nbp);
   JAC_CHECK_LAUNCH();
   int r = 0;
   if (n > 2) {
-    r = copy_convert<float, float>(U, n, n - 2, ldu, k.U, n, s);
+    r = copy_convert<float, double>(U, n, n - 2, ldu, k.U, n, s);
     if (r) return r;
-    hipLaunchKernelGGL(td_transpose_f32_kernel, dim3(tcdiv(n, 32), tcdiv(n - 2, 32)), dim3(256), 0, s, k.U, n, n,
+    hipLaunchKernelGGL(td_transpose_kernel<double>, dim3(tcdiv(n, 32), tcdiv(n - 2, 32)), dim3(256), 0, s, k.U, n, n,
                        n - 2, k.Ut, k.nbp);
     JAC_CHECK_LAUNCH();
     r = copy_convert<float, float>(tau, n - 2, 1, n, k.tau, n, s);
     if (r) return r;
   }
-  r = copy_convert<double, float>(Y, n, n, ldy, k.Y, n, s);
+  r = copy_convert<double, double>(Y, n, n, ldy, k.Y, n, s);
   if (r) return r;
-  r = td_backtransform(k.U, k.Ut, k.nbp, k.tau, n, k.Tf, k.Wb, k.W2, k.Y, s, false);
+  r = td_backtransform(k.U, k.Ut, k.nbp, k.tau, n, k.G, k.Tf, k.Wb, k.W2, k.Y, s, false);
   if (r) return r;
-  r = copy_convert<float, double>(k.Y, n, n, n, Y, ldy, s);
+  r = copy_convert<double, double>(k.Y, n, n, n, Y, ldy, s);
   if (r) return r;
   JAC_HIP(hipStreamSynchronize(s));
   return 0;
