@@ -41,7 +41,9 @@ def elem_bytes(n: int, dtype_bytes: int, steps: int, rotations: int) -> float:
     return dtype_bytes * (steps * n * (n + 1) + rotations * 4 * n)
 
 
-KERNEL_OF = {"inner64": ("blk_inner_kernel<double", "blk_inner_v_kernel<double"),
+KERNEL_OF = {"tridiag_reduce": ("sytrd_reg_kernel",),
+             "tridiag_rest": ("tri_bisect_kernel", "tri_vectors_kernel", "bt_tfactor_kernel"),
+             "inner64": ("blk_inner_kernel<double", "blk_inner_v_kernel<double"),
              "update64": ("blk_update16_kernel<double",),
              "inner32": ("blk_inner_kernel<float", "blk_inner_v_kernel<float"),
              "update32": ("blk_update16_kernel<float",),
@@ -77,6 +79,26 @@ def roofline_for(cls: str, k: dict, n: int, rotations: int) -> dict:
     chunks (2 (2b)^3 flop each) the same launches update for the previous block step."""
     ms, launches = k["ms"], max(k["launches"], 1)
     avg_s = ms / 1e3 / launches
+    if cls == "tridiag_reduce":
+        # Householder tridiagonalization: (4/3) n^3 flops (symmetric rank-2 updates and products
+        # with the trailing matrix), FP32 operands; bound in practice by the n - 2 sequential
+        # column exchanges between the workgroups, placed against the FP32 vector peak
+        flops = 4.0 / 3.0 * n ** 3
+        ach = flops / avg_s / 1e12
+        return {"bound": "alu", "achieved": round(ach, 4), "peak": PEAK["fp32_valu"], "unit": "TFLOP/s",
+                "frac": round(ach / PEAK["fp32_valu"], 6), "traffic": None, "kernel": "sytrd_reg_kernel",
+                "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_flops_per_launch": flops,
+                "launches_timed": k["launches"], "per_column_us": round(avg_s * 1e6 / max(n - 2, 1), 3)}
+    if cls == "tridiag_rest":
+        # bisection and eigenvectors of T (O(n^2) each) and the back-transformation Z = Q Y, 2 n^3
+        # flops on the FP64 matrix cores
+        flops = 2.0 * n ** 3
+        ach = flops / avg_s / 1e12
+        return {"bound": "mfma", "achieved": round(ach, 4), "peak": PEAK["fp64_mfma"], "unit": "TFLOP/s",
+                "frac": round(ach / PEAK["fp64_mfma"], 6), "traffic": None,
+                "kernel": "tri_bisect_kernel + tri_vectors_kernel + back-transformation GEMMs",
+                "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_flops_per_launch": flops,
+                "launches_timed": k["launches"]}
     if cls.startswith("update"):
         flops = k["tiles"] * 4 * TILE ** 3 + k["chunks"] * 2 * TILE ** 3
         per_launch = flops / launches
@@ -115,12 +137,13 @@ def roofline_for(cls: str, k: dict, n: int, rotations: int) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--variant", default="auto")
     ap.add_argument("--tol", type=float, default=0.0, help="<= 0: the paper's 20 * 2^-53")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-n", type=int, default=1024, help="order of the CPU oracle's full solve")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-Jacobi comparison")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-start row at n=256")
     ap.add_argument("--no-elem", action="store_true", help="skip the element-wise variant's step rooflines")
@@ -174,9 +197,12 @@ def main():
         log(f"[bench] warmup {w + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    step_s = []
     for k in range(args.steps):
+        ts = time.perf_counter()
         for i in range(len(mats)):
-            solve(i, "fp32", stats[i])
+            solve(i, "fp32", stats[i])   # synchronous: returns after the solve has completed
+        step_s.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s")
@@ -210,6 +236,7 @@ def main():
         lam_err = float(np.abs(W - np.sort(lam)).max() / np.abs(lam).max())
         st = stats[i].as_dict()
         per_spec[spectra[i]] = {"sweeps": st["sweeps"], "fp32_sweeps": st["fp32_sweeps"],
+                                "stage1": {0: "none", 1: "fp32 jacobi", 2: "fp32 tridiagonal"}[st["fp32_method"]],
                                 "JU": round(st["rotations"] / (n * (n - 1) / 2), 3),
                                 "res": res, "orth": orth, "orth_over_sqrt_n": orth / np.sqrt(n),
                                 "lam_err_rel": lam_err,
@@ -218,25 +245,38 @@ def main():
 
     plain = None
     if not args.no_plain:
+        # plain FP64 Jacobi on the same matrices, with the same warm-up and step counts
         pst = [jacobi.JacStats() for _ in mats]
-        solve(0, "none", pst[0])   # warm-up of the plain path
+        for w in range(args.warmup):
+            for i in range(len(mats)):
+                solve(i, "none", pst[i])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        for i in range(len(mats)):
-            solve(i, "none", pst[i])
+        pstep_s = []
+        for k in range(args.steps):
+            ts = time.perf_counter()
+            for i in range(len(mats)):
+                solve(i, "none", pst[i])
+            pstep_s.append(time.perf_counter() - ts)
         torch.cuda.synchronize()
         pt = time.perf_counter() - t1
-        plain = {"solves_per_s": len(mats) / pt,
+        med_pre, med_plain = float(np.median(step_s)), float(np.median(pstep_s))
+        plain = {"solves_per_s": len(mats) * args.steps / pt,
                  "sweeps": {spectra[i]: pst[i].sweeps for i in range(len(mats))},
-                 "speedup_precond_vs_plain": value / (len(mats) / pt)}
+                 "ms_per_step": {"median": round(med_plain * 1e3, 3), "min": round(min(pstep_s) * 1e3, 3),
+                                 "max": round(max(pstep_s) * 1e3, 3)},
+                 "speedup_precond_vs_plain": round(value / (len(mats) * args.steps / pt), 4),
+                 "speedup_spread": {"median_step": round(med_plain / med_pre, 4),
+                                    "worst_step": round(min(pstep_s) / max(step_s), 4),
+                                    "best_step": round(max(pstep_s) / min(step_s), 4)}}
         log(f"[bench] plain: {plain}")
 
     # Roofline of the dominant kernel (by measured launch time inside the timed region).
     dom = max(kern, key=lambda c: kern[c]["ms"])
-    roofline = roofline_for(dom, kern[dom], n, rot[dom[-2:]])
+    roofline = roofline_for(dom, kern[dom], n, rot.get(dom[-2:], 0))
     kernels = {c: {"ms_total": round(v["ms"], 3), "launches": v["launches"],
                    "share_of_profiled_step": round(v["ms"] / prof_ms, 4)} for c, v in kern.items()}
-    others = {c: roofline_for(c, kern[c], n, rot[c[-2:]]) for c in kern if c != dom}
+    others = {c: roofline_for(c, kern[c], n, rot.get(c[-2:], 0)) for c in kern if c != dom}
 
     # The element-wise variant (n/2 disjoint rotations per launch, T and V streamed through HBM):
     # one profiled preconditioned solve of the U[-1,1] matrix, for its step kernels' rooflines.
@@ -268,21 +308,22 @@ def main():
     cpu = None
     if not args.no_cpu:
         import oracle
-        ns = 512
+        ns = args.cpu_n
         A, lam = tm.precond_case(ns, "uniform")
-        log(f"[bench] CPU oracle sample: plain Jacobi, n={ns}")
+        log(f"[bench] CPU oracle: one full plain-Jacobi solve, n={ns}")
         tc = time.perf_counter()
         r = oracle.syev(A, tol=args.tol if args.tol > 0 else oracle.DEFAULT_TOL)
         dt = time.perf_counter() - tc
-        scale = (n / ns) ** 3
-        cpu = {"value": 1.0 / (dt * scale), "unit": "eigensolves/s", "cores": 1, "kind": "oracle",
-               "sample": f"one full oracle solve (cyclic Jacobi, FP64, 1 thread) of the {ns}x{ns} "
-                         f"U[-1,1] matrix of the same family: {dt:.2f} s, {r.sweeps} sweeps; "
-                         f"scaled by (n/{ns})^3 = {scale:.0f} to n={n}",
+        cpu = {"value": round(1.0 / dt, 6), "unit": "eigensolves/s", "cores": 1, "kind": "oracle", "n": ns,
+               "sample": f"one full oracle solve (row-cyclic Jacobi, FP64, 1 thread) of the {ns}x{ns} "
+                         f"U[-1,1] matrix of the same family: {dt:.2f} s, {r.sweeps} sweeps (measured at "
+                         f"n={ns}, not scaled to n={n})",
                "cpu": _cpu_model()}
 
     out = {"metric": METRIC, "value": round(value, 4), "unit": "eigensolves/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+           "ms_per_step_spread": {"median": round(float(np.median(step_s)) * 1e3, 3),
+                                  "min": round(min(step_s) * 1e3, 3), "max": round(max(step_s) * 1e3, 3)},
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": f"preconditioned pipeline (FP32 eig -> FP64 MGS -> FP64 Q^T A Q -> "

@@ -95,7 +95,9 @@ typedef struct jac_stats {
   long long fp32_step_launches;
   /* With opts.profile: per kernel class, summed HIP-event time, launch count and
    * work done.  Classes: 0 FP64 inner solve, 1 FP64 block update, 2 FP32 inner
-   * solve, 3 FP32 block update, 4 FP64 element step, 5 FP32 element step.
+   * solve, 3 FP32 block update, 4 FP64 element step, 5 FP32 element step,
+   * 6 tridiagonal step 1: the reduction (one cooperative launch), 7 tridiagonal
+   * step 1: bisection, eigenvectors of T and back-transformation.
    * Events bracket each run of consecutive launches of one class (the inner
    * launches of a block sweep, the steps of an element sweep), not each launch.
    * The inner-solve launches of block steps after the first also carry the
@@ -104,9 +106,9 @@ typedef struct jac_stats {
    * kern_work of the inner and update classes: 64x64 T tiles (high 32 bits)
    * and 64-row V chunks (low 32 bits) updated in those launches; element
    * classes: steps. */
-  double kern_ms[6];
-  long long kern_launches[6];
-  long long kern_work[6];
+  double kern_ms[8];
+  long long kern_launches[8];
+  long long kern_work[8];
   double start_resid;      /* precond MLP: ||off(Q^T A Q)||_F / ||A||_F of the predicted start */
   int fp32_method;         /* step 1 that ran: 0 none, 1 FP32 Jacobi, 2 tridiagonal */
 } jac_stats;

@@ -367,8 +367,8 @@ static int fp32_stage(const void* A, bool a_dbl, int n, int lda, double nrmA, do
     if (launches) *launches = 0;
     if (step_ms) *step_ms = 0;
     double* w = d32 ? c.take<double>(n) : nullptr;
-    int e = a_dbl ? eig_tridiag_f32<double>((const double*)A, n, lda, Z, ldz, w, c, s, no_split)
-                  : eig_tridiag_f32<float>((const float*)A, n, lda, Z, ldz, w, c, s, no_split);
+    int e = a_dbl ? eig_tridiag_f32<double>((const double*)A, n, lda, Z, ldz, w, c, s, no_split, prof)
+                  : eig_tridiag_f32<float>((const float*)A, n, lda, Z, ldz, w, c, s, no_split, prof);
     if (e) return e;
     if (d32) {
       e = copy_convert<double, float>(w, n, 1, n, d32, n, s);
@@ -742,7 +742,7 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
     if (prof.on) {
       unsigned long long wk[8];
       JAC_HIP(hipMemcpy(wk, hd.work, sizeof(wk), hipMemcpyDeviceToHost));
-      for (int i = 0; i < 6; ++i) {
+      for (int i = 0; i < 8; ++i) {
         stats->kern_ms[i] = prof.ms[i];
         stats->kern_launches[i] = prof.launches[i];
         stats->kern_work[i] = (long long)wk[i];

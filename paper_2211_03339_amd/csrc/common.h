@@ -39,8 +39,8 @@ struct Prof {
   int used = 0;
   struct Iv { int cls, e0, e1, count; };
   std::vector<Iv> ivs;
-  double ms[6] = {0, 0, 0, 0, 0, 0};
-  long long launches[6] = {0, 0, 0, 0, 0, 0};
+  double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  long long launches[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   unsigned long long* work = nullptr;   // device counters [6]
   int mark(hipStream_t s);              // record an event, return its id (-1 if off)
   // count launches of class cls ran back to back between events e0 and e1
@@ -348,7 +348,7 @@ size_t tridiag_bytes(int n);
 bool tridiag_supported(int n);
 template <typename TA>
 int eig_tridiag_f32(const TA* A, int n, int lda, double* Z, int ldz, double* w_out, Carve& c, hipStream_t s,
-                    bool no_split);
+                    bool no_split, Prof* prof = nullptr);
 int tridiag_reduce_entry(const double* A, int n, int lda, double* d, double* e, float* tau, float* U, int ldu,
                          hipStream_t s);
 int tridiag_eig_entry(const double* d, const double* e, int n, double* w, double* Z, int ldz, hipStream_t s);

@@ -1166,12 +1166,14 @@ static int td_backtransform(const double* U, const double* Ut, int nbp, const fl
 // may be NULL).  no_split: GEMMs without split-K (nothing allocated).
 template <typename TA>
 int eig_tridiag_f32(const TA* A, int n, int lda, double* Z, int ldz, double* w_out, Carve& c, hipStream_t s,
-                    bool no_split) {
+                    bool no_split, Prof* prof) {
   if (n <= 0) return 0;
   if (!tridiag_supported(n)) { set_error("tridiagonal FP32 stage: order above 8192"); return -2; }
   TdWork k = td_carve(c, n);
+  const int ev0 = prof ? prof->mark(s) : -1;
   int e = td_reduce<TA>(A, n, lda, k, s);
   if (e) return e;
+  const int ev1 = prof ? prof->mark(s) : -1;
   e = td_eigvals(k.d, k.e, n, k.bnd, k.w, s);
   if (e) return e;
   e = td_vectors<double>(k.d, k.e, n, k.w, k.bnd, k.dp, k.dm, k.nc, k.Y, n, s);
@@ -1180,6 +1182,11 @@ int eig_tridiag_f32(const TA* A, int n, int lda, double* Z, int ldz, double* w_o
   if (e) return e;
   e = copy_convert<double, double>(k.Y, n, n, n, Z, ldz, s);
   if (e) return e;
+  if (prof) {
+    const int ev2 = prof->mark(s);
+    prof->interval(6, ev0, ev1, 1);
+    prof->interval(7, ev1, ev2, 1);
+  }
   if (w_out) {
     e = copy_convert<double, double>(k.w, n, 1, n, w_out, n, s);
     if (e) return e;
@@ -1187,8 +1194,9 @@ int eig_tridiag_f32(const TA* A, int n, int lda, double* Z, int ldz, double* w_o
   return td_abort_check(k, s);
 }
 
-template int eig_tridiag_f32<double>(const double*, int, int, double*, int, double*, Carve&, hipStream_t, bool);
-template int eig_tridiag_f32<float>(const float*, int, int, double*, int, double*, Carve&, hipStream_t, bool);
+template int eig_tridiag_f32<double>(const double*, int, int, double*, int, double*, Carve&, hipStream_t, bool,
+                                     Prof*);
+template int eig_tridiag_f32<float>(const float*, int, int, double*, int, double*, Carve&, hipStream_t, bool, Prof*);
 
 // ---- stage entry points (parity tests) -----------------------------------------------------
 

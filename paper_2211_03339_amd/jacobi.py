@@ -45,18 +45,19 @@ class JacStats(ctypes.Structure):
                 ("off_hist", ctypes.c_double * JAC_HIST), ("stage_ms", ctypes.c_float * 8),
                 ("step_ms", ctypes.c_double), ("step_launches", ctypes.c_longlong),
                 ("fp32_step_ms", ctypes.c_double), ("fp32_step_launches", ctypes.c_longlong),
-                ("kern_ms", ctypes.c_double * 6), ("kern_launches", ctypes.c_longlong * 6),
-                ("kern_work", ctypes.c_longlong * 6), ("start_resid", ctypes.c_double),
+                ("kern_ms", ctypes.c_double * 8), ("kern_launches", ctypes.c_longlong * 8),
+                ("kern_work", ctypes.c_longlong * 8), ("start_resid", ctypes.c_double),
                 ("fp32_method", ctypes.c_int)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_
              if f not in ("off_hist", "stage_ms", "kern_ms", "kern_launches", "kern_work")}
-        names = ["inner64", "update64", "inner32", "update32", "elem64", "elem32"]
+        names = ["inner64", "update64", "inner32", "update32", "elem64", "elem32", "tridiag_reduce",
+                 "tridiag_rest"]
         d["kernels"] = {names[i]: {"ms": self.kern_ms[i], "launches": self.kern_launches[i],
                                    "tiles": self.kern_work[i] >> 32 if i < 4 else 0,
                                    "chunks": self.kern_work[i] & 0xFFFFFFFF if i < 4 else 0}
-                        for i in range(6) if self.kern_launches[i]}
+                        for i in range(8) if self.kern_launches[i]}
         d["off_hist"] = list(self.off_hist[: self.sweeps + 1])
         d["stage_ms"] = dict(zip(["start", "mgs", "similarity", "sweeps", "output", "total", "checks"],
                                  list(self.stage_ms)[:7]))
