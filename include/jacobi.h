@@ -134,7 +134,7 @@ int syev_jacobi_ex(const double* A, int n, int lda, double* W, double* V, int ld
  * process ends.  The call allocates nothing (no device memory, no events):
  *  - opts NULL or precond NONE / FP32 (other starts return -8);
  *  - returns -2 ("n too large") when jac_workspace_bytes(n, opts) exceeds
- *    JAC_NOALLOC_BYTES (n <= 640 preconditioned, n <= 995 plain);
+ *    JAC_NOALLOC_BYTES (n <= 524 preconditioned, n <= 995 plain);
  *  - stats (may be NULL): sweeps, rotations, norms and the off history are
  *    filled; stage_ms, step_ms and kern_* stay zero (timing needs events);
  *  - the GEMMs of Q^T A Q run without split-K (same sums, other order than
@@ -280,6 +280,14 @@ int jac_round_robin_pairs(int ne, int r, int* p, int* q);
  * becomes orthonormal with the column order and signs of the input
  * (Algorithm 4.1 step 2).  Returns +3 on a zero column. */
 int jac_mgs(double* Q, int m, int n, int ldq, void* stream);
+
+/* Step 2 as the pipeline runs it: Q (n x n, ldq >= n, in place) becomes the
+ * orthonormal factor of its QR factorization with a positive R diagonal (the
+ * factor MGS returns; Algorithm 4.1 step 2, Lemma MGS).  When ||Q^T Q - I||_F
+ * <= 1e-3 it is evaluated as Q R^{-1} from a second-order series for R (four
+ * FP64 GEMMs; error O(||Q^T Q - I||^3)), otherwise by block MGS.  method (host,
+ * may be NULL): 1 series, 2 block MGS.  Returns +3 on a zero column. */
+int jac_qr_orth(double* Q, int n, int ldq, int* method, void* stream);
 
 /* T = Q^T A Q (Algorithm 4.1 step 3), FP64: upper triangle computed, mirrored.
  * A, Q, T: n x n. */

@@ -135,6 +135,7 @@ static size_t syev_bytes(int n, int precond) {
   if (precond != JAC_PRECOND_NONE) {
     b += 2 * align_up((size_t)n * n * 8, 256);     // GEMM scratch W, T0
     b += align_up(mgs_scratch_elems(n, n) * 8, 256);
+    b += 2 * align_up((size_t)n * n * 8, 256) + align_up((size_t)(2 * n + 64) * 8, 256);   // step-2 series
     b += stage1_bytes(n);
   }
   return b + 64 * 256;
@@ -580,9 +581,21 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
     double* T0 = c.take<double>((size_t)n * n);
     T0p = T0;
     double* mscr = c.take<double>(mgs_scratch_elems(n, n));
+    double* oB3 = c.take<double>((size_t)n * n);
+    double* oB4 = c.take<double>((size_t)n * n);
+    double* opart = c.take<double>((size_t)2 * n + 64);
     bool accepted = false;
     bool mgs_done = false;   // the tridiagonal start is orthogonalised inside the stage-1 block
     int method1 = 0;
+    // Step 2: the QR factor of the start (what MGS returns), by the series on the matrix cores when
+    // the start is nearly orthonormal, else by block MGS.
+    auto step2 = [&](double* Zs) -> int {
+      int used = 0;
+      int r = orth_series_f64(Zs, n, n, Wg, T0, oB3, oB4, opart, hd.scal + 3, &used, s, fixed);
+      if (r) return r;
+      if (!used) return mgs_f64(Zs, n, n, n, mscr, hd.flag, s);
+      return 0;
+    };
     if (pre == JAC_PRECOND_MLP) {
       // Learned start: Z -> MGS -> T = Q^T A Q; kept when ||off(T)||_F / ||A||_F <= fallback_tol
       // and MGS met no zero column, else replaced by the FP32 start.
@@ -635,7 +648,7 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
         // A tridiagonal start whose columns MGS cannot orthogonalise (a zero column: eigenvectors of
         // T computed for numerically equal eigenvalues) is replaced by the FP32 Jacobi start.
         tm.mark(2);
-        e = mgs_f64(Vw, n, n, n, mscr, hd.flag, s);
+        e = step2(Vw);
         if (e) return e;
         JAC_HIP(hipMemcpyAsync(&hflag, hd.flag, 4, hipMemcpyDeviceToHost, s));
         JAC_HIP(hipStreamSynchronize(s));
@@ -663,7 +676,7 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
     if (!accepted) {
       if (!mgs_done) {
         tm.mark(2);
-        e = mgs_f64(Vw, n, n, n, mscr, hd.flag, s);
+        e = step2(Vw);
         if (e) return e;
       }
       tm.mark(3);
@@ -1181,6 +1194,40 @@ int jac_mgs(double* Q, int m, int n, int ldq, void* stream) {
   int hf = 0;
   JAC_HIP(hipMemcpyAsync(&hf, flag, 4, hipMemcpyDeviceToHost, s));
   JAC_HIP(hipStreamSynchronize(s));
+  if (hf) { set_error("modified Gram-Schmidt met a zero column"); return 3; }
+  return 0;
+}
+
+int jac_qr_orth(double* Q, int n, int ldq, int* method, void* stream) {
+  g_err.clear();
+  if (!Q && n > 0) { set_error("Q is NULL"); return -1; }
+  if (n < 0 || n > 8192) { set_error("need 0 <= n <= 8192"); return -2; }
+  if (ldq < (n > 1 ? n : 1)) { set_error("ldq < max(1,n)"); return -3; }
+  if (method) *method = 0;
+  if (n == 0) return 0;
+  hipStream_t s = as_stream(stream);
+  void* ws = workspace(4 * align_up((size_t)n * n * 8, 256) + align_up((size_t)(2 * n + 64) * 8, 256) +
+                       align_up(mgs_scratch_elems(n, n) * 8, 256) + 8192);
+  if (!ws) { set_error("workspace allocation failed"); return 4; }
+  Carve c(ws);
+  int* flag = c.take<int>(16);
+  double* scal = c.take<double>(8);
+  double* B[4];
+  for (int i = 0; i < 4; ++i) B[i] = c.take<double>((size_t)n * n);
+  double* part = c.take<double>((size_t)2 * n + 64);
+  double* mscr = c.take<double>(mgs_scratch_elems(n, n));
+  JAC_HIP(hipMemsetAsync(flag, 0, 64, s));
+  int used = 0;
+  int e = orth_series_f64(Q, n, ldq, B[0], B[1], B[2], B[3], part, scal, &used, s, false);
+  if (e) return e;
+  if (!used) {
+    e = mgs_f64(Q, n, n, ldq, mscr, flag, s);
+    if (e) return e;
+  }
+  int hf = 0;
+  JAC_HIP(hipMemcpyAsync(&hf, flag, 4, hipMemcpyDeviceToHost, s));
+  JAC_HIP(hipStreamSynchronize(s));
+  if (method) *method = used ? 1 : 2;
   if (hf) { set_error("modified Gram-Schmidt met a zero column"); return 3; }
   return 0;
 }

@@ -354,6 +354,11 @@ int tridiag_reduce_entry(const double* A, int n, int lda, double* d, double* e, 
 int tridiag_eig_entry(const double* d, const double* e, int n, double* w, double* Z, int ldz, hipStream_t s);
 int tridiag_backtransform_entry(const float* U, int ldu, const float* tau, int n, double* Y, int ldy, hipStream_t s);
 
+// Step 2 for nearly orthonormal Z (orth.hip): Q = Z R^{-1} by the second-order series; *used = 0
+// (Z unchanged) when ||Z^T Z - I||_F is too large for it.
+int orth_series_f64(double* Z, int n, int ldz, double* B1, double* B2, double* B3, double* B4, double* part,
+                    double* scal, int* used, hipStream_t s, bool no_split);
+
 // Block modified Gram-Schmidt in place (mgs.hip).  Returns 0 or 3 on breakdown.
 int mgs_f64(double* Q, int m, int n, int ldq, double* scratch, int* flag, hipStream_t s);
 size_t mgs_scratch_elems(int m, int n);

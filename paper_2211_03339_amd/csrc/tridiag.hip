@@ -682,18 +682,28 @@ __global__ __launch_bounds__(256) void tri_bounds_kernel(const double* d, const 
 // ratio m_i / m_(i-1) is the i-th pivot of the LDL^T factorization, so a sign change is a
 // negative pivot.  No division: every 16 steps both kept minors are scaled by the same power of
 // two (exact), and a zero minor is replaced by -pivmin times its predecessor (a pivot of -pivmin).
-__device__ __forceinline__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int n,
+__device__ __forceinline__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int n16,
                                            double x, double pivmin) {
+  // d, e2: n16 (a multiple of 16) entries, padded past n with d = (above every eigenvalue),
+  // e^2 = 0, which add positive pivots and no sign change
   double m1 = 1.0, m0 = 0.0;   // m_(i-1), m_(i-2)
+  double em = 0.0;             // e_(i-1)^2 (zero before the first row)
   int c = 0;
-  for (int i0 = 0; i0 < n; i0 += 16) {
-    const int i1 = i0 + 16 < n ? i0 + 16 : n;
-    for (int i = i0; i < i1; ++i) {
-      double m = fma(d[i] - x, m1, i > 0 ? -e2[i - 1] * m0 : 0.0);
+  for (int i0 = 0; i0 < n16; i0 += 16) {
+    double dd[16], ee[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      dd[u] = d[i0 + u];
+      ee[u] = e2[i0 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      double m = fma(dd[u] - x, m1, -em * m0);
       if (m == 0.0) m = -pivmin * m1;
       c += (m < 0.0) != (m1 < 0.0);
       m0 = m1;
       m1 = m;
+      em = ee[u];
     }
     int ex;
     (void)frexp(fabs(m1) + fabs(m0), &ex);
@@ -714,10 +724,12 @@ __global__ __launch_bounds__(kBisThreads) void tri_bisect_kernel(const double* _
                                                                 const double* __restrict__ bnd,
                                                                 double* __restrict__ w) {
   extern __shared__ double bis_smem[];
+  const int n16 = (n + 15) / 16 * 16;
   double* sd = bis_smem;
-  double* se2 = bis_smem + n;
-  for (int i = threadIdx.x; i < n; i += kBisThreads) {
-    sd[i] = d[i];
+  double* se2 = bis_smem + n16;
+  const double dpad = bnd[1] + 1.0 + fabs(bnd[1]);
+  for (int i = threadIdx.x; i < n16; i += kBisThreads) {
+    sd[i] = i < n ? d[i] : dpad;
     se2[i] = i + 1 < n ? e[i] * e[i] : 0.0;
   }
   __syncthreads();
@@ -734,7 +746,7 @@ __global__ __launch_bounds__(kBisThreads) void tri_bisect_kernel(const double* _
     // both groups of a wave run every round (ballot / shuffle span the wave); finished ones idle
     if (__all(done)) break;
     const double x = lo + width * (double)(lane + 1) / (double)(kBisLanes + 1);
-    const bool below = !done && sturm_count(sd, se2, n, x, pivmin) <= k;   // the k-th eigenvalue is >= x
+    const bool below = !done && sturm_count(sd, se2, n16, x, pivmin) <= k;   // the k-th eigenvalue is >= x
     const unsigned long long m = (__ballot(below) >> half) & ((1ull << kBisLanes) - 1);
     const int hb = m ? 63 - __clzll(m) : -1;                       // last point with count <= k
     const double xl = __shfl(x, half + (hb < 0 ? 0 : hb), 64);
@@ -1105,7 +1117,7 @@ static int td_abort_check(const TdWork& k, hipStream_t s) {
 static int td_eigvals(const double* d, const double* e, int n, double* bnd, double* w, hipStream_t s) {
   hipLaunchKernelGGL(tri_bounds_kernel, dim3(1), dim3(256), 0, s, d, e, n, bnd);
   JAC_CHECK_LAUNCH();
-  const size_t bsh = (size_t)2 * n * sizeof(double);
+  const size_t bsh = (size_t)2 * ((n + 15) / 16 * 16) * sizeof(double);
   JAC_HIP(hipFuncSetAttribute((const void*)tri_bisect_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bsh));
   hipLaunchKernelGGL(tri_bisect_kernel, dim3(tcdiv(n, kBisThreads / kBisLanes)), dim3(kBisThreads), bsh, s, d, e, n, bnd,
                      w);

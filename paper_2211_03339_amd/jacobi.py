@@ -105,6 +105,7 @@ def load():
         "jac_round_robin_pairs": (_i, [_i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
         "jac_mgs": (_i, [_vp, _i, _i, _i, _vp]),
         "jac_similarity": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp]),
+        "jac_qr_orth": (_i, [_vp, _i, _i, ctypes.POINTER(_i), _vp]),
         "jac_eig_fp32": (_i, [_vp, _i, _i, _vp, _i, _vp, _d, _i, ctypes.POINTER(_i), _vp]),
         "jac_sytrd_f32": (_i, [_vp, _i, _i, _vp, _vp, _vp, _vp, _i, _vp]),
         "jac_tridiag_eig": (_i, [_vp, _vp, _i, _vp, _vp, _i, _vp]),
@@ -399,6 +400,17 @@ def jac_mgs(Z: torch.Tensor):
     code = L.jac_mgs(_vp(Qc.data_ptr()), m, n, max(m, 1), _stream())
     _check("jac_mgs", code)
     return Qc.t()
+
+
+def jac_qr_orth(Z: torch.Tensor):
+    """Step 2 as the pipeline runs it: returns (Q, method) with method 1 (series) or 2 (block MGS)."""
+    L = load()
+    n = Z.shape[0]
+    Qb = _colmajor(_dev(Z))
+    meth = ctypes.c_int(0)
+    code = L.jac_qr_orth(_vp(Qb.data_ptr()), n, max(n, 1), ctypes.byref(meth), _stream())
+    _check("jac_qr_orth", code)
+    return Qb.t(), meth.value
 
 
 def jac_similarity(A: torch.Tensor, Q: torch.Tensor):
