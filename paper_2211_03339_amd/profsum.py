@@ -2,6 +2,8 @@
 
   python -m paper_2211_03339_amd.profsum stats KERNEL_STATS_CSV OUT_TXT "COMMAND"
       per-kernel calls / total / average / min / max duration from `rocprofv3 --kernel-trace --stats`.
+  python -m paper_2211_03339_amd.profsum stats-db DB_DIR OUT_TXT "COMMAND"
+      the same table from the rocpd database (*_results.db) of a `rocprofv3 --kernel-trace` run.
   python -m paper_2211_03339_amd.profsum traffic FETCH_CSV WRITE_CSV COPY_FETCH_CSV COPY_WRITE_CSV COPY_BYTES
       OUT_JSON SOURCES "COMMANDS"
       mean FETCH_SIZE / WRITE_SIZE per dispatch and kernel from two `rocprofv3 --pmc` runs, each
@@ -43,6 +45,29 @@ def stats(csv_path: str, out_path: str, command: str):
         f.write("\n".join(lines) + "\n")
 
 
+def stats_db(db_dir: str, out_path: str, command: str):
+    """The same table from the rocpd database rocprofv3 writes (*_results.db): rocprofv3 can end
+    with a fault of its own after a cooperative launch, before it writes the statistics CSV, while
+    the database of the finished run is complete."""
+    import glob
+    import sqlite3
+    db = sorted(glob.glob(db_dir.rstrip("/") + "/*.db"))[0]
+    cur = sqlite3.connect(db).cursor()
+    durs = defaultdict(list)
+    for name, st, en in cur.execute("select s.display_name, d.start, d.end from rocpd_kernel_dispatch d "
+                                    "join rocpd_info_kernel_symbol s on d.kernel_id = s.id"):
+        durs[_short(name)].append(en - st)
+    total = sum(sum(v) for v in durs.values())
+    lines = [f"# rocprofv3 kernel statistics (from the kernel-trace database)", f"# command: {command}", "",
+             f"{'kernel':70s} {'calls':>7s} {'total ms':>10s} {'avg us':>9s} {'min us':>9s} {'max us':>9s} {'share':>6s}"]
+    for k, v in sorted(durs.items(), key=lambda kv: -sum(kv[1])):
+        tot = float(sum(v))
+        lines.append(f"{k[:70]:70s} {len(v):7d} {tot / 1e6:10.3f} {tot / len(v) / 1e3:9.2f} {min(v) / 1e3:9.2f} "
+                     f"{max(v) / 1e3:9.2f} {tot / total:6.3f}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def _per_kernel(path, counter):
     acc = defaultdict(list)
     for r in _rows(path):
@@ -76,6 +101,8 @@ def traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv, copy_bytes, out_json, 
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "stats-db":
+        stats_db(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:10])
     else:
