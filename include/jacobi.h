@@ -9,8 +9,8 @@
  *    X[i + j*ldx].  Matrix/vector pointers are DEVICE pointers (hipMalloc'd or
  *    a torch tensor's data pointer) unless an argument says "host".
  *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
- *    Calls without the _batched suffix are synchronous: they return after the
- *    results are written.
+ *    Every compute call is synchronous: it returns after the results are
+ *    written.
  *  - Ownership: the caller owns every buffer it passes; the library never
  *    frees or retains them.  The library allocates its own device workspace
  *    (grow-only, kept until jac_release_workspace()).
@@ -169,31 +169,70 @@ int gesvd_jacobi(const double* A, int m, int n, int lda, double* S, double* U, i
 int gesvd_jacobi_ex(const double* A, int m, int n, int lda, double* S, double* U, int ldu, double* V, int ldv,
                     double tol, const jac_opts* opts, jac_stats* stats, void* stream);
 
-/* Batched symmetric eigendecompositions (plain FP64 Jacobi, blocked variant)
- * of `batch` independent matrices of order n[i] in [1, 512].  Host arrays:
- * n, A (device pointers to column-major n[i] x n[i] inputs, read only), lda,
- * W (device pointers, n[i] eigenvalues ascending), V (device pointers,
- * n[i] x n[i] eigenvectors, leading dimension ldv[i]).  Device arrays (may be
- * NULL): sweeps[i] = sweeps until ||off(T)||_F <= tol ||A_i||_F first held,
- * info[i] = 0 converged / 1 not converged within the tuned sweep count.
- * tol <= 0 selects 20 * 2^-53.  Asynchronous: the whole solve is one graph
- * launch on `stream` (the graph is built on the first call with these sizes
- * and pointers and replayed afterwards).  Results are valid once the stream
- * has completed.  Inputs must not change shape between calls that reuse it. */
+/* Batched symmetric eigendecompositions (blocked variant) of `batch` <= 65535
+ * independent matrices of order n[i] in [1, 512].  Host arrays: n, A (device
+ * pointers to column-major n[i] x n[i] inputs, read only), lda, W (device
+ * pointers, n[i] eigenvalues ascending), V (device pointers, n[i] x n[i]
+ * eigenvectors, leading dimension ldv[i]).  Device arrays (may be NULL):
+ * sweeps[i] = FP64 sweeps until ||off(T)||_F <= tol ||A_i||_F first held
+ * (max_sweeps when it never did), info[i] = 0 converged / 1 not converged
+ * within max_sweeps.  tol <= 0 selects 20 * 2^-53.
+ * Each matrix stops at its own convergence: its results do not depend on the
+ * rest of the batch.  The solve is one graph launch on `stream` (built on the
+ * first call with these sizes, pointers and options, replayed afterwards),
+ * then a host check of the convergence flags: size classes with unconverged
+ * matrices get further sweeps up to max_sweeps.  Synchronous. */
 int syev_jacobi_batched(int batch, const int* n, const double* const* A, const int* lda, double* const* W,
                         double* const* V, const int* ldv, double tol, int* sweeps, int* info, void* stream);
 
-/* Autotuner of the batched path: for every size class (order rounded up to 64)
- * present in the batch, times the inner-sweep caps 1..4 on up to 16 of the
- * given matrices and keeps the fastest one that converges, with its sweep
- * count.  The table is used by later syev_jacobi_batched calls in this process
- * and written to the file named by the environment variable JACOBI_TUNE_CACHE
- * (read back at the first use in a later process).  Synchronous. */
+/* Options of the batched path (NULL: all defaults). */
+typedef struct jac_batched_opts {
+  int precond;        /* JAC_PRECOND_NONE (plain, Algorithm 3.2) or JAC_PRECOND_FP32:
+                         Algorithm 4.1 per matrix -- FP32 blocked Jacobi on fl32(A)
+                         truncated at fp32_tol ||A||_F, the QR factor of its
+                         eigenvectors (series passes; a matrix whose start they
+                         cannot orthogonalise takes the plain start), T0 = Q^T A Q */
+  double fp32_tol;    /* stop of the FP32 stage; <= 0: 1e-4 */
+  int max_sweeps;     /* FP64 sweep cap including the top-up; 0: 60 (at most 1000) */
+  int reserved;       /* must be 0 */
+} jac_batched_opts;
+
+/* Host statistics of one batched call. */
+typedef struct jac_batched_stats {
+  int topup_sweeps;   /* sweeps run after the graph (summed over size classes) */
+  int series_failed;  /* JAC_PRECOND_FP32: matrices that fell back to the plain start */
+  int graph_built;    /* 1 when this call captured a new graph */
+  int classes;        /* size classes (orders rounded up to 64) */
+} jac_batched_stats;
+
+/* syev_jacobi_batched with options and statistics.  sweeps32 (device, may be
+ * NULL): FP32 sweeps per matrix (0 without preconditioning).  Error -12: bad
+ * option. */
+int syev_jacobi_batched_ex(int batch, const int* n, const double* const* A, const int* lda, double* const* W,
+                           double* const* V, const int* ldv, double tol, int* sweeps, int* info, int* sweeps32,
+                           const jac_batched_opts* opts, jac_batched_stats* stats, void* stream);
+
+/* Autotuner of the batched path: for every size class present in the batch,
+ * runs up to 16 of the given matrices with each inner-sweep cap 1..4 (with the
+ * options' preconditioning), takes the sweeps the samples needed in each
+ * stage, times that configuration and keeps the fastest.  The block size 2b is
+ * fixed at 64 (the width of the matrix-core tiles).  The table is used by
+ * later batched calls in this process and written to the file named by the
+ * environment variable JACOBI_TUNE_CACHE (read back at the first use in a
+ * later process).  Synchronous. */
 int jac_autotune_batched(int batch, const int* n, const double* const* A, const int* lda, double tol,
                          void* stream);
+int jac_autotune_batched_ex(int batch, const int* n, const double* const* A, const int* lda, double tol,
+                            const jac_batched_opts* opts, void* stream);
 
-/* Host: the (inner-sweep cap, sweep count) the batched path uses for order n. */
+/* Host: the (inner-sweep cap, FP64 sweeps[, FP32 sweeps]) the batched path
+ * uses for order n (1..512) without / with preconditioning. */
 int jac_tune_entry(int n, int* inner_sweeps, int* sweeps);
+int jac_tune_entry_ex(int n, int precond, int* inner_sweeps, int* sweeps, int* sweeps32);
+
+/* Host: forget the tuned table of this process (the built-in defaults apply
+ * until the autotuner runs again; the cache file is not read again). */
+int jac_tune_clear(void);
 
 /* ---- Learned warm start (a project addition; not in the paper) ------------
  * A three-layer perceptron theta (n_in values) -> hidden -> ReLU -> hidden ->

@@ -614,6 +614,7 @@ blk_inner_kernel(T* __restrict__ Tm, int ldt, int n, int m2, int r, T* __restric
                  int gsplit, int npair, T rel, const BDesc<T>* __restrict__ desc) {
   if (desc) {   // batched: matrix blockIdx.y of a size class
     const BDesc<T> d = desc[blockIdx.y];
+    if (*d.conv >= 0) return;   // converged in an earlier sweep
     Tm = d.Tm; ldt = d.ldt; n = d.n; Eall = d.E; ident = d.ident; rot = d.rot;
     skip_abs = (T)(d.tol_n * sqrt(*d.nrm2));
   }
@@ -839,6 +840,7 @@ blk_update_kernel(T* __restrict__ Tm, int ldt, T* __restrict__ V, int ldv, int n
                   unsigned long long* __restrict__ work, const BDesc<T>* __restrict__ desc = nullptr) {
   if (desc) {   // batched: matrix blockIdx.y of a size class
     const BDesc<T> d = desc[blockIdx.y];
+    if (*d.conv >= 0) return;   // converged in an earlier sweep
     Tm = d.Tm; ldt = d.ldt; V = d.V; ldv = d.ldv; nvr = d.n; Eall = d.E; ident = d.ident;
   }
   constexpr int b = kB2 / 2;
@@ -1479,121 +1481,8 @@ int blk_sweep_batched(const BDesc<T>* desc, int count, int np, int max_nvr, int 
   return 0;
 }
 
-// Per-matrix setup: T <- [A 0; 0 0] (np x np), V <- [I 0] (n x np), identity flags.
-template <typename T>
-__global__ void batched_init_kernel(const BDesc<T>* __restrict__ desc, const double* const* __restrict__ A,
-                                    const int* __restrict__ lda) {
-  const BDesc<T> d = desc[blockIdx.y];
-  const double* a = A[blockIdx.y];
-  const int la = lda[blockIdx.y];
-  const int np = d.ldt;
-  const long long total = (long long)np * np;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    int i = (int)(e % np), j = (int)(e / np);
-    d.Tm[i + (size_t)j * np] = (i < d.n && j < d.n) ? (T)a[i + (size_t)j * la] : T(0);
-    if (i < d.n) d.V[i + (size_t)j * d.ldv] = i == j ? T(1) : T(0);
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *d.rot = 0;
-}
-
-// Per matrix: ||off(T)||_F^2 and ||T||_F^2 (one workgroup per matrix, fixed order).
-template <typename T>
-__global__ void batched_norms_kernel(const BDesc<T>* __restrict__ desc, double* __restrict__ out) {
-  __shared__ double red[2][4];
-  const BDesc<T> d = desc[blockIdx.x];
-  const int np = d.ldt;
-  double off = 0, all = 0;
-  for (long long e = threadIdx.x; e < (long long)np * np; e += blockDim.x) {
-    int i = (int)(e % np), j = (int)(e / np);
-    double v = d.Tm[i + (size_t)j * np];
-    all += v * v;
-    if (i != j) off += v * v;
-  }
-  for (int o = 32; o > 0; o >>= 1) { off += __shfl_down(off, o, 64); all += __shfl_down(all, o, 64); }
-  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = off; red[1][threadIdx.x >> 6] = all; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    out[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    out[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
-  }
-}
-
-// Per matrix: W ascending with V's columns permuted alike, info (0 if
-// ||off(T)||_F <= tol ||A||_F after the last sweep, else 1) and the number of
-// sweeps until that test first held (norms[s] = (off^2, ||T||^2) after s sweeps).
-template <typename T>
-__global__ void batched_finish_kernel(const BDesc<T>* __restrict__ desc, double* const* __restrict__ W,
-                                      double* const* __restrict__ V, const int* __restrict__ ldv,
-                                      const double* __restrict__ norms, int stride, int nsweeps, double tol,
-                                      const int* __restrict__ orig, int* __restrict__ sweeps_out,
-                                      int* __restrict__ info) {
-  __shared__ int rank[512];
-  const BDesc<T> d = desc[blockIdx.x];
-  const int n = d.n;
-  double* w = W[blockIdx.x];
-  double* v = V[blockIdx.x];
-  const int lv = ldv[blockIdx.x];
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    T di = d.Tm[i + (size_t)i * d.ldt];
-    int rk = 0;
-    for (int j = 0; j < n; ++j) {
-      T dj = d.Tm[j + (size_t)j * d.ldt];
-      rk += (dj < di) || (dj == di && j < i);
-    }
-    rank[i] = rk;
-    w[rk] = (double)di;
-  }
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    const int rk = rank[j];
-    for (int row = threadIdx.x; row < n; row += blockDim.x)
-      v[row + (size_t)rk * lv] = (double)d.V[row + (size_t)j * d.ldv];
-  }
-  if (threadIdx.x == 0) {
-    const double nrm = sqrt(norms[2 * (size_t)blockIdx.x + 1]);
-    int first = -1;
-    for (int sw = 0; sw <= nsweeps; ++sw) {
-      double off = sqrt(norms[(size_t)sw * stride + 2 * (size_t)blockIdx.x]);
-      if (off <= tol * nrm) { first = sw; break; }
-    }
-    const int o = orig[blockIdx.x];
-    if (info) info[o] = first < 0 ? 1 : 0;
-    if (sweeps_out) sweeps_out[o] = first < 0 ? nsweeps : first;
-  }
-}
-
-template <typename T>
-int batched_init(const BDesc<T>* desc, int count, int maxnp, const double* const* A, const int* lda, hipStream_t s) {
-  int gx = cdiv((long long)maxnp * maxnp, 256);
-  if (gx > 64) gx = 64;
-  hipLaunchKernelGGL((batched_init_kernel<T>), dim3(gx, count), dim3(256), 0, s, desc, A, lda);
-  JAC_CHECK_LAUNCH();
-  return 0;
-}
-
-template <typename T>
-int batched_norms(const BDesc<T>* desc, int count, double* out, hipStream_t s) {
-  hipLaunchKernelGGL((batched_norms_kernel<T>), dim3(count), dim3(256), 0, s, desc, out);
-  JAC_CHECK_LAUNCH();
-  return 0;
-}
-
-template <typename T>
-int batched_finish(const BDesc<T>* desc, int count, double* const* W, double* const* V, const int* ldv,
-                   const double* norms, int stride, int nsweeps, double tol, const int* orig, int* sweeps_out,
-                   int* info, hipStream_t s) {
-  hipLaunchKernelGGL((batched_finish_kernel<T>), dim3(count), dim3(256), 0, s, desc, W, V, ldv, norms, stride,
-                     nsweeps, tol, orig, sweeps_out, info);
-  JAC_CHECK_LAUNCH();
-  return 0;
-}
-
 template int blk_sweep_batched<double>(const BDesc<double>*, int, int, int, int, hipStream_t);
-template int batched_init<double>(const BDesc<double>*, int, int, const double* const*, const int*, hipStream_t);
-template int batched_norms<double>(const BDesc<double>*, int, double*, hipStream_t);
-template int batched_finish<double>(const BDesc<double>*, int, double* const*, double* const*, const int*,
-                                    const double*, int, int, double, const int*, int*, int*, hipStream_t);
+template int blk_sweep_batched<float>(const BDesc<float>*, int, int, int, int, hipStream_t);
 
 #define INST(T)                                                                    \
   template int blk_load<T>(BlkState<T>&, const void*, bool, int, hipStream_t);     \

@@ -265,12 +265,15 @@ int elem_diag(const ElemState<T>& st, T* d, hipStream_t s);  // logical-order di
 template <typename T>
 struct BDesc {
   T* Tm;                    // np x np, ldt = np
-  T* V;                     // n x np, leading dimension ldv
+  T* V;                     // np x np, leading dimension ldv (rows >= n: the identity's, never touched)
   T* E;                     // (np / 64) pairs x 64 x 64
   int* ident;               // per pair
   unsigned long long* rot;  // applied rotations of this matrix
   const double* nrm2;       // ||A||_F^2 of this matrix (written before the sweeps)
-  int n, ldt, ldv, pad;
+  const int* conv;          // sweep at which the stop test first held, -1 before: the sweep
+                            // kernels leave a matrix alone once it is >= 0
+  int n, ldt, ldv;
+  int s32;                  // FP32 sweeps the graph runs for this matrix's size class (0: none)
   double tol_n;             // tol / n: skip cap = tol_n * ||A||_F
 };
 
@@ -304,14 +307,6 @@ template <typename T>
 int blk_diag(const BlkState<T>& st, T* d, hipStream_t s);
 template <typename T>
 int blk_sweep_batched(const BDesc<T>* desc, int count, int np, int max_nvr, int max_inner, hipStream_t s);
-template <typename T>
-int batched_init(const BDesc<T>* desc, int count, int maxnp, const double* const* A, const int* lda, hipStream_t s);
-template <typename T>
-int batched_norms(const BDesc<T>* desc, int count, double* out, hipStream_t s);
-template <typename T>
-int batched_finish(const BDesc<T>* desc, int count, double* const* W, double* const* V, const int* ldv,
-                   const double* norms, int stride, int nsweeps, double tol, const int* orig, int* sweeps_out,
-                   int* info, hipStream_t s);
 
 // Utilities (util.hip).
 int fro2_f64(const double* A, int m, int n, int lda, double* partial, double* out, hipStream_t s);
@@ -341,6 +336,12 @@ int svd_sweep(T* C, int ldc, int mrows, T* V, int ldv, int n, int np, T* Ebuf, i
 template <typename T>
 int gemm(bool ta, bool tb, int m, int n, int k, T alpha, const T* A, int lda, const T* B, int ldb,
          T beta, T* C, int ldc, hipStream_t s, int max_split = 0);
+// count independent products C_z = alpha op(A_z) op(B_z) + beta C_z with A_z = A + z sA (and so on);
+// state (device, may be NULL): product z runs only when state[z] <= state_max.
+template <typename T>
+int gemm_batched(bool ta, bool tb, int m, int n, int k, T alpha, const T* A, int lda, long long sA, const T* B,
+                 int ldb, long long sB, T beta, T* C, int ldc, long long sC, int count, const int* state,
+                 int state_max, hipStream_t s);
 
 // Tridiagonal FP32 eigensolver (tridiag.hip): step 1 of Algorithm 4.1 through Householder
 // tridiagonalization, bisection, twisted-factorization eigenvectors and the back-transformation.
@@ -354,10 +355,19 @@ int tridiag_reduce_entry(const double* A, int n, int lda, double* d, double* e, 
 int tridiag_eig_entry(const double* d, const double* e, int n, double* w, double* Z, int ldz, hipStream_t s);
 int tridiag_backtransform_entry(const float* U, int ldu, const float* tau, int n, double* Y, int ldy, hipStream_t s);
 
-// Step 2 for nearly orthonormal Z (orth.hip): Q = Z R^{-1} by the second-order series; *used = 0
-// (Z unchanged) when ||Z^T Z - I||_F is too large for it.
+// Step 2 for nearly orthonormal Z (orth.hip): Q = Z R^{-1} by passes of the second-order series;
+// *used = 0 when ||Z^T Z - I||_F is too large for it (Z then holds Z S with S upper triangular, whose
+// orthonormal QR factor is Z's: the caller finishes with block MGS).
+constexpr double kSeriesMax = 0.1;      // ||Z^T Z - I||_F above which no pass is tried
+constexpr double kSeriesOnePass = 2e-5; // a pass from ||E||_F below this is final: its error ||E||^3 < 1e-14
+constexpr int kSeriesPasses = 3;
 int orth_series_f64(double* Z, int n, int ldz, double* B1, double* B2, double* B3, double* B4, double* part,
                     double* scal, int* used, hipStream_t s, bool no_split);
+// The same for count matrices of order np stored back to back (leading dimension np); per matrix
+// state[z] ends as 2 (orthonormal) or 3 (the series did not apply); e2_first[z] = ||Z^T Z - I||_F^2
+// of the start.  S1..S4: count np^2 doubles each.  A fixed list of launches (no host round trip).
+int orth_series_batched(double* Z, int np, int count, double* S1, double* S2, double* S3, double* S4, int* state,
+                        double* e2_first, hipStream_t s);
 
 // Block modified Gram-Schmidt in place (mgs.hip).  Returns 0 or 3 on breakdown.
 int mgs_f64(double* Q, int m, int n, int ldq, double* scratch, int* flag, hipStream_t s);

@@ -9,7 +9,8 @@
 // (BM/2) x (BN/2) sub-tile made of 16 x 16 MFMA tiles.  K advances in steps of
 // 16 through a double-buffered LDS stage (k-major, so the MFMA operand reads
 // are 16 consecutive elements per k).  Split-K (grid z) writes partial tiles
-// to a workspace that a second kernel sums in a fixed order.
+// to a workspace that a second kernel sums in a fixed order.  The strided-batched form (BAT) runs
+// grid z over independent products instead, each optionally switched off by a per-product state.
 #include "common.h"
 
 namespace jac {
@@ -17,10 +18,18 @@ namespace jac {
 constexpr int kBK = 16;
 constexpr int kPad = 4;
 
-template <typename T, int BM, int BN, bool TA, bool TB>
+template <typename T, int BM, int BN, bool TA, bool TB, bool BAT = false>
 __global__ void __launch_bounds__(256)
 gemm_kernel(int m, int n, int k, T alpha, const T* __restrict__ A, int lda, const T* __restrict__ B, int ldb,
-            T beta, T* __restrict__ C, int ldc, int kchunk, T* __restrict__ part) {
+            T beta, T* __restrict__ C, int ldc, int kchunk, T* __restrict__ part, long long sA = 0,
+            long long sB = 0, long long sC = 0, const int* __restrict__ state = nullptr, int state_max = 0) {
+  if (BAT) {   // product z of a strided batch; skipped when its state exceeds state_max
+    const int z = blockIdx.z;
+    if (state && state[z] > state_max) return;
+    A += z * sA;
+    B += z * sB;
+    C += z * sC;
+  }
   constexpr int WM = BM / 2, WN = BN / 2;        // wave tile
   constexpr int TM = WM / 16, TN = WN / 16;      // MFMA tiles per wave
   constexpr int LA = BM * kBK / 256;             // A elements loaded per thread
@@ -32,8 +41,8 @@ gemm_kernel(int m, int n, int k, T alpha, const T* __restrict__ A, int lda, cons
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
-  const int kb = blockIdx.z * kchunk;
-  const int ke = min(k, kb + kchunk);
+  const int kb = BAT ? 0 : blockIdx.z * kchunk;
+  const int ke = BAT ? k : min(k, kb + kchunk);
 
   acc_t acc[TM][TN];
 #pragma unroll
@@ -123,7 +132,7 @@ gemm_kernel(int m, int n, int k, T alpha, const T* __restrict__ A, int lda, cons
         int gi = i0 + wm * WM + a * 16 + Mfma<T>::row(lane, r);
         if (gi >= m) continue;
         T v = alpha * acc[a][b][r];
-        if (part) {
+        if (!BAT && part) {
           part[(size_t)blockIdx.z * m * n + gi + (size_t)gj * m] = v;
         } else {
           size_t o = gi + (size_t)gj * ldc;
@@ -219,6 +228,39 @@ int gemm(bool ta, bool tb, int m, int n, int k, T alpha, const T* A, int lda, co
   }
   return 0;
 }
+
+// C_z = alpha op(A_z) op(B_z) + beta C_z for z < count (A_z = A + z sA, ...), no split-K.  state
+// (device, may be NULL): product z runs only when state[z] <= state_max.
+template <typename T>
+int gemm_batched(bool ta, bool tb, int m, int n, int k, T alpha, const T* A, int lda, long long sA, const T* B,
+                 int ldb, long long sB, T beta, T* C, int ldc, long long sC, int count, const int* state,
+                 int state_max, hipStream_t s) {
+  if (m <= 0 || n <= 0 || count <= 0) return 0;
+  if (k <= 0) { set_error("gemm_batched: k must be positive"); return 4; }
+  if (count > 65535) { set_error("gemm_batched: more than 65535 products"); return 4; }
+  const int BM = m <= 32 ? 32 : 64, BN = n <= 32 ? 32 : 64;
+  dim3 grid(cdiv(m, BM), cdiv(n, BN), count);
+#define LB(BM_, BN_, TA_, TB_)                                                                                    \
+  hipLaunchKernelGGL((gemm_kernel<T, BM_, BN_, TA_, TB_, true>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, B, \
+                     ldb, beta, C, ldc, k, (T*)nullptr, sA, sB, sC, state, state_max)
+#define LT(BM_, BN_)                          \
+  if (!ta && !tb) LB(BM_, BN_, false, false); \
+  else if (ta && !tb) LB(BM_, BN_, true, false); \
+  else if (!ta && tb) LB(BM_, BN_, false, true); \
+  else LB(BM_, BN_, true, true)
+  if (BM == 64 && BN == 64) { LT(64, 64); }
+  else if (BM == 32 && BN == 64) { LT(32, 64); }
+  else if (BM == 64 && BN == 32) { LT(64, 32); }
+  else { LT(32, 32); }
+#undef LT
+#undef LB
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
+
+template int gemm_batched<double>(bool, bool, int, int, int, double, const double*, int, long long, const double*,
+                                  int, long long, double, double*, int, long long, int, const int*, int,
+                                  hipStream_t);
 
 template int gemm<double>(bool, bool, int, int, int, double, const double*, int, const double*, int, double,
                           double*, int, hipStream_t, int);

@@ -37,6 +37,19 @@ class JacOpts(ctypes.Structure):
                 ("inner_sweeps", ctypes.c_int), ("profile", ctypes.c_int), ("stage1", ctypes.c_int)]
 
 
+class JacBatchedOpts(ctypes.Structure):
+    _fields_ = [("precond", ctypes.c_int), ("fp32_tol", ctypes.c_double), ("max_sweeps", ctypes.c_int),
+                ("reserved", ctypes.c_int)]
+
+
+class JacBatchedStats(ctypes.Structure):
+    _fields_ = [("topup_sweeps", ctypes.c_int), ("series_failed", ctypes.c_int), ("graph_built", ctypes.c_int),
+                ("classes", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class JacStats(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int), ("fp32_sweeps", ctypes.c_int),
                 ("rotations", ctypes.c_longlong), ("fp32_rotations", ctypes.c_longlong),
@@ -98,8 +111,15 @@ def load():
         "syev_jacobi_batched": (_i, [_i, ctypes.POINTER(_i), ctypes.POINTER(_vp), ctypes.POINTER(_i),
                                      ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i), _d, _vp, _vp,
                                      _vp]),
+        "syev_jacobi_batched_ex": (_i, [_i, ctypes.POINTER(_i), ctypes.POINTER(_vp), ctypes.POINTER(_i),
+                                        ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i), _d, _vp, _vp,
+                                        _vp, ctypes.POINTER(JacBatchedOpts), ctypes.POINTER(JacBatchedStats), _vp]),
         "jac_autotune_batched": (_i, [_i, ctypes.POINTER(_i), ctypes.POINTER(_vp), ctypes.POINTER(_i), _d, _vp]),
+        "jac_autotune_batched_ex": (_i, [_i, ctypes.POINTER(_i), ctypes.POINTER(_vp), ctypes.POINTER(_i), _d,
+                                         ctypes.POINTER(JacBatchedOpts), _vp]),
         "jac_tune_entry": (_i, [_i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+        "jac_tune_entry_ex": (_i, [_i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+        "jac_tune_clear": (_i, []),
         "jac_parallel_steps": (_i, [_vp, _i, _i, _vp, _i, _i, _i, _d,
                                     ctypes.POINTER(ctypes.c_longlong), _vp]),
         "jac_round_robin_pairs": (_i, [_i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
@@ -328,7 +348,7 @@ def gesvd_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", max_sweep
 
 
 class Batch:
-    """Device buffers and pointer arrays for syev_jacobi_batched over a list of symmetric
+    """Device buffers and pointer arrays for the batched entry points over a list of symmetric
     matrices (kept alive so that repeated calls replay the same graph)."""
 
     def __init__(self, mats):
@@ -339,34 +359,64 @@ class Batch:
         self.V = [torch.empty((n, n), dtype=torch.float64, device=dev) for n in self.n]
         b = len(self.A)
         self.sweeps = torch.zeros(b, dtype=torch.int32, device=dev)
+        self.sweeps32 = torch.zeros(b, dtype=torch.int32, device=dev)
         self.info = torch.zeros(b, dtype=torch.int32, device=dev)
         self.c_n = (_i * b)(*self.n)
         self.c_A = (_vp * b)(*[a.data_ptr() for a in self.A])
         self.c_W = (_vp * b)(*[w.data_ptr() for w in self.W])
         self.c_V = (_vp * b)(*[v.data_ptr() for v in self.V])
         self.c_ld = (_i * b)(*self.n)
+        self.stats = {}
 
-    def run(self, tol: float = 0.0, stream=None):
-        L = load()
-        code = L.syev_jacobi_batched(len(self.A), self.c_n, self.c_A, self.c_ld, self.c_W, self.c_V, self.c_ld, tol,
-                                     _vp(self.sweeps.data_ptr()), _vp(self.info.data_ptr()),
-                                     stream if stream is not None else _stream())
-        _check("syev_jacobi_batched", code)
+    @staticmethod
+    def _opts(precond, fp32_tol, max_sweeps):
+        return JacBatchedOpts(PRECOND[precond], float(fp32_tol), int(max_sweeps), 0)
 
-    def autotune(self, tol: float = 0.0):
+    def run(self, tol: float = 0.0, stream=None, precond: str = "none", fp32_tol: float = 0.0, max_sweeps: int = 0,
+            plain_api: bool = False):
+        """One batched solve.  plain_api: through syev_jacobi_batched (no options) instead of the _ex
+        entry point."""
         L = load()
-        code = L.jac_autotune_batched(len(self.A), self.c_n, self.c_A, self.c_ld, tol, _stream())
+        st = stream if stream is not None else _stream()
+        if plain_api:
+            code = L.syev_jacobi_batched(len(self.A), self.c_n, self.c_A, self.c_ld, self.c_W, self.c_V, self.c_ld,
+                                         tol, _vp(self.sweeps.data_ptr()), _vp(self.info.data_ptr()), st)
+            _check("syev_jacobi_batched", code)
+            return
+        o = self._opts(precond, fp32_tol, max_sweeps)
+        s = JacBatchedStats()
+        code = L.syev_jacobi_batched_ex(len(self.A), self.c_n, self.c_A, self.c_ld, self.c_W, self.c_V, self.c_ld,
+                                        tol, _vp(self.sweeps.data_ptr()), _vp(self.info.data_ptr()),
+                                        _vp(self.sweeps32.data_ptr()), ctypes.byref(o), ctypes.byref(s), st)
+        _check("syev_jacobi_batched_ex", code)
+        self.stats = s.as_dict()
+
+    def autotune(self, tol: float = 0.0, precond: str = "none", fp32_tol: float = 0.0):
+        L = load()
+        if precond == "none" and fp32_tol == 0.0:
+            code = L.jac_autotune_batched(len(self.A), self.c_n, self.c_A, self.c_ld, tol, _stream())
+        else:
+            o = self._opts(precond, fp32_tol, 0)
+            code = L.jac_autotune_batched_ex(len(self.A), self.c_n, self.c_A, self.c_ld, tol, ctypes.byref(o),
+                                             _stream())
         _check("jac_autotune_batched", code)
 
     def results(self):
-        """(W list, V list (columns = eigenvectors), sweeps, info) after the stream completed."""
+        """(W list, V list (columns = eigenvectors), sweeps, info) after the call."""
         return self.W, [v.t() for v in self.V], self.sweeps.cpu().numpy(), self.info.cpu().numpy()
 
 
-def jac_tune_entry(n: int):
-    a, b = _i(0), _i(0)
-    load().jac_tune_entry(n, ctypes.byref(a), ctypes.byref(b))
-    return a.value, b.value
+def jac_tune_clear():
+    """Forget the batched path's tuned table of this process."""
+    load().jac_tune_clear()
+
+
+def jac_tune_entry(n: int, precond: str = "none"):
+    """(inner-sweep cap, FP64 sweeps, FP32 sweeps) of the batched path's table for order n."""
+    a, b, c = _i(0), _i(0), _i(0)
+    _check("jac_tune_entry_ex", load().jac_tune_entry_ex(n, PRECOND[precond], ctypes.byref(a), ctypes.byref(b),
+                                                        ctypes.byref(c)))
+    return a.value, b.value, c.value
 
 
 def jac_parallel_steps(T: torch.Tensor, V: torch.Tensor | None, r0: int, nsteps: int, skip_abs: float = 0.0):

@@ -1,6 +1,9 @@
-"""GPU parity of the batched path: every matrix against its known spectrum (and the oracle for
-small ones), bitwise-reproducible replays of the captured graph, and agreement with the single-
-matrix blocked path."""
+"""GPU parity of the batched path: every matrix against its known spectrum and the defining
+properties (and the oracle for small ones), plain and preconditioned (Algorithm 4.1 per matrix), on
+batches that mix sizes and spectra; bitwise-reproducible replays of the captured graph; results of a
+matrix that do not depend on the rest of its batch; the convergence check with its top-up; and
+agreement with the single-matrix path (which runs other kernels -- merged launches, another FP32
+stage -- so the agreement is to rounding level, not bitwise)."""
 import numpy as np
 import pytest
 import torch
@@ -16,50 +19,162 @@ def dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
 
 
-def test_batched_uneven_sizes():
+def _solve(mats, **kw):
+    b = jacobi.Batch([dev(A) for A in mats])
+    b.run(**kw)
+    torch.cuda.synchronize()
+    return b, b.results()
+
+
+def _check_pair(A, lam, w, v, label):
+    n = A.shape[0]
+    w, v = w.cpu().numpy(), v.cpu().numpy()
+    nA = np.linalg.norm(A)
+    assert np.all(np.diff(w) >= 0), label
+    assert np.abs(w - np.sort(lam)).max() <= 1e-12 * max(np.abs(lam).max(), 1e-300), label
+    assert np.linalg.norm(A @ v - v * w) <= 1e-13 * nA, label
+    assert np.linalg.norm(v.T @ v - np.eye(n)) <= 1e-13 * max(1.0, np.sqrt(n / 256)), label
+
+
+@pytest.fixture(autouse=True)
+def _fresh_table():
+    jacobi.jac_tune_clear()
+    yield
+    jacobi.jac_tune_clear()
+
+
+@pytest.mark.parametrize("precond", ["none", "fp32"])
+def test_batched_uneven_sizes(precond):
     sizes = [32, 1, 64, 96, 2, 160, 33, 256, 7, 512, 65, 128]
     mats = [tm.batched_matrix(100 + i, n) for i, n in enumerate(sizes)]
-    b = jacobi.Batch([dev(A) for A, _ in mats])
-    print("[batched] sizes", sizes, flush=True)
-    b.run(tol=1e-15)
-    torch.cuda.synchronize()
-    W, V, sw, info = b.results()
+    print(f"[batched] precond={precond} sizes {sizes}", flush=True)
+    b, (W, V, sw, info) = _solve([A for A, _ in mats], tol=1e-15, precond=precond)
     assert np.all(info == 0), info
     for (A, lam), w, v, s in zip(mats, W, V, sw):
         n = A.shape[0]
-        w, v = w.cpu().numpy(), v.cpu().numpy()
-        assert np.all(np.diff(w) >= 0)
-        assert np.abs(w - np.sort(lam)).max() <= 1e-12 * max(np.abs(lam).max(), 1e-300)
-        assert np.linalg.norm(A @ v - v * w) <= 1e-13 * np.linalg.norm(A)
-        assert np.linalg.norm(v.T @ v - np.eye(n)) <= 1e-13 * max(1.0, np.sqrt(n / 256))
-        if n <= 64 and n > 1:
+        _check_pair(A, lam, w, v, (precond, n))
+        if precond == "none" and 1 < n <= 64:
             # one 2b x 2b subproblem: an outer sweep runs up to the tuned number of inner sweeps,
             # so it needs no more sweeps than the cyclic oracle (plus one for the final check)
             assert 1 <= s <= oracle.syev(A, tol=1e-15).sweeps + 1, (n, s)
-    # replay of the cached graph gives bitwise the same results
+        if n <= 96:
+            wo = oracle.syev(A, tol=1e-15).W
+            assert np.abs(w.cpu().numpy() - wo).max() <= 1e-13 * max(np.abs(wo).max(), 1e-300), n
+    if precond == "fp32":
+        s32 = b.sweeps32.cpu().numpy()
+        assert np.all(s32 >= 0) and s32.max() >= 1
+        assert b.stats["series_failed"] == 0
+    # a replay of the cached graph gives bitwise the same W and V
     W1 = [w.clone() for w in W]
     V1 = [v.clone() for v in V]
-    b.run(tol=1e-15)
+    b.run(tol=1e-15, precond=precond)
     torch.cuda.synchronize()
+    assert b.stats["graph_built"] == 0
     W2, V2, _, _ = b.results()
     assert all(torch.equal(a, c) for a, c in zip(W1, W2))
     assert all(torch.equal(a, c) for a, c in zip(V1, V2))
 
 
-def test_batched_autotune_and_counts():
+@pytest.mark.parametrize("precond", ["none", "fp32"])
+def test_batched_mixed_spectra(precond):
+    """A batch mixing the three test spectra (uniform, eight decades geometric, ten tight clusters)
+    over several size classes; every matrix converges and meets the accuracy bars."""
+    cases = []
+    for i, n in enumerate([64, 130, 200, 256, 384, 512]):
+        for j, kind in enumerate(tm.SPECTRA):
+            cases.append((n, kind, 7000 + 10 * i + j))
+    mats = [tm.sym_matrix(n, kind, seed) for n, kind, seed in cases]
+    print(f"[batched mixed] precond={precond} {len(mats)} matrices", flush=True)
+    b, (W, V, sw, info) = _solve([A for A, _ in mats], precond=precond)
+    assert np.all(info == 0), info
+    for (n, kind, _), (A, lam), w, v in zip(cases, mats, W, V):
+        _check_pair(A, lam, w, v, (precond, n, kind))
+    print(f"[batched mixed] sweeps {sw.tolist()} sweeps32 {b.sweeps32.cpu().numpy().tolist()} {b.stats}",
+          flush=True)
+    if precond == "fp32":
+        # the preconditioned FP64 stage needs far fewer sweeps than plain Jacobi (Table 6.3: 2-6)
+        assert sw.max() <= 8, sw
+
+
+@pytest.mark.parametrize("precond", ["none", "fp32"])
+def test_batched_result_independent_of_batch(precond):
+    """A matrix stops at its own convergence, so its W and V are bitwise the same alone and inside
+    a batch with other matrices of its size class and of other classes."""
+    X, _ = tm.sym_matrix(150, "geometric", 8101)
+    Y, _ = tm.sym_matrix(100, "uniform", 8102)
+    Z, _ = tm.sym_matrix(160, "clusters", 8103)
+    E, _ = tm.sym_matrix(140, "uniform", 8104)
+    print(f"[batched invariance] precond={precond}", flush=True)
+    _, (W1, V1, s1, i1) = _solve([X], precond=precond)
+    _, (W2, V2, s2, i2) = _solve([Y, Z, X, E], precond=precond)
+    assert i1[0] == 0 and i2[2] == 0
+    assert s1[0] == s2[2]
+    assert torch.equal(W1[0], W2[2])
+    assert torch.equal(V1[0].contiguous(), V2[2].contiguous())
+
+
+def test_batched_topup_and_cap():
+    """Tuned on easy samples (matrices that are nearly diagonal), the graph runs too few sweeps for
+    dense random matrices of the same class: the convergence check adds sweeps until every matrix
+    has converged.  With max_sweeps below what they need, info = 1 and sweeps = max_sweeps."""
+    n = 128
+    easy = []
+    for k in range(4):
+        A, _ = tm.sym_matrix(n, "uniform", 8200 + k)
+        D = np.diag(np.diag(A)) + 1e-9 * (A - np.diag(np.diag(A)))
+        easy.append(np.asfortranarray(D))
+    jacobi.Batch([dev(A) for A in easy]).autotune()
+    inner, tuned, _ = jacobi.jac_tune_entry(n)
+    print(f"[batched topup] tuned inner={inner} sweeps={tuned}", flush=True)
+    hard = [tm.sym_matrix(n, "uniform", 8300 + k) for k in range(6)]
+    b, (W, V, sw, info) = _solve([A for A, _ in hard])
+    print(f"[batched topup] sweeps {sw.tolist()} stats {b.stats}", flush=True)
+    assert tuned < sw.max()
+    assert b.stats["topup_sweeps"] >= sw.max() - tuned
+    assert np.all(info == 0)
+    for (A, lam), w, v in zip(hard, W, V):
+        _check_pair(A, lam, w, v, "topup")
+    b.run(max_sweeps=2)
+    torch.cuda.synchronize()
+    _, _, sw2, info2 = b.results()
+    assert np.all(info2 == 1) and np.all(sw2 == 2), (sw2, info2)
+
+
+@pytest.mark.parametrize("precond", ["none", "fp32"])
+def test_batched_autotune_and_counts(precond):
     sizes = [64] * 6 + [192] * 6
     mats = [tm.batched_matrix(200 + i, n) for i, n in enumerate(sizes)]
     b = jacobi.Batch([dev(A) for A, _ in mats])
-    b.autotune(tol=1e-15)
-    inner, sweeps = jacobi.jac_tune_entry(192)
-    print(f"[batched tune] n=192 inner={inner} sweeps={sweeps}", flush=True)
-    assert 1 <= inner <= 4 and 1 <= sweeps <= 41
-    b.run(tol=1e-15)
+    b.autotune(tol=1e-15, precond=precond)
+    inner, sweeps, sweeps32 = jacobi.jac_tune_entry(192, precond)
+    print(f"[batched tune] precond={precond} n=192 inner={inner} sweeps={sweeps} sweeps32={sweeps32}", flush=True)
+    assert 1 <= inner <= 4 and 1 <= sweeps <= 40
+    assert (sweeps32 >= 1) if precond == "fp32" else (sweeps32 == 0)
+    b.run(tol=1e-15, precond=precond)
     torch.cuda.synchronize()
     W, V, sw, info = b.results()
     assert np.all(info == 0)
+    assert b.stats["topup_sweeps"] == 0   # the tuned counts cover the samples themselves
     for (A, lam), w in zip(mats, W):
         assert np.abs(w.cpu().numpy() - np.sort(lam)).max() <= 1e-12
+
+
+@pytest.mark.parametrize("precond", ["none", "fp32"])
+def test_batched_matches_single_matrix_path(precond):
+    cases = [(96, "uniform", 8401), (200, "geometric", 8402), (320, "clusters", 8403)]
+    mats = [tm.sym_matrix(n, kind, seed)[0] for n, kind, seed in cases]
+    _, (W, V, sw, info) = _solve(mats, precond=precond)
+    for A, w, v in zip(mats, W, V):
+        ws, vs, _, _ = jacobi.syev_jacobi_ex(dev(A), precond=precond)
+        ws = ws.cpu().numpy()
+        nrm = np.abs(ws).max()
+        assert np.abs(w.cpu().numpy() - ws).max() <= 1e-13 * nrm
+        # eigenvectors of well-separated eigenvalues agree up to sign
+        vb, vs = v.cpu().numpy(), vs.cpu().numpy()
+        gap = np.min(np.diff(ws))
+        if gap > 1e-6 * nrm:
+            sgn = np.sign(np.sum(vb * vs, axis=0))
+            assert np.abs(vb - vs * sgn).max() <= 1e-12 * nrm / gap
 
 
 def test_batched_bad_args():
@@ -68,3 +183,14 @@ def test_batched_bad_args():
     assert L.syev_jacobi_batched(1, n, None, None, None, None, None, 0.0, None, None, None) < 0
     assert L.syev_jacobi_batched(-1, n, None, None, None, None, None, 0.0, None, None, None) == -1
     assert L.syev_jacobi_batched(0, None, None, None, None, None, None, 0.0, None, None, None) == 0
+    # an option out of range is rejected before any work
+    A, _ = tm.sym_matrix(8, "uniform", 1)
+    b = jacobi.Batch([dev(A)])
+    bad = jacobi.JacBatchedOpts(2, 0.0, 0, 0)
+    code = L.syev_jacobi_batched_ex(1, b.c_n, b.c_A, b.c_ld, b.c_W, b.c_V, b.c_ld, 0.0, None, None, None,
+                                    bad, None, None)
+    assert code == -12
+    bad = jacobi.JacBatchedOpts(0, 0.0, 0, 1)
+    code = L.syev_jacobi_batched_ex(1, b.c_n, b.c_A, b.c_ld, b.c_W, b.c_V, b.c_ld, 0.0, None, None, None,
+                                    bad, None, None)
+    assert code == -12
