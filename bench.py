@@ -148,7 +148,13 @@ def main():
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-start row at n=256")
     ap.add_argument("--no-elem", action="store_true", help="skip the element-wise variant's step rooflines")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-path row (4096 matrices)")
-    ap.add_argument("--mlp-train", type=int, default=8192, help="training solves for the learned-start row")
+    ap.add_argument("--no-ex62", action="store_true", help="skip the multiple-eigenvalue study rows")
+    ap.add_argument("--no-prec", action="store_true", help="skip the FP16 / BF16 step-1 study")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched-path row and print it (for profiling that path)")
+    ap.add_argument("--batched-noloop", action="store_true",
+                    help="batched row without its per-matrix comparison loop")
+    ap.add_argument("--mlp-train", type=int, default=4096, help="training solves for the learned-start row")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -173,6 +179,9 @@ def main():
     from paper_2211_03339_amd import testmats as tm
 
     jacobi.load()
+    if args.batched_only:
+        print(json.dumps({"batched_4096": batched_row(loop_sample=0 if args.batched_noloop else 128)}), flush=True)
+        return
     n = args.n
     spectra = list(tm.SPECTRA)
     log(f"[bench] generating {len(spectra)} matrices of order {n}")
@@ -271,6 +280,35 @@ def main():
                                     "best_step": round(max(pstep_s) / min(step_s), 4)}}
         log(f"[bench] plain: {plain}")
 
+    # Step 1 at lower precision (FP16, BF16: A and the step-1 eigenvectors rounded to it), the
+    # paper's precision study: start quality, FP64 sweeps and solve time per spectrum (one warm
+    # and one measured solve each, outside the timed region).
+    prec_study = None
+    if not args.no_prec:
+        prec_study = {}
+        for prec in ("fp16", "bf16"):
+            row = {}
+            for i in range(len(mats)):
+                o = jacobi._opts("fp32", args.variant, stage1_prec=prec)
+                pstat = jacobi.JacStats()
+                for _ in range(2):
+                    code = jacobi.syev_jacobi_raw(dev[i].data_ptr(), n, n, Ws[i].data_ptr(), Vs[i].data_ptr(), n,
+                                                  args.tol, o, pstat, sp)
+                    if code != 0:
+                        raise RuntimeError(f"syev_jacobi_ex ({prec} step 1) returned {code}: {jacobi.last_error()}")
+                torch.cuda.synchronize()
+                d = pstat.as_dict()
+                A, lam = mats[i]
+                W = Ws[i].cpu().numpy()
+                row[spectra[i]] = {"off0_rel": d["off0"] / d["nrmA"], "sweeps": d["sweeps"],
+                                   "ms_total": round(d["stage_ms"]["total"], 3),
+                                   "lam_err_rel": float(np.abs(W - np.sort(lam)).max() / np.abs(lam).max())}
+            prec_study[prec] = row
+        prec_study["fp32"] = {spectra[i]: {"off0_rel": stats[i].off0 / stats[i].nrmA, "sweeps": stats[i].sweeps,
+                                           "ms_total": round(float(stats[i].stage_ms[5]), 3)}
+                              for i in range(len(mats))}
+        log(f"[bench] precision study: {json.dumps(prec_study)}")
+
     # Roofline of the dominant kernel (by measured launch time inside the timed region).
     dom = max(kern, key=lambda c: kern[c]["ms"])
     roofline = roofline_for(dom, kern[dom], n, rot.get(dom[-2:], 0))
@@ -294,6 +332,11 @@ def main():
                 "rooflines": {c: roofline_for(c, v, n, ed["rotations"] if c == "elem64" else ed["fp32_rotations"])
                               for c, v in ed["kernels"].items() if c.startswith("elem")}}
         log(f"[bench] element variant: {json.dumps(elem)}")
+
+    ex62 = None
+    if not args.no_ex62:
+        ex62 = example62_rows(n)
+        log(f"[bench] multiple eigenvalues (Example 6.2 recipe): {json.dumps(ex62)}")
 
     bat_row = None
     if not args.no_batched:
@@ -332,6 +375,7 @@ def main():
                       "n": n, "solves_per_step": len(mats), "variant": args.variant,
                       "tol": args.tol if args.tol > 0 else 20 * 2.0 ** -53},
            "per_spectrum": per_spec, "plain": plain, "learned_n256": mlp_row, "batched_4096": bat_row, "element_variant": elem,
+           "example62_study": ex62, "precision_study": prec_study,
            "roofline": roofline,
            "cpu_baseline": cpu,
            "kernels": kernels, "other_rooflines": others}
@@ -340,33 +384,103 @@ def main():
 
 def learned_row(n_train: int, n_eval: int = 32, epochs: int = 8):
     """Learned start on the n = 256 family (the network row of the metric at the size where it is
-    feasible): train on n_train method-generated solves, then time solves of held-out matrices
-    with the learned start (FP32 fallback), the FP32 start and plain Jacobi."""
+    feasible), as the trainer runs it: the network starts as the constant start Z0 (eigenvectors of
+    A0), its targets are n_train method-generated solves matched to Z0's columns, and the
+    parameters with the best start residual on 16 validation matrices are kept; then solves of
+    held-out matrices with the learned start (FP32 fallback), the constant start, the FP32 start and
+    plain Jacobi are timed."""
     from paper_2211_03339_amd import learned
     from paper_2211_03339_amd import testmats as tm
     n = 256
     A0, B = learned.family(n)
-    theta, T, data = learned.make_dataset(A0, B, tm.param_thetas(n_train, learned.THETA_TRAIN_SEED))
+    Z0 = learned.constant_start(A0)
+    theta, T, data = learned.make_dataset(A0, B, tm.param_thetas(n_train, learned.THETA_TRAIN_SEED), Z0=Z0)
     net = learned.jacobi.Mlp(8, 1024, n, 256, seed=0)
-    tr = learned.train(net, theta, T, epochs=epochs, batch=256, lr=1e-3, weight_decay=1e-4)
+    learned.init_as_correction(net, Z0)
+    val = learned.validation_set(A0, B, tm.param_thetas(16, learned.THETA_VAL_SEED))
+    tr = learned.train(net, theta, T, epochs=epochs, batch=256, lr=3e-4, weight_decay=0.0, val=val)
     del T
-    ev = learned.evaluate(net, A0, B, tm.param_thetas(n_eval, learned.THETA_EVAL_SEED), check=True)
+    ev = learned.evaluate(net, A0, B, tm.param_thetas(n_eval, learned.THETA_EVAL_SEED), check=True, Z0=Z0)
     net.close()
+    modes = ("mlp", "const", "fp32", "plain", "mlp_forced")
     return {"n": n, "train_solves": n_train, "epochs": epochs, "data_s": round(data["seconds"], 3),
             "train_s": round(tr["seconds"], 3), "final_loss": tr["loss_per_epoch"][-1],
+            "val_start_resid": [round(x, 4) for x in tr["val_start_resid"]], "kept_epoch": tr["kept_epoch"],
             "eval_matrices": n_eval,
-            "solves_per_s": {m: round(1e3 / ev[m]["mean_ms"], 2) for m in ("mlp", "fp32", "plain", "mlp_forced")},
-            "mean_sweeps": {m: ev[m]["mean_sweeps"] for m in ("mlp", "fp32", "plain", "mlp_forced")},
-            "max_res": max(ev[m]["max_res"] for m in ("mlp", "fp32", "plain", "mlp_forced")),
-            "learned_start": ev["learned_start"]}
+            "solves_per_s": {m: round(1e3 / ev[m]["mean_ms"], 2) for m in modes},
+            "mean_sweeps": {m: ev[m]["mean_sweeps"] for m in modes},
+            "max_res": max(ev[m]["max_res"] for m in modes),
+            "learned_start": ev["learned_start"], "const_start": ev["const_start"]}
 
 
-def batched_row(count: int = 4096, loop_sample: int = 256, reps: int = 3):
+def example62_rows(n: int, kappas=(1e3, 1e6), r: int = 4):
+    """Multiple eigenvalues (Example 6.2, the shapes of its result tables): A = P diag(lam kron 1_r)
+    P^T with r = 4, P Haar (the library's MGS of a seeded Gaussian on the device) and lam by mode 1-5 and kappa,
+    solved preconditioned and plain.  Per case: ||off(Q^T A Q)||_F of the start, d(A)/4 (a quarter
+    of the smallest gap between distinct eigenvalues), the residual ||A V - V W||_F / ||A||_F,
+    ||V^T V - I||_F (raw and / sqrt(n)), the start and sweep times and the FP64 sweeps."""
+    import torch
+    from paper_2211_03339_amd import jacobi
+    from paper_2211_03339_amd import testmats as tm
+    s = n // r
+    rows = []
+    gen = torch.Generator(device="cuda")
+    for kappa in kappas:
+        for mode in range(1, 6):
+            g = tm.rng(6200 + mode)
+            if mode == 1:
+                lam = np.full(s, 1.0 / kappa); lam[0] = 1.0
+            elif mode == 2:
+                lam = np.ones(s); lam[-1] = 1.0 / kappa
+            elif mode == 3:
+                lam = kappa ** np.linspace(-1.0, 0.0, s)
+            elif mode == 4:
+                lam = 1.0 - (1.0 - 1.0 / kappa) * np.linspace(0.0, 1.0, s)
+            else:
+                lam = kappa ** (-g.uniform(size=s))
+            full = torch.from_numpy(np.kron(lam, np.ones(r))).cuda()
+            gen.manual_seed(620_000 + mode)
+            Q = jacobi.jac_mgs(torch.randn((n, n), dtype=torch.float64, device="cuda", generator=gen)).contiguous()
+            A = (Q * full.unsqueeze(0)) @ Q.t().contiguous()
+            A = (0.5 * (A + A.t())).contiguous()
+            u = np.unique(lam)
+            dA = float(np.min(np.diff(u))) / 4 if u.size > 1 else float("inf")
+            row = {"mode": mode, "kappa": kappa, "d_over_4": dA}
+            nA = float(torch.linalg.norm(A))
+            eye = torch.eye(n, dtype=torch.float64, device="cuda")
+            for pre in ("fp32", "none"):
+                jacobi.syev_jacobi_ex(A, precond=pre)   # warm
+                torch.cuda.synchronize()
+                W, V, st, _ = jacobi.syev_jacobi_ex(A, precond=pre)
+                torch.cuda.synchronize()
+                Vc = V.contiguous()
+                res = float(torch.linalg.norm(A @ Vc - Vc * W.unsqueeze(0))) / nA
+                orth = float(torch.linalg.norm(Vc.t().contiguous() @ Vc - eye))
+                lam_err = float((W - torch.sort(full).values).abs().max())
+                ms = st["stage_ms"]
+                row[pre] = {"sweeps": st["sweeps"], "res": res, "orth": orth, "orth_over_sqrt_n": orth / n ** 0.5,
+                            "lam_err": lam_err, "ms_total": round(ms["total"], 2),
+                            "ms_start": round(ms["start"] + ms["mgs"] + ms["similarity"], 2),
+                            "ms_sweeps": round(ms["sweeps"], 2)}
+                if pre == "fp32":
+                    row["off_QtAQ"] = st["off0"]
+            rows.append(row)
+            del A, Q
+    return {"n": n, "r": r, "cases": rows,
+            "total_ms_precond": round(sum(c["fp32"]["ms_total"] for c in rows), 1),
+            "total_ms_plain": round(sum(c["none"]["ms_total"] for c in rows), 1)}
+
+
+def batched_row(count: int = 4096, loop_sample: int = 128, reps: int = 3):
     """The batched path on its own workload: `count` matrices A = Q diag(lambda) Q^T with sizes
-    32 * U{1..16} (seed 3), Haar Q, lambda ~ U[-1,1], solved by one replayed graph launch (after
-    the autotuner and a capturing first run), next to a per-matrix loop through the single-matrix
-    call on the first `loop_sample` matrices.  The inputs are built on the device (batched QR of
-    each size class, seeded) so that the bench does not spend minutes in host QRs."""
+    32 * U{1..16} (seed 3), Haar Q, lambda ~ U[-1,1], plain and preconditioned (Algorithm 4.1 per
+    matrix).  Each form: the autotuner, a capturing first call, then `reps` timed calls (graph
+    replay plus the convergence check); next to it a per-matrix loop through the single-matrix
+    call on the first `loop_sample` matrices.  The inputs are built on the device (seeded Gaussian
+    matrices orthonormalised by the library's MGS) so that the bench does not spend minutes in host
+    QRs.
+    Roofline: FP64 matrix-core work of the blocked sweeps, 12 n^3 flop per FP64 sweep of an order-n
+    matrix (T updated as 8 n^3, V as 4 n^3), over the wall time of a call, against the FP64 peak."""
     import torch
     from paper_2211_03339_amd import jacobi
     from paper_2211_03339_amd import testmats as tm
@@ -378,61 +492,80 @@ def batched_row(count: int = 4096, loop_sample: int = 256, reps: int = 3):
     for nval in sorted(set(sizes)):
         idx = [i for i, x in enumerate(sizes) if x == nval]
         G = torch.randn((len(idx), nval, nval), dtype=torch.float64, device="cuda", generator=gen)
-        Q, R = torch.linalg.qr(G)
-        Q = Q * torch.sign(torch.diagonal(R, dim1=-2, dim2=-1)).unsqueeze(-2)
+        # Haar factors: the orthonormal QR factor (positive R diagonal) of each Gaussian matrix,
+        # by the library's MGS
+        Q = torch.stack([jacobi.jac_mgs(G[j]).contiguous() for j in range(len(idx))])
         lam = torch.rand((len(idx), nval), dtype=torch.float64, device="cuda", generator=gen) * 2 - 1
         A = torch.matmul(Q * lam.unsqueeze(-2), Q.transpose(-2, -1).contiguous())
         A = 0.5 * (A + A.transpose(-2, -1).contiguous())
         for j, i in enumerate(idx):
             mats[i] = A[j].contiguous()
             lams[i] = lam[j]
-        del G, Q, R, A
+        del G, Q, A
     torch.cuda.synchronize()
     b = jacobi.Batch(mats)
-    t0 = time.perf_counter()
-    b.autotune()
-    torch.cuda.synchronize()
-    tune_s = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    b.run()
-    torch.cuda.synchronize()
-    first_s = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        b.run()
-    torch.cuda.synchronize()
-    run_s = (time.perf_counter() - t0) / reps
-    W, V, sw, info = b.results()
-    # accuracy on every 16th matrix, against its known spectrum and by the defining properties
-    worst = {"res": 0.0, "orth": 0.0, "lam_err": 0.0}
-    for i in range(0, count, 16):
-        A, w, v = mats[i], W[i], V[i].contiguous()
-        nA = float(torch.linalg.norm(A))
-        worst["res"] = max(worst["res"], float(torch.linalg.norm(A @ v - v * w[None, :])) / nA)
-        eye = torch.eye(A.shape[0], dtype=torch.float64, device="cuda")
-        worst["orth"] = max(worst["orth"], float(torch.linalg.norm(v.t().contiguous() @ v - eye)))
-        lam_sorted = torch.sort(lams[i]).values
-        worst["lam_err"] = max(worst["lam_err"], float((w - lam_sorted).abs().max() / lam_sorted.abs().max()))
-    # the per-matrix loop on a sample
     ns = min(loop_sample, count)
-    for i in range(2):   # warm the single-matrix path
-        jacobi.syev_jacobi_ex(mats[i], precond="none")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(ns):
-        jacobi.syev_jacobi_ex(mats[i], precond="none")
-    torch.cuda.synchronize()
-    loop_s = time.perf_counter() - t0
     cube = sum(x ** 3 for x in sizes)
-    cube_s = sum(x ** 3 for x in sizes[:ns])
-    loop_proj = loop_s * cube / cube_s
-    return {"matrices": count, "sizes": "32*U{1..16}, seed 3", "mean_n": round(sum(sizes) / count, 1),
-            "autotune_s": round(tune_s, 3), "first_run_s": round(first_s, 3), "run_s": round(run_s, 4),
-            "matrices_per_s": round(count / run_s, 1), "unconverged": int((info != 0).sum()),
-            "mean_sweeps": round(float(sw.mean()), 2),
-            "loop_sample": ns, "loop_sample_s": round(loop_s, 4),
-            "loop_projected_s": round(loop_proj, 3), "speedup_vs_loop": round(loop_proj / run_s, 2),
-            "checked_every_16th": {k: float("%.3g" % v) for k, v in worst.items()}}
+    cube_s = max(sum(x ** 3 for x in sizes[:ns]), 1)
+    row = {"matrices": count, "sizes": "32*U{1..16}, seed 3", "mean_n": round(sum(sizes) / count, 1)}
+    for pre in ("none", "fp32"):
+        t0 = time.perf_counter()
+        b.autotune(precond=pre)
+        torch.cuda.synchronize()
+        tune_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        b.run(precond=pre)
+        torch.cuda.synchronize()
+        first_s = time.perf_counter() - t0
+        per = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            b.run(precond=pre)
+            torch.cuda.synchronize()
+            per.append(time.perf_counter() - t0)
+        run_s = float(np.median(per))
+        W, V, sw, info = b.results()
+        s32 = b.sweeps32.cpu().numpy()
+        # accuracy on every 16th matrix, against its known spectrum and by the defining properties
+        worst = {"res": 0.0, "orth": 0.0, "lam_err": 0.0}
+        for i in range(0, count, 16):
+            A, w, v = mats[i], W[i], V[i].contiguous()
+            nA = float(torch.linalg.norm(A))
+            worst["res"] = max(worst["res"], float(torch.linalg.norm(A @ v - v * w[None, :])) / nA)
+            eye = torch.eye(A.shape[0], dtype=torch.float64, device="cuda")
+            worst["orth"] = max(worst["orth"], float(torch.linalg.norm(v.t().contiguous() @ v - eye)))
+            lam_sorted = torch.sort(lams[i]).values
+            worst["lam_err"] = max(worst["lam_err"], float((w - lam_sorted).abs().max() / lam_sorted.abs().max()))
+        # the per-matrix loop through the single-matrix call on a sample
+        loop_s = loop_proj = float("nan")
+        if ns:
+            for i in range(2):
+                jacobi.syev_jacobi_ex(mats[i], precond=pre)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(ns):
+                jacobi.syev_jacobi_ex(mats[i], precond=pre)
+            torch.cuda.synchronize()
+            loop_s = time.perf_counter() - t0
+            loop_proj = loop_s * cube / cube_s
+        flops64 = float(sum(12.0 * n ** 3 * int(k) for n, k in zip(sizes, sw)))
+        achieved = flops64 / run_s / 1e12
+        row[pre] = {"autotune_s": round(tune_s, 3), "first_call_s": round(first_s, 3), "call_s": round(run_s, 4),
+                    "call_s_spread": [round(x, 4) for x in per],
+                    "matrices_per_s": round(count / run_s, 1), "unconverged": int((info != 0).sum()),
+                    "mean_sweeps": round(float(sw.mean()), 2), "max_sweeps": int(sw.max()),
+                    "mean_fp32_sweeps": round(float(s32.mean()), 2), "stats": b.stats,
+                    "tuned_n512": jacobi.jac_tune_entry(512, pre),
+                    "loop_sample": ns, "loop_sample_s": round(loop_s, 4) if ns else None,
+                    "loop_projected_s": round(loop_proj, 3) if ns else None,
+                    "speedup_vs_loop": round(loop_proj / run_s, 2) if ns else None,
+                    "roofline_fp64_sweeps": {"bound": "mfma", "achieved": round(achieved, 3), "peak": 78.6,
+                                             "unit": "TFLOP/s", "frac": round(achieved / 78.6, 4),
+                                             "work": "12 n^3 per FP64 sweep, summed over the batch"},
+                    "checked_every_16th": {k: float("%.3g" % v) for k, v in worst.items()}}
+        log(f"[bench] batched {pre}: {json.dumps(row[pre])}")
+    row["speedup_precond_vs_plain"] = round(row["none"]["call_s"] / row["fp32"]["call_s"], 3)
+    return row
 
 
 def _cpu_model():

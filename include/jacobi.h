@@ -58,6 +58,28 @@ typedef enum {
                               n <= 8192 (larger orders use Jacobi) */
 } jac_stage1_t;
 
+/* QR preconditioning of the one-sided SVD for m >> n (the remark after
+ * Algorithm 5.2): A = Q_A B with Q_A (m x n) orthonormal -- two passes of block
+ * MGS, so that Q_A is orthonormal to working precision -- and B = Q_A^T A
+ * (n x n); the SVD B = U_B S V^T by the same method; U = Q_A U_B.  The sweeps
+ * then work on n x n columns instead of m x n.  Needs m <= 8192 (block MGS). */
+typedef enum {
+  JAC_SVD_QR_AUTO = 0,  /* QR first when m >= 8 n and m <= 8192 */
+  JAC_SVD_QR_OFF = 1,
+  JAC_SVD_QR_ON = 2
+} jac_svd_qr_t;
+
+/* Precision upsilon of step 1 (Algorithm 4.1; the paper's precision study,
+ * Section 6.1).  FP16 and BF16: A is rounded to upsilon (FP16 after scaling by
+ * a power of two near 1/||A||_F) before the step-1 eigensolver, and the
+ * eigenvectors it returns are rounded to upsilon before step 2, so that the
+ * start carries upsilon's accuracy; the eigensolver itself computes in FP32. */
+typedef enum {
+  JAC_PREC_FP32 = 0,
+  JAC_PREC_FP16 = 1,
+  JAC_PREC_BF16 = 2
+} jac_prec_t;
+
 struct jac_mlp;
 
 typedef struct jac_opts {
@@ -74,6 +96,8 @@ typedef struct jac_opts {
   int inner_sweeps;    /* blocked variant: cap on the sweeps of each 2b x 2b subproblem; <= 0: default */
   int profile;         /* nonzero: time every sweep launch with HIP events into jac_stats.kern_* */
   int stage1;          /* jac_stage1_t: solver of the FP32 step 1 (FP32 start and fallback) */
+  int svd_qr;          /* jac_svd_qr_t: gesvd_jacobi_ex only */
+  int stage1_prec;     /* jac_prec_t: precision of step 1 (syev with the FP32 start only) */
 } jac_opts;
 
 #define JAC_HIST 65
@@ -111,6 +135,8 @@ typedef struct jac_stats {
   long long kern_work[8];
   double start_resid;      /* precond MLP: ||off(Q^T A Q)||_F / ||A||_F of the predicted start */
   int fp32_method;         /* step 1 that ran: 0 none, 1 FP32 Jacobi, 2 tridiagonal */
+  int svd_qr_used;         /* gesvd: 1 when the QR-first form ran */
+  float qr_ms;             /* gesvd QR first: time of A = Q_A B and U = Q_A U_B */
 } jac_stats;
 
 /* Symmetric eigendecomposition A = V diag(W) V^T by Algorithm 4.1
@@ -119,7 +145,9 @@ typedef struct jac_stats {
  * V: n x n (leading dimension n), column i pairs with W[i].
  * tol: stop when ||off(T)||_F <= tol ||A||_F (tested before each sweep);
  * tol <= 0 selects the paper's 20 * 2^-53.  sweeps_out (host, may be NULL):
- * FP64 sweeps executed. */
+ * FP64 sweeps executed.  Preconditioned solves (and custom starts) need
+ * n <= 8192, the row limit of step 2's block MGS (-2 otherwise); plain Jacobi
+ * has no such limit. */
 int syev_jacobi(const double* A, int n, int lda, double* W, double* V, double tol, int* sweeps_out);
 
 /* As syev_jacobi with explicit options, leading dimension of V, statistics
@@ -160,7 +188,8 @@ int syev_jacobi_warm(const double* A, int n, int lda, const double* Q0, int ldq,
  * only when |c_i.c_j| > m tol ||c_i|| ||c_j||; tol <= 0 selects 2^-53.
  * A: m x n (lda >= m), read only.  S: n singular values, descending.
  * U: m x n (ldu >= m), u_j = c_j / s_j.  V: n x n (ldv >= n).
- * sweeps_out (host, may be NULL). */
+ * sweeps_out (host, may be NULL).  Takes the QR-first form (jac_svd_qr_t) when
+ * m >= 8 n and m <= 8192.  The preconditioned SVD needs n <= 8192 (-3). */
 int gesvd_jacobi(const double* A, int m, int n, int lda, double* S, double* U, int ldu, double* V, int ldv,
                  double tol, int* sweeps_out);
 

@@ -502,7 +502,15 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
     set_error("syev_jacobi_ex: opts.stage1 must be a jac_stage1_t");
     return -8;
   }
+  if (o.stage1_prec < JAC_PREC_FP32 || o.stage1_prec > JAC_PREC_BF16) {
+    set_error("syev_jacobi_ex: opts.stage1_prec must be a jac_prec_t");
+    return -8;
+  }
   if (n == 0) return 0;
+  if (o.precond != JAC_PRECOND_NONE && n > kMgsMaxRows) {
+    set_error("syev_jacobi: preconditioned solves (and custom starts) need n <= 8192 (block MGS of step 2)");
+    return -2;
+  }
   if (o.precond == JAC_PRECOND_MLP) {
     if (!o.mlp || !o.theta) {
       set_error("syev_jacobi_ex: the learned start needs opts.mlp and opts.theta");
@@ -640,10 +648,27 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
       double ms32 = 0;
       long long l32 = 0;
       Carve c1 = c;   // the FP32 stage's carve, reused if it has to run again
-      e = fp32_stage(A, true, n, lda, nrm, tol32, max32, Vw, n, nullptr, c, hd, s, &sw32, &r32,
+      // Step 1 at precision upsilon below FP32: the eigensolver sees fl_upsilon(A) (held in T0
+      // until step 3 overwrites it) and its eigenvectors are rounded to upsilon as well.
+      const double* As = A;
+      int las = lda;
+      const double lp_scale = std::ldexp(1.0, -std::ilogb(nrm) - 1);   // ||A||_F scale < 1
+      if (o.stage1_prec != JAC_PREC_FP32) {
+        e = copy_convert<double, double>(A, n, n, lda, T0, n, s);
+        if (e) return e;
+        e = round_lowp(T0, n, n, n, o.stage1_prec, o.stage1_prec == JAC_PREC_FP16 ? lp_scale : 1.0, s);
+        if (e) return e;
+        As = T0;
+        las = n;
+      }
+      e = fp32_stage(As, true, n, las, nrm, tol32, max32, Vw, n, nullptr, c, hd, s, &sw32, &r32,
                      stats && !fixed ? &ms32 : nullptr, &l32, o.variant, o.inner_sweeps, pf, o.stage1, &method1,
                      fixed);
       if (e) return e;
+      if (o.stage1_prec != JAC_PREC_FP32) {
+        e = round_lowp(Vw, n, n, n, o.stage1_prec, 1.0, s);
+        if (e) return e;
+      }
       if (method1 == 2) {
         // A tridiagonal start whose columns MGS cannot orthogonalise (a zero column: eigenvectors of
         // T computed for numerically equal eigenvalues) is replaced by the FP32 Jacobi start.
@@ -656,10 +681,14 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
         if (hflag) {
           JAC_HIP(hipMemsetAsync(hd.flag, 0, 16 * sizeof(int), s));
           c = c1;
-          e = fp32_stage(A, true, n, lda, nrm, tol32, max32, Vw, n, nullptr, c, hd, s, &sw32, &r32,
+          e = fp32_stage(As, true, n, las, nrm, tol32, max32, Vw, n, nullptr, c, hd, s, &sw32, &r32,
                          stats && !fixed ? &ms32 : nullptr, &l32, o.variant, o.inner_sweeps, pf,
                          JAC_STAGE1_JACOBI, &method1, fixed);
           if (e) return e;
+          if (o.stage1_prec != JAC_PREC_FP32) {
+            e = round_lowp(Vw, n, n, n, o.stage1_prec, 1.0, s);
+            if (e) return e;
+          }
         }
       }
       if (stats) {
@@ -813,6 +842,14 @@ static int gesvd_impl(const double* A, int m, int n, int lda, double* S, double*
   tm.mark(0);
   const int pre = o.precond;
   if (pre == JAC_PRECOND_MLP) { set_error("gesvd_jacobi: no learned start for the SVD"); return -10; }
+  if (o.stage1_prec != JAC_PREC_FP32) {
+    set_error("gesvd_jacobi_ex: opts.stage1_prec applies to the symmetric eigensolver only");
+    return -11;
+  }
+  if (pre != JAC_PRECOND_NONE && n > kMgsMaxRows) {
+    set_error("gesvd_jacobi: the preconditioned SVD needs n <= 8192 (block MGS of step 2)");
+    return -3;
+  }
   if (o.block_b != 0) { set_error("gesvd_jacobi_ex: opts.block_b is reserved and must be 0"); return -11; }
   if (o.stage1 < JAC_STAGE1_AUTO || o.stage1 > JAC_STAGE1_TRIDIAG) {
     set_error("gesvd_jacobi_ex: opts.stage1 must be a jac_stage1_t");
@@ -939,6 +976,96 @@ static int gesvd_impl(const double* A, int m, int n, int lda, double* S, double*
   return info;
 }
 
+
+// B (n x m) = A^T for an m x n block (32 x 32 tiles through LDS).
+__global__ void transpose_rect_kernel(const double* __restrict__ A, int m, int n, int lda, double* __restrict__ B,
+                                      int ldb) {
+  __shared__ double t[32][33];
+  const int bi = blockIdx.x * 32, bj = blockIdx.y * 32;   // rows / columns of A
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bi + tx, j = bj + r;
+    if (i < m && j < n) t[r][tx] = A[i + (size_t)j * lda];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int j = bj + tx, i = bi + r;
+    if (i < m && j < n) B[j + (size_t)i * ldb] = t[tx][r];
+  }
+}
+
+static bool svd_qr_first(const jac_opts& o, int m, int n) {
+  if (o.svd_qr == JAC_SVD_QR_ON) return true;
+  if (o.svd_qr == JAC_SVD_QR_OFF) return false;
+  return n > 0 && m >= 8 * n && m <= kMgsMaxRows;
+}
+
+// QR-first SVD (m >> n; the remark after Algorithm 5.2): A = Q_A B with Q_A from two passes of
+// block MGS (orthonormal to working precision for any full-rank A with cond(A) < 1/u) and
+// B = Q_A^T A; the SVD of the n x n B by gesvd_impl; U = Q_A U_B.  The outer buffers lie behind
+// the inner call's part of the same grow-only workspace: the inner call asks for less than this
+// call did, so it gets the same block back and carves only its own front part.
+static int gesvd_qr_first(const double* A, int m, int n, int lda, double* S, double* U, int ldu, double* V, int ldv,
+                          double tol, const jac_opts& o, jac_stats* stats, hipStream_t s) {
+  if (m > kMgsMaxRows) { set_error("gesvd_jacobi_ex: the QR-first form needs m <= 8192"); return -2; }
+  const size_t inner = align_up(gesvd_bytes(n, n, o.precond), 256);
+  const size_t outer = 8192 + 2 * align_up((size_t)m * n * 8, 256) + 2 * align_up((size_t)n * n * 8, 256) +
+                       align_up(mgs_scratch_elems(m, n) * 8, 256) + align_up((size_t)(n + 64) * 8, 256) +
+                       align_up(1024 * 8, 256);
+  void* ws = workspace(inner + outer);
+  if (!ws) { set_error("gesvd_jacobi: workspace allocation failed"); return 4; }
+  Carve c(static_cast<char*>(ws) + inner);
+  int* flag = c.take<int>(16);
+  double* Qa = c.take<double>((size_t)m * n);
+  double* Qt = c.take<double>((size_t)m * n);
+  double* B = c.take<double>((size_t)n * n);
+  double* Ub = c.take<double>((size_t)n * n);
+  double* mscr = c.take<double>(mgs_scratch_elems(m, n));
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+  if (stats) {
+    JAC_HIP(hipEventCreate(&e0)); JAC_HIP(hipEventCreate(&e1)); JAC_HIP(hipEventCreate(&e2)); JAC_HIP(hipEventCreate(&e3));
+    JAC_HIP(hipEventRecord(e0, s));
+  }
+  JAC_HIP(hipMemsetAsync(flag, 0, 16 * sizeof(int), s));
+  int e = check_finite(A, m, n, lda, flag, s);
+  if (e) return e;
+  int hflag = 0;
+  JAC_HIP(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s));
+  JAC_HIP(hipStreamSynchronize(s));
+  if (hflag) { set_error("gesvd_jacobi: A contains NaN or Inf"); return 2; }
+  e = copy_convert<double, double>(A, m, n, lda, Qa, m, s);
+  if (e) return e;
+  for (int pass = 0; pass < 2 && !e; ++pass) e = mgs_f64(Qa, m, n, m, mscr, flag, s);
+  if (e) return e;
+  hipLaunchKernelGGL(transpose_rect_kernel, dim3(cdiv(m, 32), cdiv(n, 32)), dim3(256), 0, s, (const double*)Qa, m, n,
+                     m, Qt, n);
+  JAC_CHECK_LAUNCH();
+  e = gemm<double>(false, false, n, n, m, 1.0, Qt, n, A, lda, 0.0, B, n, s);   // B = Q_A^T A
+  if (e) return e;
+  JAC_HIP(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s));
+  JAC_HIP(hipStreamSynchronize(s));
+  if (hflag) { set_error("gesvd_jacobi: modified Gram-Schmidt met a zero column (rank-deficient A)"); return 3; }
+  if (e1) JAC_HIP(hipEventRecord(e1, s));
+  jac_opts oi = o;
+  oi.svd_qr = JAC_SVD_QR_OFF;
+  const int info = gesvd_impl(B, n, n, n, S, Ub, n, V, ldv, tol, &oi, stats, s);
+  if (info != 0 && info != 1) return info;
+  if (e2) JAC_HIP(hipEventRecord(e2, s));
+  e = gemm<double>(false, false, m, n, n, 1.0, Qa, m, Ub, n, 0.0, U, ldu, s);   // U = Q_A U_B
+  if (e) return e;
+  if (e3) JAC_HIP(hipEventRecord(e3, s));
+  JAC_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    float a = 0, b = 0;
+    JAC_HIP(hipEventElapsedTime(&a, e0, e1));
+    JAC_HIP(hipEventElapsedTime(&b, e2, e3));
+    stats->svd_qr_used = 1;
+    stats->qr_ms = a + b;
+    stats->stage_ms[5] += a + b;
+    (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); (void)hipEventDestroy(e2); (void)hipEventDestroy(e3);
+  }
+  return info;
+}
 }  // namespace jac
 
 using namespace jac;
@@ -1088,7 +1215,8 @@ int gesvd_jacobi(const double* A, int m, int n, int lda, double* S, double* U, i
   jac_opts o{};
   o.precond = JAC_PRECOND_FP32;
   jac_stats st;
-  e = gesvd_impl(A, m, n, lda, S, U, ldu, V, ldv, tol, &o, &st, nullptr);
+  e = svd_qr_first(o, m, n) ? gesvd_qr_first(A, m, n, lda, S, U, ldu, V, ldv, tol, o, &st, nullptr)
+                            : gesvd_impl(A, m, n, lda, S, U, ldu, V, ldv, tol, &o, &st, nullptr);
   if (sweeps_out) *sweeps_out = st.sweeps;
   return e;
 }
@@ -1097,7 +1225,17 @@ int gesvd_jacobi_ex(const double* A, int m, int n, int lda, double* S, double* U
                     double tol, const jac_opts* opts, jac_stats* stats, void* stream) {
   int e = check_svd_args(A, m, n, lda, S, U, ldu, V, ldv, tol);
   if (e) return e;
-  return gesvd_impl(A, m, n, lda, S, U, ldu, V, ldv, tol, opts, stats, as_stream(stream));
+  jac_opts o{};
+  if (opts) o = *opts;
+  if (o.svd_qr < JAC_SVD_QR_AUTO || o.svd_qr > JAC_SVD_QR_ON) {
+    set_error("gesvd_jacobi_ex: opts.svd_qr must be a jac_svd_qr_t");
+    return -11;
+  }
+  if (svd_qr_first(o, m, n)) {
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    return gesvd_qr_first(A, m, n, lda, S, U, ldu, V, ldv, tol, o, stats, as_stream(stream));
+  }
+  return gesvd_impl(A, m, n, lda, S, U, ldu, V, ldv, tol, &o, stats, as_stream(stream));
 }
 
 int jac_parallel_steps(double* T, int n, int ldt, double* V, int ldv, int r0, int nsteps, double skip_abs,

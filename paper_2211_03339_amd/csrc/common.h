@@ -323,6 +323,8 @@ template <typename T>
 int sort_eigs(const T* d, const T* Vw, int n, int ldw, double* W, double* Vout, int ldv,
               int* rank, hipStream_t s);
 int check_finite(const double* A, int m, int n, int lda, int* flag, hipStream_t s);
+// X <- fl_p(X scale) / scale (p = JAC_PREC_FP16 / JAC_PREC_BF16; scale a power of two).
+int round_lowp(double* X, int m, int n, int ldx, int prec, double scale, hipStream_t s);
 int svd_finish(const double* C, int m, int ldc, const double* Vw, int n, int ldvw, double* sig, int* rank,
                double* S, double* U, int ldu, double* V, int ldv, hipStream_t s);
 
@@ -369,7 +371,9 @@ int orth_series_f64(double* Z, int n, int ldz, double* B1, double* B2, double* B
 int orth_series_batched(double* Z, int np, int count, double* S1, double* S2, double* S3, double* S4, int* state,
                         double* e2_first, hipStream_t s);
 
-// Block modified Gram-Schmidt in place (mgs.hip).  Returns 0 or 3 on breakdown.
+// Block modified Gram-Schmidt in place (mgs.hip).  Returns 0 or 3 on breakdown.  The panel kernel
+// holds a panel's rows in registers: at most kMgsMaxRows rows.
+constexpr int kMgsMaxRows = 8192;
 int mgs_f64(double* Q, int m, int n, int ldq, double* scratch, int* flag, hipStream_t s);
 size_t mgs_scratch_elems(int m, int n);
 

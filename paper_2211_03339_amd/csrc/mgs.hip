@@ -342,7 +342,8 @@ size_t mgs_scratch_elems(int m, int n) {
 }
 
 int mgs_f64(double* Q, int m, int n, int ldq, double* W, int* flag, hipStream_t s) {
-  if (m > 16 * kMT) {
+  static_assert(kMgsMaxRows == 16 * kMT, "the panel kernel's largest register tile");
+  if (m > kMgsMaxRows) {
     set_error("mgs: more than 8192 rows is not supported");
     return -2;
   }

@@ -1,4 +1,8 @@
 // Small device utilities: norms, conversions, identity, output ordering.
+#include <hip/hip_fp16.h>
+
+#include "../../include/jacobi.h"
+
 #include "common.h"
 
 namespace jac {
@@ -221,5 +225,33 @@ template int copy_convert<double, double>(const double*, int, int, int, double*,
 template int copy_convert<float, float>(const float*, int, int, int, float*, int, hipStream_t);
 template int sort_eigs<double>(const double*, const double*, int, int, double*, double*, int, int*, hipStream_t);
 template int sort_eigs<float>(const float*, const float*, int, int, double*, double*, int, int*, hipStream_t);
+
+// X <- fl_p(X scale) / scale in place (m x n, ldx): the value of precision p (FP16 or BF16, round to
+// nearest even, reached through FP32) of each entry; scale is a power of two, so the scaling is exact.
+__global__ void round_lowp_kernel(double* __restrict__ X, int m, int n, int ldx, int prec, double scale) {
+  const int j = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    double* x = X + i + (size_t)j * ldx;
+    const float f = (float)(*x * scale);
+    float r;
+    if (prec == JAC_PREC_FP16) {
+      r = __half2float(__float2half_rn(f));
+    } else {   // BF16: keep the top 16 bits, rounded to nearest even
+      unsigned int u = __float_as_uint(f);
+      if ((u & 0x7F800000u) != 0x7F800000u) u += 0x7FFFu + ((u >> 16) & 1u);
+      r = __uint_as_float(u & 0xFFFF0000u);
+    }
+    *x = (double)r / scale;
+  }
+}
+
+int round_lowp(double* X, int m, int n, int ldx, int prec, double scale, hipStream_t s) {
+  if (m <= 0 || n <= 0) return 0;
+  int gx = (m + 255) / 256;
+  if (gx > 16) gx = 16;
+  hipLaunchKernelGGL(round_lowp_kernel, dim3(gx, n), dim3(256), 0, s, X, m, n, ldx, prec, scale);
+  JAC_CHECK_LAUNCH();
+  return 0;
+}
 
 }  // namespace jac

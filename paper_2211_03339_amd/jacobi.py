@@ -26,6 +26,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "jacobi.h")
 PRECOND = {"none": 0, "fp32": 1, "mlp": 2}
 VARIANT = {"auto": 0, "element": 1, "blocked": 2}
 STAGE1 = {"auto": 0, "jacobi": 1, "tridiag": 2}
+SVD_QR = {"auto": 0, "off": 1, "on": 2}
+PREC = {"fp32": 0, "fp16": 1, "bf16": 2}
 JAC_HIST = 65
 
 
@@ -34,7 +36,8 @@ class JacOpts(ctypes.Structure):
                 ("max_sweeps", ctypes.c_int), ("fp32_tol", ctypes.c_double),
                 ("fp32_max_sweeps", ctypes.c_int), ("mlp", ctypes.c_void_p),
                 ("theta", ctypes.c_void_p), ("fallback_tol", ctypes.c_double),
-                ("inner_sweeps", ctypes.c_int), ("profile", ctypes.c_int), ("stage1", ctypes.c_int)]
+                ("inner_sweeps", ctypes.c_int), ("profile", ctypes.c_int), ("stage1", ctypes.c_int),
+                ("svd_qr", ctypes.c_int), ("stage1_prec", ctypes.c_int)]
 
 
 class JacBatchedOpts(ctypes.Structure):
@@ -60,7 +63,7 @@ class JacStats(ctypes.Structure):
                 ("fp32_step_ms", ctypes.c_double), ("fp32_step_launches", ctypes.c_longlong),
                 ("kern_ms", ctypes.c_double * 8), ("kern_launches", ctypes.c_longlong * 8),
                 ("kern_work", ctypes.c_longlong * 8), ("start_resid", ctypes.c_double),
-                ("fp32_method", ctypes.c_int)]
+                ("fp32_method", ctypes.c_int), ("svd_qr_used", ctypes.c_int), ("qr_ms", ctypes.c_float)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_
@@ -199,9 +202,10 @@ def _colmajor(M: torch.Tensor) -> torch.Tensor:
 
 
 def _opts(precond="fp32", variant="auto", block_b=0, max_sweeps=0, fp32_tol=0.0, fp32_max_sweeps=0,
-          fallback_tol=0.0, inner_sweeps=0, profile=0, mlp=None, theta=None, stage1="auto"):
+          fallback_tol=0.0, inner_sweeps=0, profile=0, mlp=None, theta=None, stage1="auto", stage1_prec="fp32"):
     o = JacOpts()
     o.stage1 = STAGE1[stage1] if isinstance(stage1, str) else int(stage1)
+    o.stage1_prec = PREC[stage1_prec] if isinstance(stage1_prec, str) else int(stage1_prec)
     if mlp is not None:
         o.mlp = mlp.h.value
     if theta is not None:
@@ -236,7 +240,7 @@ def syev_jacobi(A: torch.Tensor, tol: float = 0.0):
 
 def syev_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", variant="auto", max_sweeps=0,
                    fp32_tol=0.0, fp32_max_sweeps=0, block_b=0, allow_unconverged=False, inner_sweeps=0,
-                   mlp=None, theta=None, fallback_tol=0.0, profile=0, stage1="auto"):
+                   mlp=None, theta=None, fallback_tol=0.0, profile=0, stage1="auto", stage1_prec="fp32"):
     """Returns (W, V, stats dict, info).  precond="mlp" takes the network `mlp` (Mlp) and its
     input `theta` (device float32 tensor of n_in values)."""
     if theta is not None:
@@ -248,7 +252,8 @@ def syev_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", variant="a
     W = torch.empty(n, dtype=torch.float64, device=A.device)
     Vb = torch.empty((n, n), dtype=torch.float64, device=A.device)
     o = _opts(precond, variant, block_b, max_sweeps, fp32_tol, fp32_max_sweeps, fallback_tol=fallback_tol,
-              inner_sweeps=inner_sweeps, profile=profile, mlp=mlp, theta=theta, stage1=stage1)
+              inner_sweeps=inner_sweeps, profile=profile, mlp=mlp, theta=theta, stage1=stage1,
+              stage1_prec=stage1_prec)
     st = JacStats()
     code = L.syev_jacobi_ex(_vp(Ac.data_ptr()), n, max(n, 1), _vp(W.data_ptr()), _vp(Vb.data_ptr()),
                             max(n, 1), tol, ctypes.byref(o), ctypes.byref(st), _stream())
@@ -326,8 +331,9 @@ def gesvd_jacobi(A: torch.Tensor, tol: float = 0.0):
 
 
 def gesvd_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", max_sweeps=0, variant="auto",
-                    allow_unconverged=False, stage1="auto"):
-    """Thin SVD A = U diag(S) V^T (m >= n): returns (S descending, U, V, stats, info)."""
+                    allow_unconverged=False, stage1="auto", svd_qr="auto"):
+    """Thin SVD A = U diag(S) V^T (m >= n): returns (S descending, U, V, stats, info).
+    svd_qr: "auto" / "off" / "on" (QR first, for m >> n)."""
     L = load()
     A = _dev(A)
     m, n = A.shape
@@ -336,6 +342,7 @@ def gesvd_jacobi_ex(A: torch.Tensor, tol: float = 0.0, precond="fp32", max_sweep
     Ub = torch.empty((n, m), dtype=torch.float64, device=A.device)
     Vb = torch.empty((n, n), dtype=torch.float64, device=A.device)
     o = _opts(precond, variant, 0, max_sweeps, stage1=stage1)
+    o.svd_qr = SVD_QR[svd_qr]
     st = JacStats()
     code = L.gesvd_jacobi_ex(_vp(Ac.data_ptr()), m, n, max(m, 1), _vp(S.data_ptr()), _vp(Ub.data_ptr()),
                              max(m, 1), _vp(Vb.data_ptr()), max(n, 1), tol, ctypes.byref(o), ctypes.byref(st),

@@ -1,12 +1,17 @@
-"""What the trained network gains: a reduced-size run of the learned-start pipeline.
+"""What the trained network gains, against the starts it competes with: the constant start Z0 (the
+eigenvectors of A0, i.e. theta = 0, which every member of the family can take), the FP32 start and
+plain Jacobi.
 
-Family A(theta) = A0 + sum_k theta_k B_k at n = 32 (8 parameters), network 8 -> 256 -> 256 -> 32^2,
-trained on 4096 solves of the batched FP64 path, evaluated on 24 held-out parameters.  Asserted:
-every solve (learned start with fallback, learned start always accepted, FP32 start, plain) meets
-the acceptance bar; training lowers the loss; the trained network's start is closer to diagonal
-than both the untrained network's and no start at all (A itself), and started from it Jacobi needs
-no more sweeps than plain Jacobi.  The comparison with the FP32 start is printed, not asserted:
-how far a learned start gets is what this run measures.
+* The learning machinery on a small family (n = 32, network 8 -> 256 -> 256 -> 32^2, random
+  initialisation, eigenvalue-ordered targets): training lowers the loss, and the trained start is
+  closer to diagonal than the untrained network's and than no start at all.
+* The configured family (n = 256, network 8 -> 1024 -> 1024 -> 256^2) as the trainer runs it: the
+  network starts as the constant start (last layer zero, output bias vec(Z0)), its targets are the
+  eigenvectors matched to Z0's columns, and the parameters with the best validation start residual
+  are kept.  Asserted: the trained start is no worse than the constant start; both stay far above
+  the 1e-2 acceptance bar on this family (the perturbation spans many eigenvalue spacings, so
+  eigenvectors reorder across theta), so every learned solve falls back to the FP32 start; the
+  constant start needs fewer FP64 sweeps than plain Jacobi.  Every solve meets the accuracy bars.
 """
 import json
 
@@ -26,23 +31,59 @@ def test_learned_start_gain_small_family():
     A0, B = learned.family(n)
     th_train = tm.param_thetas(4096, learned.THETA_TRAIN_SEED)
     th_eval = tm.param_thetas(24, learned.THETA_EVAL_SEED)
-    print("[learned] data", flush=True)
+    print("[learned n=32] data", flush=True)
     theta, T, data = learned.make_dataset(A0, B, th_train)
     assert data["unconverged"] == 0
     net = jacobi.Mlp(8, hidden, n, 256, seed=3)
     before = learned.evaluate(net, A0, B, th_eval, check=False, forced=False)
-    print("[learned] train", flush=True)
+    print("[learned n=32] train", flush=True)
     tr = learned.train(net, theta, T, epochs=40, batch=256, lr=2e-3, weight_decay=1e-4)
-    print("[learned] eval", flush=True)
-    ev = learned.evaluate(net, A0, B, th_eval)
+    print("[learned n=32] eval", flush=True)
+    Z0 = learned.constant_start(A0)
+    ev = learned.evaluate(net, A0, B, th_eval, Z0=Z0)
     print(json.dumps({"data": data, "loss": tr["loss_per_epoch"][::8] + tr["loss_per_epoch"][-1:],
                       "before": before["learned_start"], "after": ev}), flush=True)
     assert tr["loss_per_epoch"][-1] < 0.5 * tr["loss_per_epoch"][0]
-    for m in ("mlp", "mlp_forced", "fp32", "plain"):
+    for m in ("mlp", "mlp_forced", "const", "fp32", "plain"):
         assert ev[m]["max_res"] <= 1e-13, (m, ev[m])
         assert ev[m]["max_orth"] <= 1e-13, (m, ev[m])
     ls = ev["learned_start"]
     assert ls["mean_start_resid"] < before["learned_start"]["mean_start_resid"]
     assert ls["mean_start_resid"] < ls["mean_identity_start_resid"]
     assert ev["mlp_forced"]["mean_sweeps"] <= ev["plain"]["mean_sweeps"]
+    net.close()
+
+
+def test_learned_start_configured_family_vs_constant_start():
+    n, hidden = 256, 1024
+    A0, B = learned.family(n)
+    Z0 = learned.constant_start(A0)
+    th_train = tm.param_thetas(4096, learned.THETA_TRAIN_SEED)
+    th_eval = tm.param_thetas(12, learned.THETA_EVAL_SEED)
+    print("[learned n=256] data", flush=True)
+    theta, T, data = learned.make_dataset(A0, B, th_train, Z0=Z0)
+    assert data["unconverged"] == 0
+    net = jacobi.Mlp(8, hidden, n, 256, seed=3)
+    learned.init_as_correction(net, Z0)
+    # the correction-initialised network outputs Z0 itself
+    Zp = net.predict(torch.zeros(8, dtype=torch.float32, device="cuda"))
+    assert (Zp - Z0).abs().max().item() <= 2.0 ** -24 * Z0.abs().max().item()
+    val = learned.validation_set(A0, B, tm.param_thetas(8, learned.THETA_VAL_SEED))
+    print("[learned n=256] train", flush=True)
+    tr = learned.train(net, theta, T, epochs=6, batch=256, lr=3e-4, weight_decay=0.0, val=val)
+    print("[learned n=256] eval", flush=True)
+    ev = learned.evaluate(net, A0, B, th_eval, Z0=Z0)
+    out = {"loss": tr["loss_per_epoch"], "val_start_resid": tr["val_start_resid"], "kept_epoch": tr["kept_epoch"],
+           "learned": ev["learned_start"], "const": ev["const_start"],
+           "sweeps": {m: ev[m]["mean_sweeps"] for m in ("mlp", "mlp_forced", "const", "fp32", "plain")},
+           "ms": {m: round(ev[m]["mean_ms"], 2) for m in ("mlp", "mlp_forced", "const", "fp32", "plain")}}
+    print(json.dumps(out), flush=True)
+    for m in ("mlp", "mlp_forced", "const", "fp32", "plain"):
+        assert ev[m]["max_res"] <= 1e-13, (m, ev[m])
+        assert ev[m]["max_orth"] <= 1e-13, (m, ev[m])
+    ls, cs = ev["learned_start"], ev["const_start"]
+    assert ls["mean_start_resid"] <= 1.02 * cs["mean_start_resid"]
+    assert cs["min_start_resid"] > 1e-2 and ls["fallback_rate"] == 1.0
+    assert ev["mlp"]["mean_sweeps"] == ev["fp32"]["mean_sweeps"]
+    assert ev["const"]["mean_sweeps"] < ev["plain"]["mean_sweeps"]
     net.close()

@@ -89,3 +89,39 @@ def test_gesvd_jacobi_default_entry_point():
     check_svd(A, S, U, V, sig)
     ref = oracle.gesvd(A)
     assert np.abs(S - ref.S).max() <= 1e-12 * sig.max()
+
+
+@pytest.mark.parametrize("m,n,pre", [(700, 40, "fp32"), (2000, 100, "none"), (2048, 128, "fp32"),
+                                     (4096, 256, "fp32"), (8192, 512, "fp32")])
+def test_svd_qr_first(m, n, pre):
+    """QR preconditioning for m >> n (the remark after Algorithm 5.2): A = Q_A B by two passes of
+    block MGS, the SVD of the n x n B, U = Q_A U_B.  The same bars as the direct form, the known
+    singular values, and the direct form's singular values."""
+    A, sig = tm.svd_case(m, n, decades=6.0, seed=31 + m + n)
+    print(f"[svd qr-first m={m} n={n} {pre}]", flush=True)
+    S, U, V, st, info = jacobi.gesvd_jacobi_ex(dev(A), precond=pre, svd_qr="on")
+    assert info == 0 and st["svd_qr_used"] == 1
+    check_svd(A, host(S), host(U), host(V), sig)
+    S2, U2, V2, st2, info2 = jacobi.gesvd_jacobi_ex(dev(A), precond=pre, svd_qr="off")
+    assert st2["svd_qr_used"] == 0
+    assert np.abs(host(S) - host(S2)).max() <= 1e-12 * sig.max()
+    print(f"  qr-first {st['stage_ms']['total']:.2f} ms ({st['sweeps']} sweeps, QR {st['qr_ms']:.2f} ms) vs "
+          f"direct {st2['stage_ms']['total']:.2f} ms ({st2['sweeps']} sweeps)", flush=True)
+    if n <= 64:
+        ref = oracle.gesvd(A)
+        assert np.abs(host(S) - ref.S).max() <= 1e-12 * ref.S[0]
+
+
+def test_svd_qr_first_rule_and_limit():
+    A, _ = tm.svd_case(1024, 100, seed=5)
+    _, _, _, st, _ = jacobi.gesvd_jacobi_ex(dev(A))            # m >= 8 n: QR first
+    assert st["svd_qr_used"] == 1
+    A, _ = tm.svd_case(1024, 200, seed=6)
+    _, _, _, st, _ = jacobi.gesvd_jacobi_ex(dev(A))            # m < 8 n: direct
+    assert st["svd_qr_used"] == 0
+    A, _ = tm.svd_case(8200, 8, seed=7)
+    _, _, _, st, _ = jacobi.gesvd_jacobi_ex(dev(A))            # beyond the MGS rows: direct
+    assert st["svd_qr_used"] == 0
+    with pytest.raises(jacobi.JacobiError) as e:
+        jacobi.gesvd_jacobi_ex(dev(A), svd_qr="on")
+    assert e.value.code == -2
