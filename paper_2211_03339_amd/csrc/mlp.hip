@@ -1,7 +1,7 @@
 // Learned warm start (a project addition; the paper has no learned component): a three-layer
 // perceptron theta (I values) -> H -> ReLU -> H -> ReLU -> O = n^2 values, read as the
 // column-major entries of an approximate eigenvector matrix Z of A(theta), which then takes
-// the place of the FP32 eigensolve (Section 3, step 1) in front of MGS and Q^T A Q.
+// the place of the FP32 eigensolve (Algorithm 4.1, step 1) in front of MGS and Q^T A Q.
 //
 // Precision model: every matrix product takes bfloat16 operands, rounded to nearest even from
 // FP32, and accumulates in FP32; the first layer (I <= 32 inputs) runs on the vector units with
