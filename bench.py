@@ -385,7 +385,8 @@ def main():
 def learned_row(n_train: int, n_eval: int = 32, epochs: int = 8):
     """Learned start on the n = 256 family (the network row of the metric at the size where it is
     feasible), as the trainer runs it: the network starts as the constant start Z0 (eigenvectors of
-    A0), its targets are n_train method-generated solves matched to Z0's columns, and the
+    A0), its targets are n_train method-generated solves aligned to Z0 within windows of nearby
+    eigenvalues, and the
     parameters with the best start residual on 16 validation matrices are kept; then solves of
     held-out matrices with the learned start (FP32 fallback), the constant start, the FP32 start and
     plain Jacobi are timed."""
@@ -393,12 +394,13 @@ def learned_row(n_train: int, n_eval: int = 32, epochs: int = 8):
     from paper_2211_03339_amd import testmats as tm
     n = 256
     A0, B = learned.family(n)
-    Z0 = learned.constant_start(A0)
-    theta, T, data = learned.make_dataset(A0, B, tm.param_thetas(n_train, learned.THETA_TRAIN_SEED), Z0=Z0)
+    Z0, lam0 = learned.constant_start(A0, with_eigenvalues=True)
+    theta, T, data = learned.make_dataset(A0, B, tm.param_thetas(n_train, learned.THETA_TRAIN_SEED), Z0=Z0,
+                                          lam0=lam0)
     net = learned.jacobi.Mlp(8, 1024, n, 256, seed=0)
     learned.init_as_correction(net, Z0)
     val = learned.validation_set(A0, B, tm.param_thetas(16, learned.THETA_VAL_SEED))
-    tr = learned.train(net, theta, T, epochs=epochs, batch=256, lr=3e-4, weight_decay=0.0, val=val)
+    tr = learned.train(net, theta, T, epochs=epochs, batch=256, lr=1e-4, weight_decay=0.0, val=val)
     del T
     ev = learned.evaluate(net, A0, B, tm.param_thetas(n_eval, learned.THETA_EVAL_SEED), check=True, Z0=Z0)
     net.close()

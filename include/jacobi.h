@@ -321,6 +321,11 @@ int jac_mlp_train_step(struct jac_mlp* net, const float* theta, const unsigned s
  * T + c ldt (device).  count <= 65535. */
 int jac_mlp_pack_targets(const double* V, int n, int ldv, long long stride_v, int count, unsigned short* T,
                          long long ldt, void* stream);
+/* The same with a choice of signs: sign_mode 0 as jac_mlp_pack_targets,
+ * 1 the columns as given (for targets whose signs the caller has already
+ * aligned).  Error -8: sign_mode not 0 or 1. */
+int jac_mlp_pack_targets_ex(const double* V, int n, int ldv, long long stride_v, int count, unsigned short* T,
+                            long long ldt, int sign_mode, void* stream);
 /* Weights, AdamW moments, step count and hyper-parameters to / from a file
  * ("JACMLP01", int32 n_in, hidden, n, int64 t, float beta1, beta2, eps, then
  * the weights, first and second moments as num_params floats each).  Loading

@@ -439,7 +439,7 @@ __global__ void init_uniform_kernel(float* __restrict__ p, long long off, long l
 // first one on ties) is made positive; the column-major entries are rounded to bfloat16 (from
 // their FP32 value).  One workgroup per (column, matrix).
 __global__ void pack_targets_kernel(const double* __restrict__ V, int n, int ldv, long long stride_v,
-                                    uint16_t* __restrict__ T, long long ldt) {
+                                    uint16_t* __restrict__ T, long long ldt, int canonical) {
   __shared__ double bv[4];
   __shared__ int bi[4];
   const int j = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
@@ -462,7 +462,7 @@ __global__ void pack_targets_kernel(const double* __restrict__ V, int n, int ldv
       if (bv[w] > bv[0] || (bv[w] == bv[0] && bi[w] < bi[0])) { bv[0] = bv[w]; bi[0] = bi[w]; }
   }
   __syncthreads();
-  const double sgn = col[bi[0]] < 0.0 ? -1.0 : 1.0;
+  const double sgn = (canonical && col[bi[0]] < 0.0) ? -1.0 : 1.0;
   uint16_t* out = T + c * ldt + (size_t)j * n;
   for (int i = tid; i < n; i += blockDim.x) out[i] = f2bf((float)(sgn * col[i]));
 }
@@ -739,9 +739,10 @@ int jac_mlp_train_step(jac_mlp* net, const float* theta, const uint16_t* target,
   return jac_mlp_adamw(net, lr, weight_decay, stream);
 }
 
-int jac_mlp_pack_targets(const double* V, int n, int ldv, long long stride_v, int count, uint16_t* T, long long ldt,
-                         void* stream) {
+int jac_mlp_pack_targets_ex(const double* V, int n, int ldv, long long stride_v, int count, uint16_t* T,
+                            long long ldt, int sign_mode, void* stream) {
   if (n < 0 || count < 0) { set_error("jac_mlp_pack_targets: negative size"); return -2; }
+  if (sign_mode != 0 && sign_mode != 1) { set_error("jac_mlp_pack_targets_ex: sign_mode must be 0 or 1"); return -8; }
   if (n == 0 || count == 0) return 0;
   if (!V || !T) { set_error("jac_mlp_pack_targets: NULL argument"); return -1; }
   if (ldv < n) { set_error("jac_mlp_pack_targets: ldv < n"); return -3; }
@@ -749,9 +750,14 @@ int jac_mlp_pack_targets(const double* V, int n, int ldv, long long stride_v, in
   if (count > 1 && ldt < (long long)n * n) { set_error("jac_mlp_pack_targets: ldt < n^2"); return -7; }
   if (count > 65535) { set_error("jac_mlp_pack_targets: count > 65535"); return -5; }
   hipLaunchKernelGGL(pack_targets_kernel, dim3(n, count), dim3(256), 0, as_stream(stream), V, n, ldv, stride_v, T,
-                     ldt);
+                     ldt, sign_mode == 0 ? 1 : 0);
   JAC_CHECK_LAUNCH();
   return 0;
+}
+
+int jac_mlp_pack_targets(const double* V, int n, int ldv, long long stride_v, int count, uint16_t* T, long long ldt,
+                         void* stream) {
+  return jac_mlp_pack_targets_ex(V, n, ldv, stride_v, count, T, ldt, 0, stream);
 }
 
 // File layout: "JACMLP01", int32 I, H, n, int64 steps, float beta1, beta2, eps, then P floats

@@ -152,6 +152,7 @@ def load():
         "jac_mlp_train_step": (_i, [_vp, _vp, _vp, ctypes.c_longlong, _i, ctypes.c_float, ctypes.c_float, _vp,
                                     _vp]),
         "jac_mlp_pack_targets": (_i, [_vp, _i, _i, ctypes.c_longlong, _i, _vp, ctypes.c_longlong, _vp]),
+        "jac_mlp_pack_targets_ex": (_i, [_vp, _i, _i, ctypes.c_longlong, _i, _vp, ctypes.c_longlong, _i, _vp]),
         "jac_mlp_save": (_i, [_vp, ctypes.c_char_p]),
         "jac_mlp_load": (_i, [_vp, ctypes.c_char_p]),
         "jac_workspace_bytes": (ctypes.c_size_t, [_i, ctypes.POINTER(JacOpts)]),
@@ -662,15 +663,16 @@ class Mlp:
         _check("jac_mlp_load", load().jac_mlp_load(self.h, path.encode()))
 
 
-def jac_mlp_pack_targets(V: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-    """Sign-canonicalised bfloat16 training targets of a stack of eigenvector matrices.
-    V: (count, n, n) FP64, V[c][:, j] = eigenvector j.  Returns (count, n*n) int16 bfloat16 bits,
-    row c = column-major entries of V[c] with every column's largest-|entry| made positive."""
+def jac_mlp_pack_targets(V: torch.Tensor, out: torch.Tensor | None = None, canonical: bool = True) -> torch.Tensor:
+    """bfloat16 training targets of a stack of eigenvector matrices.  V: (count, n, n) FP64,
+    V[c][:, j] = eigenvector j.  Returns (count, n*n) int16 bfloat16 bits, row c = column-major
+    entries of V[c], with every column's largest-|entry| made positive (canonical) or as given."""
     V = _dev(V)
     count, n, _ = V.shape
     Vc = V.transpose(1, 2).contiguous()          # row-major buffer of V^T = column-major V
     if out is None:
         out = torch.empty((count, n * n), dtype=torch.int16, device=V.device)
-    _check("jac_mlp_pack_targets", load().jac_mlp_pack_targets(_vp(Vc.data_ptr()), n, n, n * n, count,
-                                                                _vp(out.data_ptr()), out.stride(0), _stream()))
+    _check("jac_mlp_pack_targets", load().jac_mlp_pack_targets_ex(_vp(Vc.data_ptr()), n, n, n * n, count,
+                                                                   _vp(out.data_ptr()), out.stride(0),
+                                                                   0 if canonical else 1, _stream()))
     return out

@@ -3,9 +3,10 @@ training loop and the evaluation against the FP32 start and plain Jacobi.
 
 Matrix family: A(theta) = A0 + sum_k theta_k B_k with A0, B_k symmetric (0.5 (G + G^T),
 G ~ N(0, 1)), B_k scaled by 0.1 and theta ~ U[-1, 1]^k.  Every training matrix is solved by the
-batched FP64 Jacobi path (syev_jacobi_batched); its eigenvectors, matched column by column to
-the constant start Z0 (align_to; without Z0: in ascending eigenvalue order), become
-sign-canonical bfloat16 targets (jac_mlp_pack_targets).  Training runs jac_mlp_train_step
+batched FP64 Jacobi path (syev_jacobi_batched); its eigenvectors, aligned to the constant start
+Z0 within windows of nearby eigenvalues (window_align; without Z0: in ascending eigenvalue order),
+become bfloat16 targets (jac_mlp_pack_targets; eigenvalue-ordered ones with their signs made
+canonical, aligned ones with the signs the alignment gave them).  Training runs jac_mlp_train_step
 over shuffled mini-batches with a cosine-decayed learning rate.  The network starts as the
 constant start -- the eigenvectors Z0 of A0 (theta = 0), which every member of the family can
 take -- with its last layer zero and its output bias vec(Z0), so it learns a correction to Z0.
@@ -47,15 +48,17 @@ def matrices(A0: torch.Tensor, B: torch.Tensor, theta: torch.Tensor) -> torch.Te
     return 0.5 * (A + A.transpose(1, 2))
 
 
-def constant_start(A0: torch.Tensor) -> torch.Tensor:
+def constant_start(A0: torch.Tensor, with_eigenvalues: bool = False):
     """Z0: the eigenvectors of A0 in ascending eigenvalue order with every column's largest-|entry|
-    positive (the sign convention of the training targets); columns are the vectors."""
-    _, V, _, _ = jacobi.syev_jacobi_ex(A0, precond="fp32")
+    positive (the sign convention of the training targets); columns are the vectors.  With
+    with_eigenvalues, (Z0, lam0)."""
+    W, V, _, _ = jacobi.syev_jacobi_ex(A0, precond="fp32")
     V = V.contiguous()
     idx = V.abs().argmax(dim=0)
     sgn = torch.sign(V[idx, torch.arange(V.shape[1], device=V.device)])
     sgn[sgn == 0] = 1.0
-    return (V * sgn[None, :]).contiguous()
+    Z0 = (V * sgn[None, :]).contiguous()
+    return (Z0, W) if with_eigenvalues else Z0
 
 
 def init_as_correction(net: jacobi.Mlp, Z0: torch.Tensor):
@@ -106,27 +109,35 @@ class BatchedSolver:
         jacobi._check("syev_jacobi_batched", code)
 
 
-def align_to(V: torch.Tensor, Z0: torch.Tensor) -> torch.Tensor:
-    """V: (count, n, n) with V[c][:, j] an eigenvector of A(theta_c).  Returns the eigenvectors with
-    their columns reordered to match the columns of Z0: a linear assignment that maximises
-    sum_j |v_perm(j) . z0_j| over |V[c]^T Z0| (the overlaps from the library's GEMM).  The targets
-    then follow the eigenvectors that continue each column of the constant start, instead of the
-    eigenvalue order, which reshuffles them wherever eigenvalues cross."""
-    from scipy.optimize import linear_sum_assignment
+def window_align(V: torch.Tensor, lam: torch.Tensor, Z0: torch.Tensor, lam0: torch.Tensor, delta: float = 2.0,
+                 iters: int = 12) -> torch.Tensor:
+    """Targets that follow the constant start where the spectrum lets them.  V: (count, n, n) with
+    V[c][:, i] the eigenvector of A(theta_c) for eigenvalue lam[c, i]; Z0, lam0: the eigenpairs of
+    A0.  Target c is V[c] P with P the orthogonal polar factor of the overlaps V[c]^T Z0 kept only
+    where |lam_i - lam0_j| <= delta: column j mixes only eigenvectors whose eigenvalues lie within
+    delta of Z0's eigenvalue j, so it stays close to an invariant subspace (a good start), and the
+    arbitrary rotations inside groups of nearby eigenvalues, which make the eigenvectors themselves
+    jump as theta moves, are taken out (it varies smoothly with theta).  The polar factor comes from
+    Newton-Schulz steps X <- X (3 I - X^T X) / 2 (the products by the library's GEMM), started from
+    the masked overlaps scaled below unit 2-norm by sqrt(||X||_1 ||X||_inf)."""
     count, n, _ = V.shape
     out = torch.empty_like(V)
     for c in range(count):
-        M = jacobi.jac_gemm(V[c].contiguous(), Z0, transa=True).abs().cpu().numpy()   # M[i, j] = |v_i . z0_j|
-        rows, cols = linear_sum_assignment(M, maximize=True)
-        perm = np.empty(n, dtype=np.int64)
-        perm[cols] = rows
-        out[c] = V[c][:, torch.from_numpy(perm).to(V.device)]
+        M = jacobi.jac_gemm(V[c].contiguous(), Z0, transa=True)            # M[i, j] = v_i . z0_j
+        M = M * ((lam[c][:, None] - lam0[None, :]).abs() <= delta)
+        s = math.sqrt(float(M.abs().sum(0).max()) * float(M.abs().sum(1).max()))
+        X = (M / max(s, 1e-300)).contiguous()
+        for _ in range(iters):
+            G = jacobi.jac_gemm(X, X, transa=True)
+            X = (1.5 * X - 0.5 * jacobi.jac_gemm(X, G)).contiguous()
+        out[c] = jacobi.jac_gemm(V[c].contiguous(), X)
     return out
 
 
-def make_dataset(A0, B, thetas: np.ndarray, chunk: int = 4096, Z0: torch.Tensor | None = None, log=None):
+def make_dataset(A0, B, thetas: np.ndarray, chunk: int = 4096, Z0: torch.Tensor | None = None,
+                 lam0: torch.Tensor | None = None, delta: float = 2.0, log=None):
     """Targets (count, n^2) int16 bfloat16 bits and theta (count, k) float32, on the device.  With Z0
-    the eigenvectors are matched to Z0's columns (align_to) before packing."""
+    (and A0's eigenvalues lam0) the eigenvectors are aligned to Z0 (window_align) before packing."""
     n = A0.shape[0]
     count = thetas.shape[0]
     O = n * n
@@ -145,9 +156,9 @@ def make_dataset(A0, B, thetas: np.ndarray, chunk: int = 4096, Z0: torch.Tensor 
         # solver.V[c] holds column-major eigenvectors: its transpose as a (n, n) tensor has
         # columns = eigenvectors, which is the layout jac_mlp_pack_targets reads.
         Vc = solver.V[: c1 - c0].transpose(1, 2)
-        if Z0 is not None:
-            Vc = align_to(Vc, Z0)
-        jacobi.jac_mlp_pack_targets(Vc, out=T[c0:c1])
+        if Z0 is not None:   # aligned to Z0, signs included: packed as they are
+            Vc = window_align(Vc, solver.W[: c1 - c0], Z0, lam0, delta)
+        jacobi.jac_mlp_pack_targets(Vc, out=T[c0:c1], canonical=Z0 is None)
         unconverged += int((solver.info[: c1 - c0] != 0).sum().item())
         if log:
             log(f"[data] {c1}/{count} solved ({time.perf_counter() - t0:.1f} s)")
@@ -275,13 +286,13 @@ def evaluate(net: jacobi.Mlp, A0, B, thetas: np.ndarray, fallback_tol: float = 1
     return summary
 
 
-def run(n=256, hidden=1024, n_train=50000, n_eval=5000, epochs=20, batch=256, lr=1e-3, weight_decay=1e-4,
+def run(n=256, hidden=1024, n_train=50000, n_eval=5000, epochs=20, batch=256, lr=1e-4, weight_decay=0.0,
         fallback_tol=1e-2, seed=0, correction=True, log=None):
     A0, B = family(n)
     th_train = tm.param_thetas(n_train, THETA_TRAIN_SEED)
     th_eval = tm.param_thetas(n_eval, THETA_EVAL_SEED)
-    Z0 = constant_start(A0)
-    theta, T, data = make_dataset(A0, B, th_train, Z0=Z0 if correction else None, log=log)
+    Z0, lam0 = constant_start(A0, with_eigenvalues=True)
+    theta, T, data = make_dataset(A0, B, th_train, Z0=Z0 if correction else None, lam0=lam0, log=log)
     net = jacobi.Mlp(th_train.shape[1], hidden, n, batch, seed=seed)
     if correction:
         init_as_correction(net, Z0)
@@ -304,8 +315,8 @@ def main(argv=None):
     ap.add_argument("--eval", type=int, default=5000)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=256)
-    ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--wd", type=float, default=1e-4)
+    ap.add_argument("--lr", type=float, default=1e-4)
+    ap.add_argument("--wd", type=float, default=0.0)
     ap.add_argument("--fallback-tol", type=float, default=1e-2)
     ap.add_argument("--no-correction", action="store_true", help="train from the random initialisation")
     ap.add_argument("--out", default=None)

@@ -7,11 +7,12 @@ plain Jacobi.
   closer to diagonal than the untrained network's and than no start at all.
 * The configured family (n = 256, network 8 -> 1024 -> 1024 -> 256^2) as the trainer runs it: the
   network starts as the constant start (last layer zero, output bias vec(Z0)), its targets are the
-  eigenvectors matched to Z0's columns, and the parameters with the best validation start residual
-  are kept.  Asserted: the trained start is no worse than the constant start; both stay far above
-  the 1e-2 acceptance bar on this family (the perturbation spans many eigenvalue spacings, so
-  eigenvectors reorder across theta), so every learned solve falls back to the FP32 start; the
-  constant start needs fewer FP64 sweeps than plain Jacobi.  Every solve meets the accuracy bars.
+  method's eigenvectors aligned to Z0 within windows of nearby eigenvalues, and the parameters with
+  the best validation start residual are kept.  Asserted: the trained start beats the constant
+  start by at least 2x in start residual on held-out parameters; both stay above the 1e-2
+  acceptance bar on this family (the perturbation spans many eigenvalue spacings), so every
+  learned solve falls back to the FP32 start; the constant start needs fewer FP64 sweeps than
+  plain Jacobi.  Every solve meets the accuracy bars.
 """
 import json
 
@@ -57,11 +58,11 @@ def test_learned_start_gain_small_family():
 def test_learned_start_configured_family_vs_constant_start():
     n, hidden = 256, 1024
     A0, B = learned.family(n)
-    Z0 = learned.constant_start(A0)
+    Z0, lam0 = learned.constant_start(A0, with_eigenvalues=True)
     th_train = tm.param_thetas(4096, learned.THETA_TRAIN_SEED)
     th_eval = tm.param_thetas(12, learned.THETA_EVAL_SEED)
     print("[learned n=256] data", flush=True)
-    theta, T, data = learned.make_dataset(A0, B, th_train, Z0=Z0)
+    theta, T, data = learned.make_dataset(A0, B, th_train, Z0=Z0, lam0=lam0)
     assert data["unconverged"] == 0
     net = jacobi.Mlp(8, hidden, n, 256, seed=3)
     learned.init_as_correction(net, Z0)
@@ -70,7 +71,7 @@ def test_learned_start_configured_family_vs_constant_start():
     assert (Zp - Z0).abs().max().item() <= 2.0 ** -24 * Z0.abs().max().item()
     val = learned.validation_set(A0, B, tm.param_thetas(8, learned.THETA_VAL_SEED))
     print("[learned n=256] train", flush=True)
-    tr = learned.train(net, theta, T, epochs=6, batch=256, lr=3e-4, weight_decay=0.0, val=val)
+    tr = learned.train(net, theta, T, epochs=8, batch=256, lr=1e-4, weight_decay=0.0, val=val)
     print("[learned n=256] eval", flush=True)
     ev = learned.evaluate(net, A0, B, th_eval, Z0=Z0)
     out = {"loss": tr["loss_per_epoch"], "val_start_resid": tr["val_start_resid"], "kept_epoch": tr["kept_epoch"],
@@ -82,8 +83,8 @@ def test_learned_start_configured_family_vs_constant_start():
         assert ev[m]["max_res"] <= 1e-13, (m, ev[m])
         assert ev[m]["max_orth"] <= 1e-13, (m, ev[m])
     ls, cs = ev["learned_start"], ev["const_start"]
-    assert ls["mean_start_resid"] <= 1.02 * cs["mean_start_resid"]
-    assert cs["min_start_resid"] > 1e-2 and ls["fallback_rate"] == 1.0
+    assert ls["mean_start_resid"] < 0.5 * cs["mean_start_resid"]
+    assert ls["min_start_resid"] > 1e-2 and ls["fallback_rate"] == 1.0
     assert ev["mlp"]["mean_sweeps"] == ev["fp32"]["mean_sweeps"]
     assert ev["const"]["mean_sweeps"] < ev["plain"]["mean_sweeps"]
     net.close()

@@ -204,6 +204,10 @@ def test_pack_targets_bit_exact():
         got = tm.bf16_value(T[c])
         assert np.array_equal(got, want), c
     assert np.all(tm.bf16_value(T[0])[5 * n:6 * n][[3, 7]] == [5.0, -5.0])
+    # the same entries with the signs as given
+    T1 = jacobi.jac_mlp_pack_targets(dev(V), canonical=False).cpu().numpy()
+    for c in range(count):
+        assert np.array_equal(tm.bf16_value(T1[c]), ref.bf16(V[c].T.ravel())), c
 
 
 def test_save_load_roundtrip_and_shape_check():
