@@ -50,7 +50,7 @@ typedef enum {
  * LAPACK-style tridiagonal FP32 eigensolver there, Section 6 setup, and needs
  * only its backward stability, Lemma symeig). */
 typedef enum {
-  JAC_STAGE1_AUTO = 0,     /* tridiagonal for 16 <= n <= 2048, else Jacobi */
+  JAC_STAGE1_AUTO = 0,     /* tridiagonal for 16 <= n <= 4096, else Jacobi */
   JAC_STAGE1_JACOBI = 1,   /* FP32 cyclic Jacobi (the same sweep kernels in float), stopped at
                               fp32_tol ||A||_F: a truncated start (default fp32_tol 1e-4) */
   JAC_STAGE1_TRIDIAG = 2   /* FP32 Householder tridiagonalization, FP64 bisection and
@@ -64,7 +64,7 @@ typedef enum {
  * (n x n); the SVD B = U_B S V^T by the same method; U = Q_A U_B.  The sweeps
  * then work on n x n columns instead of m x n.  Needs m <= 8192 (block MGS). */
 typedef enum {
-  JAC_SVD_QR_AUTO = 0,  /* QR first when m >= 8 n and m <= 8192 */
+  JAC_SVD_QR_AUTO = 0,  /* QR first when m >= 8 n, n >= 512 and m <= 8192 */
   JAC_SVD_QR_OFF = 1,
   JAC_SVD_QR_ON = 2
 } jac_svd_qr_t;
@@ -189,7 +189,7 @@ int syev_jacobi_warm(const double* A, int n, int lda, const double* Q0, int ldq,
  * A: m x n (lda >= m), read only.  S: n singular values, descending.
  * U: m x n (ldu >= m), u_j = c_j / s_j.  V: n x n (ldv >= n).
  * sweeps_out (host, may be NULL).  Takes the QR-first form (jac_svd_qr_t) when
- * m >= 8 n and m <= 8192.  The preconditioned SVD needs n <= 8192 (-3). */
+ * m >= 8 n, n >= 512 and m <= 8192.  The preconditioned SVD needs n <= 8192 (-3). */
 int gesvd_jacobi(const double* A, int m, int n, int lda, double* S, double* U, int ldu, double* V, int ldv,
                  double tol, int* sweeps_out);
 

@@ -113,10 +113,13 @@ def test_svd_qr_first(m, n, pre):
 
 
 def test_svd_qr_first_rule_and_limit():
-    A, _ = tm.svd_case(1024, 100, seed=5)
-    _, _, _, st, _ = jacobi.gesvd_jacobi_ex(dev(A))            # m >= 8 n: QR first
+    A, _ = tm.svd_case(4096, 512, seed=5)
+    _, _, _, st, _ = jacobi.gesvd_jacobi_ex(dev(A))            # m >= 8 n, n >= 512: QR first
     assert st["svd_qr_used"] == 1
-    A, _ = tm.svd_case(1024, 200, seed=6)
+    A, _ = tm.svd_case(1024, 100, seed=5)
+    _, _, _, st, _ = jacobi.gesvd_jacobi_ex(dev(A))            # n < 512: direct
+    assert st["svd_qr_used"] == 0
+    A, _ = tm.svd_case(2048, 512, seed=6)
     _, _, _, st, _ = jacobi.gesvd_jacobi_ex(dev(A))            # m < 8 n: direct
     assert st["svd_qr_used"] == 0
     A, _ = tm.svd_case(8200, 8, seed=7)
