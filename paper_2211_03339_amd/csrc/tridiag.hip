@@ -374,6 +374,8 @@ __device__ __forceinline__ double lane_swap(double x, int lane) {
 
 constexpr int td_pow2(int x) { return x <= 1 ? 1 : 2 * td_pow2((x + 1) / 2); }
 constexpr int td_log2(int x) { return x <= 1 ? 0 : 1 + td_log2(x / 2); }
+// Largest divisor of x that is at most m (the gather's batch: whole batches only).
+constexpr int td_batch(int x, int m) { return m <= 1 ? 1 : (x % m == 0 ? m : td_batch(x, m - 1)); }
 
 template <int LVL, int NP, typename T>
 __device__ __forceinline__ void td_halve(T (&w)[NP], int lane) {
@@ -566,29 +568,35 @@ __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ 
                            __HIP_MEMORY_SCOPE_AGENT);
     }
     if (t == 0) __hip_atomic_store(a.hb + wg, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // (2) gather p(k+1:) and row k+1: every load issued before any tag is tested
-    unsigned long long xp[kCols], xr[kCols];
-#pragma unroll
-    for (int q = 0; q < kCols; ++q) {
-      const int j = q * kThr + t;
-      if (j > k && j < n) {
-        xp[q] = __hip_atomic_load(pb + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        xr[q] = __hip_atomic_load(rb + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
+    // (2) gather p(k+1:) and row k+1 in batches of up to 8 columns (a divisor of kCols): every
+    // load of a batch is issued before any of its tags is tested
     float spart = 0.f;
+    constexpr int kGB = td_batch(kCols, 8);
+    static_assert(kCols % kGB == 0, "whole batches");
 #pragma unroll
-    for (int q = 0; q < kCols; ++q) {
-      const int j = q * kThr + t;
-      if (j > k && j < n) {
-        pq[q] = (unsigned)(xp[q] >> 32) == tag ? __uint_as_float((unsigned)xp[q]) : td_wait(pb, j, tag, a.abort, bad, 0);
-        rq[q] = (unsigned)(xr[q] >> 32) == tag ? __uint_as_float((unsigned)xr[q]) : td_wait(rb, j, tag, a.abort, bad, 1);
-      } else {
-        pq[q] = 0.f;
-        rq[q] = 0.f;
+    for (int q0 = 0; q0 < kCols; q0 += kGB) {
+      unsigned long long xp[kGB], xr[kGB];
+#pragma unroll
+      for (int u = 0; u < kGB; ++u) {
+        const int j = (q0 + u) * kThr + t;
+        if (j > k && j < n) {
+          xp[u] = __hip_atomic_load(pb + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          xr[u] = __hip_atomic_load(rb + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
       }
-      pL[q * kThr + t] = pq[q];
-      spart = fmaf(pq[q], vq[q], spart);
+#pragma unroll
+      for (int u = 0; u < kGB; ++u) {
+        const int q = q0 + u, j = q * kThr + t;
+        if (j > k && j < n) {
+          pq[q] = (unsigned)(xp[u] >> 32) == tag ? __uint_as_float((unsigned)xp[u]) : td_wait(pb, j, tag, a.abort, bad, 0);
+          rq[q] = (unsigned)(xr[u] >> 32) == tag ? __uint_as_float((unsigned)xr[u]) : td_wait(rb, j, tag, a.abort, bad, 1);
+        } else {
+          pq[q] = 0.f;
+          rq[q] = 0.f;
+        }
+        pL[q * kThr + t] = pq[q];
+        spart = fmaf(pq[q], vq[q], spart);
+      }
     }
     if (t < G) td_wait_hb(a.hb + t, tag, a.abort, bad);
     if (bad) bad_any[par] = 1;
@@ -1085,10 +1093,15 @@ static int td_reduce(const TA* A, int n, int lda, TdWork& k, hipStream_t s) {
   a.Ut = k.Ut;
   a.ldut = k.nbp;
   a.abort = k.abort;
+  // One 256-thread workgroup per CU (one wave per SIMD) leaves each wave the whole register file
+  // (VGPRs and AGPRs): the rows stay in FP64 up to n = 2048 and in FP32 above, where a thread holds
+  // up to 16 x 16 entries.  512-thread workgroups (two waves per SIMD, half the registers each)
+  // spill at n = 4096 and are slower at n <= 2048.
   int rc;
   if (n <= 1024) rc = td_launch_reg<TA, 256, 4, 4, double>(A, lda, a, s);
   else if (n <= 2048) rc = td_launch_reg<TA, 256, 8, 8, double>(A, lda, a, s);
-  else if (n <= 4096) rc = td_launch_reg<TA, 512, 16, 8, float>(A, lda, a, s);
+  else if (n <= 3072) rc = td_launch_reg<TA, 256, 12, 12, float>(A, lda, a, s);
+  else if (n <= 4096) rc = td_launch_reg<TA, 256, 16, 16, float>(A, lda, a, s);
   else return td_launch<TA, false, kTdGlbRows>(A, lda, a, s);   // writes Ut itself
   if (rc) return rc;
   // Ut = U^T for the back-transformation's untransposed products

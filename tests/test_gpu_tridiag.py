@@ -144,7 +144,7 @@ def test_backtransform_matches_oracle(n):
 
 @pytest.mark.parametrize("n,kind", [(16, "uniform"), (100, "geometric"), (257, "clusters"),
                                     (1024, "uniform"), (1024, "geometric"), (1024, "clusters"),
-                                    (2048, "clusters"), (4096, "uniform")])
+                                    (2048, "clusters"), (2500, "geometric"), (4096, "uniform")])
 def test_tridiag_stage_start_bound(n, kind):
     """The whole step: Theorem evd-ubd with the proxy bd = n ||A||_2 upsilon for the start."""
     print(f"[tridiag stage] n={n} {kind}", flush=True)
