@@ -455,17 +455,23 @@ __device__ __forceinline__ double td_block_sum_d(double x, double* lds2, int& pa
 
 // ---- the reduction with the working rows in registers (n <= kCols * kThr, n <= kRows * G) -------
 // Thread t holds column j = q kThr + t (q < kCols) of each own row and of v, p and the published
-// row; LDS copies of v and p serve the few entries other threads need (v(i), w(i) of the own rows,
-// p(k+1)).  Per column: the owner of row k+1 publishes it, one workgroup sum gives the own entries
-// of p, the gather brings p and the row, one sum gives p^T v, the rank-2 update runs in registers,
-// and one sum gives the norm of the next reflector's vector.
+// row; LDS copies of v and p (two of each, by column parity) serve the few entries other threads
+// need (v(i), w(i) of the own rows, p(k+1)).
+// The rank-2 update of column k is applied one column late, off the dependency chain: the rows
+// enter column k + 1 as B_k (updated through column k - 1) and its product is formed as
+//   B_(k+1) u_(k+1) = B_k u_(k+1) - v_k (w_k^T u_(k+1)) - w_k (v_k^T u_(k+1)),
+// the two scalars coming out of the workgroup sum that already yields the new reflector's norm.
+// Per column: the owner of row k+1 publishes it (the pending update applied on the fly), one
+// workgroup sum gives the own entries of p, which are published; the pending rank-2 update of the
+// own rows then runs while the other workgroups publish; the gather brings p and the row, one sum
+// gives p^T v, and one sum gives the norm of the next reflector's vector and the two scalars.
 template <typename TA, int kThr, int kRows, int kCols, typename TS>
 __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ A, int lda, TdArgs a) {
   constexpr int kW = kThr / 64;
-  __shared__ float vL[kCols * kThr];
-  __shared__ float pL[kCols * kThr];
+  __shared__ float vL[2][kCols * kThr];
+  __shared__ float pL[2][kCols * kThr];
   __shared__ TS redf[2 * kW * 16];
-  __shared__ double redd[2 * kW];
+  __shared__ double redd[2 * kW * 16];
   __shared__ float bc[2];
   __shared__ int bad_any[2];
   const int n = a.n, G = a.G, wg = blockIdx.x, t = threadIdx.x;
@@ -473,6 +479,7 @@ __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ 
   int fpar = 0, dpar = 0;
   TS R[kRows][kCols];
   float vq[kCols], pq[kCols], rq[kCols];
+  float vp[kCols], wp[kCols];   // v and w of the pending update (column k - 1), own columns
 #pragma unroll
   for (int r = 0; r < kRows; ++r) {
     const int i = wg + r * G;
@@ -486,20 +493,33 @@ __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ 
   for (int q = 0; q < kCols; ++q) {
     const int j = q * kThr + t;
     rq[q] = j < n ? (float)A[j] : 0.f;
+    vp[q] = 0.f;
+    wp[q] = 0.f;
   }
   if (t < 2) bad_any[t] = 0;
-  // reflector of row k (entries of rq at j >= k+1): vq, vL, tau, beta; uniform results
-  float tauk = 0.f, beta = 0.f;
-  auto reflect = [&](int k) {
-    double part = 0.0;
+  // reflector of row k (entries of rq at j >= k+1): vq, vL[k & 1], tau, beta; with corr, also
+  // al_w = w^T u_k and al_v = v^T u_k for the v = vq, w = pq - cw vq of column k - 1 (read before vq
+  // is overwritten; their entries k+1 come from the LDS copies of column k - 1); uniform results
+  float tauk = 0.f, beta = 0.f, cp = 0.f;
+  double al_w = 0.0, al_v = 0.0;
+  auto reflect = [&](int k, bool corr, float cw) {
+    double part[3] = {0.0, 0.0, 0.0}, tot3[3];
 #pragma unroll
     for (int q = 0; q < kCols; ++q) {
       const int j = q * kThr + t;
-      if (j >= k + 2 && j < n) part += (double)rq[q] * (double)rq[q];
+      if (j >= k + 2 && j < n) {
+        const double x = (double)rq[q];
+        part[0] += x * x;
+        if (corr) {
+          part[1] += (double)(pq[q] - cw * vq[q]) * x;
+          part[2] += (double)vq[q] * x;
+        }
+      }
       if (j == k + 1) bc[dpar] = rq[q];
     }
     const int slot = dpar;
-    const double tail = td_block_sum_d<kThr>(part, redd, dpar);
+    td_block_sum<3, kThr, double>(part, redd, dpar, tot3);
+    const double tail = tot3[0];
     const float alpha = bc[slot];
     float scal = 0.f;
     if (tail == 0.0) {
@@ -513,11 +533,20 @@ __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ 
       beta = (float)b;
       scal = (float)(1.0 / (al - b));
     }
+    if (corr) {   // u_k = e_(k+1) + scal x(k+2:)
+      const int pk = (k - 1) & 1;
+      const float v1 = vL[pk][k + 1];
+      al_v = (double)v1 + (double)scal * tot3[2];
+      al_w = (double)(pL[pk][k + 1] - cw * v1) + (double)scal * tot3[1];
+    } else {
+      al_v = 0.0;
+      al_w = 0.0;
+    }
 #pragma unroll
     for (int q = 0; q < kCols; ++q) {
       const int j = q * kThr + t;
       vq[q] = j == k + 1 ? 1.f : (j > k + 1 && j < n ? rq[q] * scal : 0.f);
-      vL[q * kThr + t] = vq[q];
+      vL[k & 1][q * kThr + t] = vq[q];
     }
     if (wg == k % G) {   // the write-out rotates over the workgroups (none lags behind the others)
       if (t == 0) { a.e[k] = beta; a.tau[k] = tauk; }
@@ -530,28 +559,34 @@ __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ 
       }
     }
   };
-  reflect(0);
+  reflect(0, false, 0.f);
   bool bad = false;
   for (int k = 0; k + 2 < n; ++k) {
     const unsigned tag = (unsigned)k + 1u;
-    const int par = k & 1;
+    const int par = k & 1, pp = par ^ 1;   // LDS copies: column k, column k - 1
     unsigned long long* pb = a.pbuf + (size_t)par * n;
     unsigned long long* rb = a.rbuf + (size_t)par * n;
-    // the owner of row k+1 publishes it (its rows are current through column k - 1)
+    // the owner of row k+1 publishes it, current through column k - 1 (the pending update of
+    // column k - 1 applied on the fly; for k = 0 vp = wp = 0)
     if ((k + 1) % G == wg) {
       const int r1 = (k + 1 - wg) / G;
+      const float vi = k > 0 ? vL[pp][k + 1] : 0.f;
+      const float wi = k > 0 ? pL[pp][k + 1] - cp * vi : 0.f;
 #pragma unroll
       for (int r = 0; r < kRows; ++r)
         if (r == r1) {
 #pragma unroll
           for (int q = 0; q < kCols; ++q) {
             const int j = q * kThr + t;
-            if (j > k && j < n)
-              __hip_atomic_store(rb + j, td_pack(tag, (float)R[r][q]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (j > k && j < n) {
+              const TS x = R[r][q] - ((TS)vi * (TS)wp[q] + (TS)wi * (TS)vp[q]);
+              __hip_atomic_store(rb + j, td_pack(tag, (float)x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
           }
         }
     }
-    // (1) p(i) = tau B(i, :) v for the own rows (v is zero at j <= k)
+    // (1) p(i) = tau B_k(i, :) u_k for the own rows i > k, from the rows B_(k-1) and the pending
+    // update's scalars (u_k is zero at j <= k)
     TS acc[kRows], tot[kRows];
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
@@ -563,11 +598,28 @@ __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ 
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
       const int i = wg + r * G;
-      if (t == r && r < nr && i > k)
-        __hip_atomic_store(pb + i, td_pack(tag, (float)((TS)tauk * tot[r])), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+      if (t == r && r < nr && i > k) {
+        const float vi = k > 0 ? vL[pp][i] : 0.f;
+        const float wi = k > 0 ? pL[pp][i] - cp * vi : 0.f;
+        const TS pi = tot[r] - ((TS)vi * (TS)al_w + (TS)wi * (TS)al_v);
+        __hip_atomic_store(pb + i, td_pack(tag, (float)((TS)tauk * pi)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     if (t == 0) __hip_atomic_store(a.hb + wg, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // (1b) the pending update of column k - 1 on the own rows i > k, while the others publish:
+    // B(i, j) -= v(i) w(j) + w(i) v(j)
+    if (k > 0) {
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) {
+        const int i = wg + r * G;
+        if (r < nr && i > k) {
+          const float vi = vL[pp][i], wi = pL[pp][i] - cp * vL[pp][i];
+#pragma unroll
+          for (int q = 0; q < kCols; ++q)   // FP32 operands: in FP64 storage the products are exact
+            R[r][q] = R[r][q] - ((TS)vi * (TS)wp[q] + (TS)wi * (TS)vp[q]);
+        }
+      }
+    }
     // (2) gather p(k+1:) and row k+1 in batches of up to 8 columns (a divisor of kCols): every
     // load of a batch is issued before any of its tags is tested
     float spart = 0.f;
@@ -594,7 +646,7 @@ __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ 
           pq[q] = 0.f;
           rq[q] = 0.f;
         }
-        pL[q * kThr + t] = pq[q];
+        pL[par][q * kThr + t] = pq[q];
         spart = fmaf(pq[q], vq[q], spart);
       }
     }
@@ -606,26 +658,20 @@ __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ 
     if (bad_any[par]) break;
     if (t == 0) bad_any[par ^ 1] = 0;
     const float c = (float)(TS(0.5f * tauk) * st[0]);
-    // (4) own rows i > k:  B(i, j) -= v(i) w(j) + w(i) v(j)
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-      const int i = wg + r * G;
-      if (r < nr && i > k) {
-        const float vi = vL[i], wi = pL[i] - c * vL[i];
-#pragma unroll
-        for (int q = 0; q < kCols; ++q) {
-          const float wj = pq[q] - c * vq[q];
-          // FP32 operands; in FP64 storage their products are exact and the update rounds once
-          R[r][q] = R[r][q] - ((TS)vi * (TS)wj + (TS)wi * (TS)vq[q]);
-        }
-      }
-    }
-    // (5) row k+1 of the updated matrix (v(k+1) = 1), then its reflector
-    const float wk1 = pL[k + 1] - c;
+    // (4) row k+1 of the updated matrix (v(k+1) = 1), then its reflector; column k's update
+    // becomes the pending one
+    const float wk1 = pL[par][k + 1] - c;
 #pragma unroll
     for (int q = 0; q < kCols; ++q) rq[q] = rq[q] - ((pq[q] - c * vq[q]) + wk1 * vq[q]);
     if (k + 3 < n) {
-      reflect(k + 1);
+      reflect(k + 1, true, c);
+#pragma unroll
+      for (int q = 0; q < kCols; ++q) {   // (vq was overwritten; its old values are in the LDS copy)
+        const float v = vL[par][q * kThr + t];
+        vp[q] = v;
+        wp[q] = pq[q] - c * v;
+      }
+      cp = c;
     } else {
       if (wg == (n - 2) % G) {
 #pragma unroll
@@ -635,13 +681,16 @@ __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ 
           if (j == n - 1) a.e[n - 2] = rq[q];
         }
       }
-      if ((n - 1) % G == wg) {
+      if ((n - 1) % G == wg) {   // entry (n-1, n-1): rows through column n - 4, then column n - 3's update
         const int r1 = (n - 1 - wg) / G;
 #pragma unroll
         for (int r = 0; r < kRows; ++r)
 #pragma unroll
           for (int q = 0; q < kCols; ++q)
-            if (r == r1 && q * kThr + t == n - 1) a.d[n - 1] = (float)R[r][q];
+            if (r == r1 && q * kThr + t == n - 1) {
+              const float w = pq[q] - c * vq[q];
+              a.d[n - 1] = (float)(R[r][q] - ((TS)vq[q] * (TS)w + (TS)w * (TS)vq[q]));
+            }
       }
     }
   }
@@ -776,9 +825,21 @@ __global__ __launch_bounds__(kBisThreads) void tri_bisect_kernel(const double* _
 // z(i) = -e(i) z(i+1) / dp(i) above, z(i) = -e(i-1) z(i-1) / dm(i) below; then z / ||z||.
 // Scratch dp, dm: n x nc each (entry i of eigenvector c at i * nc + c), read back in prefetched
 // chunks of kPre entries so that their loads do not sit in the recurrence's dependency chain;
-// d and e come from an LDS copy.  Y column c0 + c receives z.
+// d and e come from an LDS copy, also in chunks.  The pivot recurrences divide through
+// td_rcp; the outward solves multiply z by the ratio -e / pivot, formed off the chain.
+// Y column c0 + c receives z.
 constexpr int kVecThreads = 64;
 constexpr int kPre = 32;
+
+// 1 / x for a normal nonzero x: the hardware estimate refined by two Newton steps
+// r <- r + r (1 - x r), each of which squares the relative error.
+__device__ __forceinline__ double td_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double h = fma(-x, r, 1.0);
+  r = fma(r, h, r);
+  h = fma(-x, r, 1.0);
+  return fma(r, h, r);
+}
 
 template <typename TY>
 __global__ __launch_bounds__(kVecThreads) void tri_vectors_kernel(const double* __restrict__ d,
@@ -788,8 +849,8 @@ __global__ __launch_bounds__(kVecThreads) void tri_vectors_kernel(const double* 
                                                                  double* __restrict__ dp, double* __restrict__ dm,
                                                                  TY* __restrict__ Y, int ldy) {
   extern __shared__ double vec_smem[];
-  double* sd = vec_smem;
-  double* se = vec_smem + n;
+  double* sd = vec_smem;        // d(i)
+  double* se = vec_smem + n;    // e(i) (zero at i = n - 1)
   for (int i = threadIdx.x; i < n; i += kVecThreads) {
     sd[i] = d[i];
     se[i] = i + 1 < n ? e[i] : 0.0;
@@ -798,14 +859,29 @@ __global__ __launch_bounds__(kVecThreads) void tri_vectors_kernel(const double* 
   const int c = blockIdx.x * kVecThreads + threadIdx.x;
   if (c >= nc) return;
   const double lam = w[c0 + c];
-  const double pivmin = bnd[2];
+  // smallest pivot magnitude 2^-1020 max(1, max e^2) (4 bnd[2] when max e^2 >= 1): pivots stay
+  // normal, so td_rcp is finite, and e^2 / pivot stays below 2^1020, so no pivot overflows
+  const double pivmin = fmax(4.0 * bnd[2], 0x1p-1020);
   double q = sd[0] - lam;
   if (fabs(q) < pivmin) q = -pivmin;
   dp[c] = q;
-  for (int i = 1; i < n; ++i) {
-    q = (sd[i] - lam) - se[i - 1] * se[i - 1] / q;
-    if (fabs(q) < pivmin) q = -pivmin;
-    dp[(size_t)i * nc + c] = q;
+  for (int lo = 1; lo < n; lo += kPre) {
+    double a[kPre], b[kPre];   // d(i) - lambda, e(i-1)^2
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int i = lo + u < n ? lo + u : n - 1;
+      a[u] = sd[i] - lam;
+      b[u] = se[i - 1] * se[i - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int i = lo + u;
+      if (i < n) {
+        q = fma(-b[u], td_rcp(q), a[u]);
+        if (fabs(q) < pivmin) q = -pivmin;
+        dp[(size_t)i * nc + c] = q;
+      }
+    }
   }
   double qm = sd[n - 1] - lam;
   if (fabs(qm) < pivmin) qm = -pivmin;
@@ -813,17 +889,22 @@ __global__ __launch_bounds__(kVecThreads) void tri_vectors_kernel(const double* 
   int r = n - 1;
   double best = fabs(q);   // g(n-1) = dp(n-1)
   for (int hi = n - 2; hi >= 0; hi -= kPre) {
-    double pre[kPre];
+    double pre[kPre], a[kPre], b[kPre];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) pre[u] = hi - u >= 0 ? dp[(size_t)(hi - u) * nc + c] : 0.0;
+    for (int u = 0; u < kPre; ++u) {
+      const int i = hi - u >= 0 ? hi - u : 0;
+      pre[u] = hi - u >= 0 ? dp[(size_t)i * nc + c] : 0.0;
+      a[u] = sd[i] - lam;
+      b[u] = se[i] * se[i];
+    }
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
       const int i = hi - u;
       if (i >= 0) {
-        qm = (sd[i] - lam) - se[i] * se[i] / qm;
+        qm = fma(-b[u], td_rcp(qm), a[u]);
         if (fabs(qm) < pivmin) qm = -pivmin;
         dm[(size_t)i * nc + c] = qm;
-        const double g = fabs(pre[u] + qm - (sd[i] - lam));
+        const double g = fabs(pre[u] + qm - a[u]);
         if (g < best) { best = g; r = i; }
       }
     }
@@ -831,31 +912,37 @@ __global__ __launch_bounds__(kVecThreads) void tri_vectors_kernel(const double* 
   // outward solve; z(i) overwrites the pivot it consumed
   double nrm2 = 1.0, z = 1.0;
   for (int hi = r - 1; hi >= 0; hi -= kPre) {
-    double pre[kPre];
+    double ratio[kPre];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) pre[u] = hi - u >= 0 ? dp[(size_t)(hi - u) * nc + c] : 1.0;
+    for (int u = 0; u < kPre; ++u) {
+      const int i = hi - u >= 0 ? hi - u : 0;
+      ratio[u] = hi - u >= 0 ? -se[i] * td_rcp(dp[(size_t)i * nc + c]) : 0.0;
+    }
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
       const int i = hi - u;
       if (i >= 0) {
-        z = -se[i] * z / pre[u];
+        z *= ratio[u];
         dp[(size_t)i * nc + c] = z;
-        nrm2 += z * z;
+        nrm2 = fma(z, z, nrm2);
       }
     }
   }
   z = 1.0;
   for (int lo = r + 1; lo < n; lo += kPre) {
-    double pre[kPre];
+    double ratio[kPre];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) pre[u] = lo + u < n ? dm[(size_t)(lo + u) * nc + c] : 1.0;
+    for (int u = 0; u < kPre; ++u) {
+      const int i = lo + u < n ? lo + u : n - 1;
+      ratio[u] = lo + u < n ? -se[i - 1] * td_rcp(dm[(size_t)i * nc + c]) : 0.0;
+    }
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
       const int i = lo + u;
       if (i < n) {
-        z = -se[i - 1] * z / pre[u];
+        z *= ratio[u];
         dm[(size_t)i * nc + c] = z;
-        nrm2 += z * z;
+        nrm2 = fma(z, z, nrm2);
       }
     }
   }
