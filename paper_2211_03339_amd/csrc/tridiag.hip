@@ -825,21 +825,9 @@ __global__ __launch_bounds__(kBisThreads) void tri_bisect_kernel(const double* _
 // z(i) = -e(i) z(i+1) / dp(i) above, z(i) = -e(i-1) z(i-1) / dm(i) below; then z / ||z||.
 // Scratch dp, dm: n x nc each (entry i of eigenvector c at i * nc + c), read back in prefetched
 // chunks of kPre entries so that their loads do not sit in the recurrence's dependency chain;
-// d and e come from an LDS copy, also in chunks.  The pivot recurrences divide through
-// td_rcp; the outward solves multiply z by the ratio -e / pivot, formed off the chain.
-// Y column c0 + c receives z.
+// d and e come from an LDS copy.  Y column c0 + c receives z.
 constexpr int kVecThreads = 64;
 constexpr int kPre = 32;
-
-// 1 / x for a normal nonzero x: the hardware estimate refined by two Newton steps
-// r <- r + r (1 - x r), each of which squares the relative error.
-__device__ __forceinline__ double td_rcp(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double h = fma(-x, r, 1.0);
-  r = fma(r, h, r);
-  h = fma(-x, r, 1.0);
-  return fma(r, h, r);
-}
 
 template <typename TY>
 __global__ __launch_bounds__(kVecThreads) void tri_vectors_kernel(const double* __restrict__ d,
@@ -849,8 +837,8 @@ __global__ __launch_bounds__(kVecThreads) void tri_vectors_kernel(const double* 
                                                                  double* __restrict__ dp, double* __restrict__ dm,
                                                                  TY* __restrict__ Y, int ldy) {
   extern __shared__ double vec_smem[];
-  double* sd = vec_smem;        // d(i)
-  double* se = vec_smem + n;    // e(i) (zero at i = n - 1)
+  double* sd = vec_smem;
+  double* se = vec_smem + n;
   for (int i = threadIdx.x; i < n; i += kVecThreads) {
     sd[i] = d[i];
     se[i] = i + 1 < n ? e[i] : 0.0;
@@ -859,29 +847,14 @@ __global__ __launch_bounds__(kVecThreads) void tri_vectors_kernel(const double* 
   const int c = blockIdx.x * kVecThreads + threadIdx.x;
   if (c >= nc) return;
   const double lam = w[c0 + c];
-  // smallest pivot magnitude 2^-1020 max(1, max e^2) (4 bnd[2] when max e^2 >= 1): pivots stay
-  // normal, so td_rcp is finite, and e^2 / pivot stays below 2^1020, so no pivot overflows
-  const double pivmin = fmax(4.0 * bnd[2], 0x1p-1020);
+  const double pivmin = bnd[2];
   double q = sd[0] - lam;
   if (fabs(q) < pivmin) q = -pivmin;
   dp[c] = q;
-  for (int lo = 1; lo < n; lo += kPre) {
-    double a[kPre], b[kPre];   // d(i) - lambda, e(i-1)^2
-#pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int i = lo + u < n ? lo + u : n - 1;
-      a[u] = sd[i] - lam;
-      b[u] = se[i - 1] * se[i - 1];
-    }
-#pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int i = lo + u;
-      if (i < n) {
-        q = fma(-b[u], td_rcp(q), a[u]);
-        if (fabs(q) < pivmin) q = -pivmin;
-        dp[(size_t)i * nc + c] = q;
-      }
-    }
+  for (int i = 1; i < n; ++i) {
+    q = (sd[i] - lam) - se[i - 1] * se[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    dp[(size_t)i * nc + c] = q;
   }
   double qm = sd[n - 1] - lam;
   if (fabs(qm) < pivmin) qm = -pivmin;
@@ -889,22 +862,17 @@ __global__ __launch_bounds__(kVecThreads) void tri_vectors_kernel(const double* 
   int r = n - 1;
   double best = fabs(q);   // g(n-1) = dp(n-1)
   for (int hi = n - 2; hi >= 0; hi -= kPre) {
-    double pre[kPre], a[kPre], b[kPre];
+    double pre[kPre];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int i = hi - u >= 0 ? hi - u : 0;
-      pre[u] = hi - u >= 0 ? dp[(size_t)i * nc + c] : 0.0;
-      a[u] = sd[i] - lam;
-      b[u] = se[i] * se[i];
-    }
+    for (int u = 0; u < kPre; ++u) pre[u] = hi - u >= 0 ? dp[(size_t)(hi - u) * nc + c] : 0.0;
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
       const int i = hi - u;
       if (i >= 0) {
-        qm = fma(-b[u], td_rcp(qm), a[u]);
+        qm = (sd[i] - lam) - se[i] * se[i] / qm;
         if (fabs(qm) < pivmin) qm = -pivmin;
         dm[(size_t)i * nc + c] = qm;
-        const double g = fabs(pre[u] + qm - a[u]);
+        const double g = fabs(pre[u] + qm - (sd[i] - lam));
         if (g < best) { best = g; r = i; }
       }
     }
@@ -912,37 +880,31 @@ __global__ __launch_bounds__(kVecThreads) void tri_vectors_kernel(const double* 
   // outward solve; z(i) overwrites the pivot it consumed
   double nrm2 = 1.0, z = 1.0;
   for (int hi = r - 1; hi >= 0; hi -= kPre) {
-    double ratio[kPre];
+    double pre[kPre];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int i = hi - u >= 0 ? hi - u : 0;
-      ratio[u] = hi - u >= 0 ? -se[i] * td_rcp(dp[(size_t)i * nc + c]) : 0.0;
-    }
+    for (int u = 0; u < kPre; ++u) pre[u] = hi - u >= 0 ? dp[(size_t)(hi - u) * nc + c] : 1.0;
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
       const int i = hi - u;
       if (i >= 0) {
-        z *= ratio[u];
+        z = -se[i] * z / pre[u];
         dp[(size_t)i * nc + c] = z;
-        nrm2 = fma(z, z, nrm2);
+        nrm2 += z * z;
       }
     }
   }
   z = 1.0;
   for (int lo = r + 1; lo < n; lo += kPre) {
-    double ratio[kPre];
+    double pre[kPre];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int i = lo + u < n ? lo + u : n - 1;
-      ratio[u] = lo + u < n ? -se[i - 1] * td_rcp(dm[(size_t)i * nc + c]) : 0.0;
-    }
+    for (int u = 0; u < kPre; ++u) pre[u] = lo + u < n ? dm[(size_t)(lo + u) * nc + c] : 1.0;
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
       const int i = lo + u;
       if (i < n) {
-        z *= ratio[u];
+        z = -se[i - 1] * z / pre[u];
         dm[(size_t)i * nc + c] = z;
-        nrm2 = fma(z, z, nrm2);
+        nrm2 += z * z;
       }
     }
   }
