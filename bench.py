@@ -86,7 +86,7 @@ def roofline_for(cls: str, k: dict, n: int, rotations: int) -> dict:
         flops = 4.0 / 3.0 * n ** 3
         ach = flops / avg_s / 1e12
         return {"bound": "alu", "achieved": round(ach, 4), "peak": PEAK["fp32_valu"], "unit": "TFLOP/s",
-                "frac": round(ach / PEAK["fp32_valu"], 6), "traffic": None, "kernel": "sytrd_reg_kernel",
+                "frac": round(ach / PEAK["fp32_valu"], 6), "traffic": measured_traffic(cls), "kernel": "sytrd_reg_kernel",
                 "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_flops_per_launch": flops,
                 "launches_timed": k["launches"], "per_column_us": round(avg_s * 1e6 / max(n - 2, 1), 3)}
     if cls == "tridiag_rest":

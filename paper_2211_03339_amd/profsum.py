@@ -6,6 +6,10 @@
       the same table from the rocpd database (*_results.db) of a `rocprofv3 --kernel-trace` run.
   python -m paper_2211_03339_amd.profsum traffic FETCH_CSV WRITE_CSV COPY_FETCH_CSV COPY_WRITE_CSV COPY_BYTES
       OUT_JSON SOURCES "COMMANDS"
+  python -m paper_2211_03339_amd.profsum traffic-db FETCH_DB_DIR WRITE_DB_DIR COPY_FETCH_DB_DIR COPY_WRITE_DB_DIR
+      COPY_BYTES OUT_JSON SOURCES "COMMANDS"
+      the same from the rocpd databases of the four `rocprofv3 --pmc` runs (for a run that ends with
+      the profiler's own fault after a cooperative launch, when no CSV is written)
       mean FETCH_SIZE / WRITE_SIZE per dispatch and kernel from two `rocprofv3 --pmc` runs, each
       scaled by bytes / counter of a plain device copy of COPY_BYTES bytes measured with the same
       counter, with the sha256 of each kernel source in SOURCES (comma-separated; bench.py reports
@@ -77,11 +81,26 @@ def _per_kernel(path, counter):
     return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
 
 
-def traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv, copy_bytes, out_json, sources, command):
-    fetch, nf = _per_kernel(fetch_csv, "FETCH_SIZE")
-    write, nw = _per_kernel(write_csv, "WRITE_SIZE")
-    cf, _ = _per_kernel(cfetch_csv, "FETCH_SIZE")
-    cw, _ = _per_kernel(cwrite_csv, "WRITE_SIZE")
+def _per_kernel_db(db_dir, counter):
+    """Mean counter value per dispatch and kernel from a rocpd database (counters_collection view:
+    one row per dispatch and counter, the value summed over the counter's instances)."""
+    import glob
+    import sqlite3
+    db = sorted(glob.glob(db_dir.rstrip("/") + "/*.db"))[0]
+    cur = sqlite3.connect(db).cursor()
+    acc = defaultdict(list)
+    for name, value in cur.execute("select kernel_name, value from counters_collection where counter_name = ?",
+                                   (counter,)):
+        acc[_short(name)].append(float(value))
+    return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
+
+
+def traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv, copy_bytes, out_json, sources, command, reader=None):
+    reader = reader or _per_kernel
+    fetch, nf = reader(fetch_csv, "FETCH_SIZE")
+    write, nw = reader(write_csv, "WRITE_SIZE")
+    cf, _ = reader(cfetch_csv, "FETCH_SIZE")
+    cw, _ = reader(cwrite_csv, "WRITE_SIZE")
     # the copy kernel is the one whose mean counter is largest in the copy runs
     ck = max(cf, key=cf.get)
     sf = float(copy_bytes) / (cf[ck] * 1024.0)
@@ -105,5 +124,7 @@ if __name__ == "__main__":
         stats_db(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:10])
+    elif sys.argv[1] == "traffic-db":
+        traffic(*sys.argv[2:10], reader=_per_kernel_db)
     else:
         raise SystemExit(__doc__)
