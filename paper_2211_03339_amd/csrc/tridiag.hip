@@ -650,7 +650,10 @@ __global__ __launch_bounds__(kThr) void sytrd_reg_kernel(const TA* __restrict__ 
         spart = fmaf(pq[q], vq[q], spart);
       }
     }
-    if (t < G) td_wait_hb(a.hb + t, tag, a.abort, bad);
+    // Column k + 1 reuses the buffers of column k - 1 (its parity): every workgroup must have read
+    // them, i.e. published p for column k.  While k + G < n every workgroup owns a row > k, whose
+    // entry of p this gather has just seen, so only the last G columns need the heartbeats.
+    if (k + G >= n && t < G) td_wait_hb(a.hb + t, tag, a.abort, bad);
     if (bad) bad_any[par] = 1;
     // (3) s = p^T v (one workgroup sum), w = p - (tau s / 2) v
     TS sv[1] = {(TS)spart}, st[1];
