@@ -1207,8 +1207,10 @@ static int td_vectors(const double* d, const double* e, int n, const double* w, 
 
 // Step 1d: Y (n x n, ld n) <- H_0 ... H_{n-3} Y, in FP64 on the matrix cores: per block of kBtNb
 // reflectors its Gram Ub^T Ub and triangular factor Tb, then Y -= Ub (Tb (Ub^T Y)).
-static int td_backtransform(const double* U, const double* Ut, int nbp, const float* tau, int n, double* Gb,
-                            double* Tf, double* Wb, double* W2, double* Y, hipStream_t s, bool no_split) {
+// Step 1d, first part: the Gram matrix and triangular factor of every reflector block (they
+// depend on the reflectors only).
+static int td_bt_factors(const double* U, const double* Ut, int nbp, const float* tau, int n, double* Gb,
+                         double* Tf, hipStream_t s, bool no_split) {
   const int nref = n > 2 ? n - 2 : 0;
   if (nref == 0) return 0;
   const int nblk = tcdiv(nref, kBtNb);
@@ -1223,6 +1225,16 @@ static int td_backtransform(const double* U, const double* Ut, int nbp, const fl
   JAC_HIP(hipFuncSetAttribute((const void*)bt_tfactor_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tsh));
   hipLaunchKernelGGL(bt_tfactor_kernel, dim3(nblk), dim3(256), tsh, s, Gb, tau, nref, Tf);
   JAC_CHECK_LAUNCH();
+  return 0;
+}
+
+// Step 1d, second part: Y <- H_0 ... H_(n-3) Y, block by block from the last.
+static int td_bt_apply(const double* U, const double* Ut, int nbp, int n, const double* Tf, double* Wb, double* W2,
+                       double* Y, hipStream_t s, bool no_split) {
+  const int nref = n > 2 ? n - 2 : 0;
+  if (nref == 0) return 0;
+  const int nblk = tcdiv(nref, kBtNb);
+  const int msplit = no_split ? 1 : 0;
   for (int b = nblk - 1; b >= 0; --b) {
     const int k0 = b * kBtNb, r0 = k0 + 1, m = n - r0;
     int e1 = gemm<double>(false, false, kBtNb, n, m, 1.0, Ut + k0 + (size_t)r0 * nbp, nbp, Y + r0, n, 0.0, Wb, kBtNb,
@@ -1238,6 +1250,13 @@ static int td_backtransform(const double* U, const double* Ut, int nbp, const fl
   return 0;
 }
 
+static int td_backtransform(const double* U, const double* Ut, int nbp, const float* tau, int n, double* Gb,
+                            double* Tf, double* Wb, double* W2, double* Y, hipStream_t s, bool no_split) {
+  int e = td_bt_factors(U, Ut, nbp, tau, n, Gb, Tf, s, no_split);
+  if (e) return e;
+  return td_bt_apply(U, Ut, nbp, n, Tf, Wb, W2, Y, s, no_split);
+}
+
 // FP32 eigenvectors of A (n x n, FP64 or FP32, lda) through the tridiagonal route.  Z (FP64,
 // n x n, ldz) receives them in ascending order of the eigenvalues of T, which go to w_out (FP64,
 // may be NULL).  no_split: GEMMs without split-K (nothing allocated).
@@ -1251,11 +1270,46 @@ int eig_tridiag_f32(const TA* A, int n, int lda, double* Z, int ldz, double* w_o
   int e = td_reduce<TA>(A, n, lda, k, s);
   if (e) return e;
   const int ev1 = prof ? prof->mark(s) : -1;
-  e = td_eigvals(k.d, k.e, n, k.bnd, k.w, s);
-  if (e) return e;
-  e = td_vectors<double>(k.d, k.e, n, k.w, k.bnd, k.dp, k.dm, k.nc, k.Y, n, s);
-  if (e) return e;
-  e = td_backtransform(k.U, k.Ut, k.nbp, k.tau, n, k.G, k.Tf, k.Wb, k.W2, k.Y, s, no_split);
+  // The blocks' Gram matrices and triangular factors need only the reflectors: they run on a
+  // second stream while the eigenvalues and eigenvectors of T take the first (the eigenvector
+  // kernel fills few CUs).  Not for the allocation-free form (no_split), which creates nothing.
+  hipStream_t s2 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  auto release = [&]() {
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (s2) (void)hipStreamDestroy(s2);
+    fork = join = nullptr;
+    s2 = nullptr;
+  };
+  auto hip_ok = [](hipError_t r, const char* what) {
+    if (r == hipSuccess) return 0;
+    set_error(std::string(what) + ": " + hipGetErrorString(r));
+    return 4;
+  };
+  if (!no_split && n >= 512) {   // (if the second stream cannot be set up, one stream does it all)
+    if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess)
+      release();
+  }
+  if (s2) {
+    e = hip_ok(hipEventRecord(fork, s), "hipEventRecord");
+    if (!e) e = hip_ok(hipStreamWaitEvent(s2, fork, 0), "hipStreamWaitEvent");
+    if (e) { release(); return e; }
+  }
+  e = td_bt_factors(k.U, k.Ut, k.nbp, k.tau, n, k.G, k.Tf, s2 ? s2 : s, no_split);
+  if (!e && s2) e = hip_ok(hipEventRecord(join, s2), "hipEventRecord");
+  if (!e) e = td_eigvals(k.d, k.e, n, k.bnd, k.w, s);
+  if (!e) e = td_vectors<double>(k.d, k.e, n, k.w, k.bnd, k.dp, k.dm, k.nc, k.Y, n, s);
+  if (!e && s2) e = hip_ok(hipStreamWaitEvent(s, join, 0), "hipStreamWaitEvent");
+  if (e) {
+    if (s2) (void)hipStreamSynchronize(s2);
+    release();
+    return e;
+  }
+  e = td_bt_apply(k.U, k.Ut, k.nbp, n, k.Tf, k.Wb, k.W2, k.Y, s, no_split);
+  release();   // (destroying a stream whose work is queued or waited on is allowed; it completes)
   if (e) return e;
   e = copy_convert<double, double>(k.Y, n, n, n, Z, ldz, s);
   if (e) return e;
