@@ -62,7 +62,7 @@ typedef enum {
  * Algorithm 5.2): A = Q_A B with Q_A (m x n) orthonormal -- two passes of block
  * MGS, so that Q_A is orthonormal to working precision -- and B = Q_A^T A
  * (n x n); the SVD B = U_B S V^T by the same method; U = Q_A U_B.  The sweeps
- * then work on n x n columns instead of m x n.  Needs m <= 8192 (block MGS). */
+ * then work on n x n columns instead of m x n.  Needs m <= 32768 (block MGS). */
 typedef enum {
   JAC_SVD_QR_AUTO = 0,  /* QR first when m >= 8 n, n >= 512 and m <= 8192 */
   JAC_SVD_QR_OFF = 1,
@@ -146,7 +146,7 @@ typedef struct jac_stats {
  * tol: stop when ||off(T)||_F <= tol ||A||_F (tested before each sweep);
  * tol <= 0 selects the paper's 20 * 2^-53.  sweeps_out (host, may be NULL):
  * FP64 sweeps executed.  Preconditioned solves (and custom starts) need
- * n <= 8192, the row limit of step 2's block MGS (-2 otherwise); plain Jacobi
+ * n <= 32768, the row limit of step 2's block MGS (-2 otherwise); plain Jacobi
  * has no such limit. */
 int syev_jacobi(const double* A, int n, int lda, double* W, double* V, double tol, int* sweeps_out);
 
@@ -189,7 +189,7 @@ int syev_jacobi_warm(const double* A, int n, int lda, const double* Q0, int ldq,
  * A: m x n (lda >= m), read only.  S: n singular values, descending.
  * U: m x n (ldu >= m), u_j = c_j / s_j.  V: n x n (ldv >= n).
  * sweeps_out (host, may be NULL).  Takes the QR-first form (jac_svd_qr_t) when
- * m >= 8 n, n >= 512 and m <= 8192.  The preconditioned SVD needs n <= 8192 (-3). */
+ * m >= 8 n, n >= 512 and m <= 8192.  The preconditioned SVD needs n <= 32768 (-3). */
 int gesvd_jacobi(const double* A, int m, int n, int lda, double* S, double* U, int ldu, double* V, int ldv,
                  double tol, int* sweeps_out);
 
@@ -349,7 +349,7 @@ int jac_parallel_steps(double* T, int n, int ldt, double* V, int ldv, int r0, in
  * ordering for ne (even) indices. */
 int jac_round_robin_pairs(int ne, int r, int* p, int* q);
 
-/* FP64 modified Gram-Schmidt, in place: Q (m x n, m >= n, ldq >= m, m <= 8192)
+/* FP64 modified Gram-Schmidt, in place: Q (m x n, m >= n, ldq >= m, m <= 32768)
  * becomes orthonormal with the column order and signs of the input
  * (Algorithm 4.1 step 2).  Returns +3 on a zero column. */
 int jac_mgs(double* Q, int m, int n, int ldq, void* stream);
@@ -359,7 +359,7 @@ int jac_mgs(double* Q, int m, int n, int ldq, void* stream);
  * factor MGS returns; Algorithm 4.1 step 2, Lemma MGS).  When ||Q^T Q - I||_F
  * <= 1e-3 it is evaluated as Q R^{-1} from a second-order series for R (four
  * FP64 GEMMs; error O(||Q^T Q - I||^3)), otherwise by block MGS.  method (host,
- * may be NULL): 1 series, 2 block MGS.  Returns +3 on a zero column. */
+ * may be NULL): 1 series, 2 block MGS.  n <= 32768.  Returns +3 on a zero column. */
 int jac_qr_orth(double* Q, int n, int ldq, int* method, void* stream);
 
 /* T = Q^T A Q (Algorithm 4.1 step 3), FP64: upper triangle computed, mirrored.

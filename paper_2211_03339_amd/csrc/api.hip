@@ -509,7 +509,7 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
   }
   if (n == 0) return 0;
   if (o.precond != JAC_PRECOND_NONE && n > kMgsMaxRows) {
-    set_error("syev_jacobi: preconditioned solves (and custom starts) need n <= 8192 (block MGS of step 2)");
+    set_error("syev_jacobi: preconditioned solves (and custom starts) need n <= 32768 (block MGS of step 2)");
     return -2;
   }
   if (o.precond == JAC_PRECOND_MLP) {
@@ -848,7 +848,7 @@ static int gesvd_impl(const double* A, int m, int n, int lda, double* S, double*
     return -11;
   }
   if (pre != JAC_PRECOND_NONE && n > kMgsMaxRows) {
-    set_error("gesvd_jacobi: the preconditioned SVD needs n <= 8192 (block MGS of step 2)");
+    set_error("gesvd_jacobi: the preconditioned SVD needs n <= 32768 (block MGS of step 2)");
     return -3;
   }
   if (o.block_b != 0) { set_error("gesvd_jacobi_ex: opts.block_b is reserved and must be 0"); return -11; }
@@ -1000,7 +1000,7 @@ static bool svd_qr_first(const jac_opts& o, int m, int n) {
   if (o.svd_qr == JAC_SVD_QR_OFF) return false;
   // measured: 8192 x 512 37.6 vs 41.9 ms direct; at n <= 256 the two MGS passes cost more than
   // the shorter columns save (4096 x 256 13.4 vs 13.2 ms, 2048 x 128 5.0 vs 4.6 ms)
-  return n >= 512 && m >= 8 * n && m <= kMgsMaxRows;
+  return n >= 512 && m >= 8 * n && m <= kMgsFastRows;
 }
 
 // QR-first SVD (m >> n; the remark after Algorithm 5.2): A = Q_A B with Q_A from two passes of
@@ -1010,7 +1010,7 @@ static bool svd_qr_first(const jac_opts& o, int m, int n) {
 // call did, so it gets the same block back and carves only its own front part.
 static int gesvd_qr_first(const double* A, int m, int n, int lda, double* S, double* U, int ldu, double* V, int ldv,
                           double tol, const jac_opts& o, jac_stats* stats, hipStream_t s) {
-  if (m > kMgsMaxRows) { set_error("gesvd_jacobi_ex: the QR-first form needs m <= 8192"); return -2; }
+  if (m > kMgsMaxRows) { set_error("gesvd_jacobi_ex: the QR-first form needs m <= 32768"); return -2; }
   const size_t inner = align_up(gesvd_bytes(n, n, o.precond), 256);
   const size_t outer = 8192 + 2 * align_up((size_t)m * n * 8, 256) + 2 * align_up((size_t)n * n * 8, 256) +
                        align_up(mgs_scratch_elems(m, n) * 8, 256) + align_up((size_t)(n + 64) * 8, 256) +
@@ -1321,7 +1321,7 @@ int jac_mgs(double* Q, int m, int n, int ldq, void* stream) {
   if (m < 0) { set_error("m < 0"); return -2; }
   if (n < 0 || n > m) { set_error("need 0 <= n <= m"); return -3; }
   if (ldq < (m > 1 ? m : 1)) { set_error("ldq < max(1,m)"); return -4; }
-  if (m > 8192) { set_error("m > 8192 is not supported"); return -2; }
+  if (m > kMgsMaxRows) { set_error("m > 32768 is not supported"); return -2; }
   if (n == 0) return 0;
   hipStream_t s = as_stream(stream);
   void* ws = workspace(align_up(mgs_scratch_elems(m, n) * 8, 256) + 4096);
@@ -1342,7 +1342,7 @@ int jac_mgs(double* Q, int m, int n, int ldq, void* stream) {
 int jac_qr_orth(double* Q, int n, int ldq, int* method, void* stream) {
   g_err.clear();
   if (!Q && n > 0) { set_error("Q is NULL"); return -1; }
-  if (n < 0 || n > 8192) { set_error("need 0 <= n <= 8192"); return -2; }
+  if (n < 0 || n > kMgsMaxRows) { set_error("need 0 <= n <= 32768"); return -2; }
   if (ldq < (n > 1 ? n : 1)) { set_error("ldq < max(1,n)"); return -3; }
   if (method) *method = 0;
   if (n == 0) return 0;

@@ -372,8 +372,10 @@ int orth_series_batched(double* Z, int np, int count, double* S1, double* S2, do
                         double* e2_first, hipStream_t s);
 
 // Block modified Gram-Schmidt in place (mgs.hip).  Returns 0 or 3 on breakdown.  The panel kernel
-// holds a panel's rows in registers: at most kMgsMaxRows rows.
-constexpr int kMgsMaxRows = 8192;
+// holds a panel's rows in registers: at most kMgsMaxRows rows (64 per thread, one-column panels
+// above 16384 rows).  kMgsFastRows bounds the automatic QR-first SVD (measured faster only there).
+constexpr int kMgsMaxRows = 32768;
+constexpr int kMgsFastRows = 8192;
 int mgs_f64(double* Q, int m, int n, int ldq, double* scratch, int* flag, hipStream_t s);
 size_t mgs_scratch_elems(int m, int n);
 

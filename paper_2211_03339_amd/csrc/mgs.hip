@@ -324,7 +324,9 @@ static int panel_width(int m) {
   int R = (m + kMT - 1) / kMT;
   if (R <= 4) return 16;
   if (R <= 8) return 8;
-  return 4;
+  if (R <= 16) return 4;
+  if (R <= 32) return 2;
+  return 1;
 }
 
 // nrm0 (n) and the partial W of the projection kernels (per 16-column block and 256-row block).
@@ -334,7 +336,9 @@ static void launch_panel(int R, hipStream_t s, double* Qp, int m, int ldq, int w
   else if (R <= 2) hipLaunchKernelGGL((mgs_panel_kernel<2, 16, FULL>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0, flag);
   else if (R <= 4) hipLaunchKernelGGL((mgs_panel_kernel<4, 16, FULL>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0, flag);
   else if (R <= 8) hipLaunchKernelGGL((mgs_panel_kernel<8, 8, FULL>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0, flag);
-  else hipLaunchKernelGGL((mgs_panel_kernel<16, 4, FULL>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0, flag);
+  else if (R <= 16) hipLaunchKernelGGL((mgs_panel_kernel<16, 4, FULL>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0, flag);
+  else if (R <= 32) hipLaunchKernelGGL((mgs_panel_kernel<32, 2, FULL>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0, flag);
+  else hipLaunchKernelGGL((mgs_panel_kernel<64, 1, FULL>), dim3(1), dim3(kMT), 0, s, Qp, m, ldq, w, nrm0, flag);
 }
 
 size_t mgs_scratch_elems(int m, int n) {
@@ -342,9 +346,9 @@ size_t mgs_scratch_elems(int m, int n) {
 }
 
 int mgs_f64(double* Q, int m, int n, int ldq, double* W, int* flag, hipStream_t s) {
-  static_assert(kMgsMaxRows == 16 * kMT, "the panel kernel's largest register tile");
+  static_assert(kMgsMaxRows == 64 * kMT, "the panel kernel's largest register tile");
   if (m > kMgsMaxRows) {
-    set_error("mgs: more than 8192 rows is not supported");
+    set_error("mgs: more than 32768 rows is not supported");
     return -2;
   }
   const int P = panel_width(m);

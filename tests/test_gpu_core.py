@@ -230,7 +230,8 @@ def test_gemm_f32(shape):
     assert np.abs(C - ref).max() <= 4 * k * 2.0 ** -24 * np.abs(A).max() * np.abs(B).max()
 
 
-@pytest.mark.parametrize("m,n", [(7, 7), (64, 64), (300, 300), (1100, 1000), (2050, 64)])
+@pytest.mark.parametrize("m,n", [(7, 7), (64, 64), (300, 300), (1100, 1000), (2050, 64), (12000, 37),
+                                 (20000, 9)])
 def test_mgs_vs_oracle(m, n):
     """Step 2: GPU block MGS against the oracle's column MGS on a near-orthogonal Z."""
     g = tm.rng(m + n)

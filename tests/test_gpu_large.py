@@ -67,6 +67,21 @@ def test_order_8192_geometric_1e10():
           f"lam_err={le:.2e} ms={st['stage_ms']['total']:.1f}", flush=True)
 
 
+def test_preconditioned_above_8192():
+    """An order above 8192 (the old row limit of step 2's block MGS): the Jacobi start, the series
+    QR factor and the FP64 sweeps."""
+    n = 8320
+    print(f"[large] n={n} uniform: generating", flush=True)
+    A, lam = tm.sym_matrix(n, "uniform", 5_100_000 + n)
+    Ad = torch.from_numpy(A).cuda()
+    del A
+    print(f"[large] n={n} solving", flush=True)
+    W, V, st, _ = jacobi.syev_jacobi_ex(Ad, precond="fp32")
+    res, orth, le = check_eig_dev(Ad, W, V, lam, raw_orth=False)
+    print(f"  sweeps={st['sweeps']} fp32_sweeps={st['fp32_sweeps']} res={res:.2e} orth={orth:.2e} "
+          f"lam_err={le:.2e} ms={st['stage_ms']['total']:.1f}", flush=True)
+
+
 def test_svd_8192_by_2048():
     print("[large] SVD 8192 x 2048: generating", flush=True)
     A, sig = tm.svd_case(8192, 2048)

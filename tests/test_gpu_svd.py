@@ -122,9 +122,15 @@ def test_svd_qr_first_rule_and_limit():
     A, _ = tm.svd_case(2048, 512, seed=6)
     _, _, _, st, _ = jacobi.gesvd_jacobi_ex(dev(A))            # m < 8 n: direct
     assert st["svd_qr_used"] == 0
-    A, _ = tm.svd_case(8200, 8, seed=7)
-    _, _, _, st, _ = jacobi.gesvd_jacobi_ex(dev(A))            # beyond the MGS rows: direct
+    A, sig = tm.svd_case(8200, 8, seed=7)
+    _, _, _, st, _ = jacobi.gesvd_jacobi_ex(dev(A))            # beyond the measured rows: direct
     assert st["svd_qr_used"] == 0
+    S, U, V, st, _ = jacobi.gesvd_jacobi_ex(dev(A), svd_qr="on")   # forced: two-column MGS panels
+    assert st["svd_qr_used"] == 1
+    assert np.abs(host(S) - np.sort(sig)[::-1]).max() <= 1e-13 * sig.max()
+    U = host(U)
+    assert np.linalg.norm(U.T @ U - np.eye(8)) <= 1e-13
+    A, _ = tm.svd_case(32769, 8, seed=8)
     with pytest.raises(jacobi.JacobiError) as e:
-        jacobi.gesvd_jacobi_ex(dev(A), svd_qr="on")
+        jacobi.gesvd_jacobi_ex(dev(A), svd_qr="on")            # beyond the MGS rows
     assert e.value.code == -2
