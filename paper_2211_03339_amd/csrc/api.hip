@@ -439,7 +439,8 @@ static int fp32_stage(const void* A, bool a_dbl, int n, int lda, double nrmA, do
 
 // T = Q^T A Q: Q^T is formed explicitly in T (a coalesced tiled transpose), then W = Q^T A and
 // T = W Q as untransposed GEMMs (a transposed operand streams 128-byte pieces of columns and
-// runs an order of magnitude slower), then T is mirrored from its upper triangle.
+// runs an order of magnitude slower), then T is mirrored from its upper triangle, the only part
+// the second product forms.
 __global__ void mirror_upper_kernel(double* T, int n, int ldt) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y;
@@ -470,7 +471,8 @@ static int similarity(const double* A, int n, int lda, const double* Q, int ldq,
   const int ms = no_split ? 1 : 0;
   int e = gemm<double>(false, false, n, n, n, 1.0, T, ldt, A, lda, 0.0, W, n, s, ms);
   if (e) return e;
-  e = gemm<double>(false, false, n, n, n, 1.0, W, n, Q, ldq, 0.0, T, ldt, s, ms);
+  // (only T's upper triangle is formed: the tiles below the diagonal are skipped, then mirrored)
+  e = gemm<double>(false, false, n, n, n, 1.0, W, n, Q, ldq, 0.0, T, ldt, s, ms, kGemmCUpper);
   if (e) return e;
   hipLaunchKernelGGL(mirror_upper_kernel, dim3(cdiv(n, 256), n), dim3(256), 0, s, T, n, ldt);
   JAC_CHECK_LAUNCH();

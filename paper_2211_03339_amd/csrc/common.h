@@ -335,9 +335,13 @@ int svd_sweep(T* C, int ldc, int mrows, T* V, int ldv, int n, int np, T* Ebuf, i
 
 // GEMM (gemm.hip): C = alpha * op(A) * op(B) + beta * C, column-major.  max_split = 1 keeps K
 // whole (no split-K partial buffer, which is allocated on first need); 0 lets the GEMM choose.
+// tri: zero structure the product may skip (square operands, m = n = k): kGemmBUpper, op(B)(kk, j) =
+// 0 for kk > j; kGemmALower, op(A)(i, kk) = 0 for kk > i; kGemmCUpper, only C(i, j) with i <= j
+// is wanted (tiles wholly below the diagonal are written as alpha * 0, i.e. beta C).
+constexpr int kGemmBUpper = 1, kGemmALower = 2, kGemmCUpper = 4;
 template <typename T>
 int gemm(bool ta, bool tb, int m, int n, int k, T alpha, const T* A, int lda, const T* B, int ldb,
-         T beta, T* C, int ldc, hipStream_t s, int max_split = 0);
+         T beta, T* C, int ldc, hipStream_t s, int max_split = 0, int tri = 0);
 // count independent products C_z = alpha op(A_z) op(B_z) + beta C_z with A_z = A + z sA (and so on);
 // state (device, may be NULL): product z runs only when state[z] <= state_max.
 template <typename T>

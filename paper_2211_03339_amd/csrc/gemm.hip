@@ -21,7 +21,7 @@ constexpr int kPad = 4;
 template <typename T, int BM, int BN, bool TA, bool TB, bool BAT = false>
 __global__ void __launch_bounds__(256)
 gemm_kernel(int m, int n, int k, T alpha, const T* __restrict__ A, int lda, const T* __restrict__ B, int ldb,
-            T beta, T* __restrict__ C, int ldc, int kchunk, T* __restrict__ part, long long sA = 0,
+            T beta, T* __restrict__ C, int ldc, int kchunk, T* __restrict__ part, int tri, long long sA = 0,
             long long sB = 0, long long sC = 0, const int* __restrict__ state = nullptr, int state_max = 0) {
   if (BAT) {   // product z of a strided batch; skipped when its state exceeds state_max
     const int z = blockIdx.z;
@@ -42,7 +42,12 @@ gemm_kernel(int m, int n, int k, T alpha, const T* __restrict__ A, int lda, cons
   const int wm = wave >> 1, wn = wave & 1;
   const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
   const int kb = BAT ? 0 : blockIdx.z * kchunk;
-  const int ke = BAT ? k : min(k, kb + kchunk);
+  int ke = BAT ? k : min(k, kb + kchunk);
+  // zero structure (tri): the K range that can contribute to this tile; a tile wholly below the
+  // diagonal of an upper-only product gets none (and is written as zeros)
+  if (tri & kGemmBUpper) ke = min(ke, j0 + BN);
+  if (tri & kGemmALower) ke = min(ke, i0 + BM);
+  if ((tri & kGemmCUpper) && i0 >= j0 + BN) ke = kb;
 
   acc_t acc[TM][TN];
 #pragma unroll
@@ -158,10 +163,10 @@ static inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b)
 
 template <typename T, int BM, int BN>
 static void launch_cfg(bool ta, bool tb, dim3 grid, hipStream_t s, int m, int n, int k, T alpha, const T* A,
-                       int lda, const T* B, int ldb, T beta, T* C, int ldc, int kchunk, T* part) {
+                       int lda, const T* B, int ldb, T beta, T* C, int ldc, int kchunk, T* part, int tri) {
 #define L(TA_, TB_)                                                                                       \
   hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TA_, TB_>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, B, \
-                     ldb, beta, C, ldc, kchunk, part)
+                     ldb, beta, C, ldc, kchunk, part, tri)
   if (!ta && !tb) L(false, false);
   else if (ta && !tb) L(true, false);
   else if (!ta && tb) L(false, true);
@@ -176,7 +181,7 @@ static size_t g_part_bytes = 0;
 // max_split = 1: never split K (no partial-sum buffer, so nothing is allocated).
 template <typename T>
 int gemm(bool ta, bool tb, int m, int n, int k, T alpha, const T* A, int lda, const T* B, int ldb, T beta,
-         T* C, int ldc, hipStream_t s, int max_split) {
+         T* C, int ldc, hipStream_t s, int max_split, int tri) {
   if (m <= 0 || n <= 0) return 0;
   if (k <= 0) {
     // C = beta C
@@ -216,10 +221,10 @@ int gemm(bool ta, bool tb, int m, int n, int k, T alpha, const T* A, int lda, co
     part = static_cast<T*>(g_part);
   }
   dim3 grid(cdiv(m, BM), cdiv(n, BN), S);
-  if (BM == 64 && BN == 64) launch_cfg<T, 64, 64>(ta, tb, grid, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
-  else if (BM == 32 && BN == 64) launch_cfg<T, 32, 64>(ta, tb, grid, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
-  else if (BM == 64 && BN == 32) launch_cfg<T, 64, 32>(ta, tb, grid, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
-  else launch_cfg<T, 32, 32>(ta, tb, grid, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part);
+  if (BM == 64 && BN == 64) launch_cfg<T, 64, 64>(ta, tb, grid, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tri);
+  else if (BM == 32 && BN == 64) launch_cfg<T, 32, 64>(ta, tb, grid, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tri);
+  else if (BM == 64 && BN == 32) launch_cfg<T, 64, 32>(ta, tb, grid, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tri);
+  else launch_cfg<T, 32, 32>(ta, tb, grid, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, tri);
   JAC_CHECK_LAUNCH();
   if (S > 1) {
     hipLaunchKernelGGL((splitk_reduce_kernel<T>), dim3(cdiv(m, 256), n), dim3(256), 0, s, part, S, m, n, beta, C,
@@ -242,7 +247,7 @@ int gemm_batched(bool ta, bool tb, int m, int n, int k, T alpha, const T* A, int
   dim3 grid(cdiv(m, BM), cdiv(n, BN), count);
 #define LB(BM_, BN_, TA_, TB_)                                                                                    \
   hipLaunchKernelGGL((gemm_kernel<T, BM_, BN_, TA_, TB_, true>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, B, \
-                     ldb, beta, C, ldc, k, (T*)nullptr, sA, sB, sC, state, state_max)
+                     ldb, beta, C, ldc, k, (T*)nullptr, 0, sA, sB, sC, state, state_max)
 #define LT(BM_, BN_)                          \
   if (!ta && !tb) LB(BM_, BN_, false, false); \
   else if (ta && !tb) LB(BM_, BN_, true, false); \
@@ -263,8 +268,8 @@ template int gemm_batched<double>(bool, bool, int, int, int, double, const doubl
                                   hipStream_t);
 
 template int gemm<double>(bool, bool, int, int, int, double, const double*, int, const double*, int, double,
-                          double*, int, hipStream_t, int);
+                          double*, int, hipStream_t, int, int);
 template int gemm<float>(bool, bool, int, int, int, float, const float*, int, const float*, int, float, float*,
-                         int, hipStream_t, int);
+                         int, hipStream_t, int, int);
 
 }  // namespace jac

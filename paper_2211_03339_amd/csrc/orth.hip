@@ -47,8 +47,9 @@ __global__ __launch_bounds__(256) void orth_f0_kernel(const double* __restrict__
   const int j = blockIdx.y;
   double acc = 0.0;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const double e = G[i + (size_t)j * n] - (i == j ? 1.0 : 0.0);
-    acc += e * e;
+    // only G's upper triangle is formed (G is symmetric): off-diagonal entries count twice
+    const double e = i <= j ? G[i + (size_t)j * n] - (i == j ? 1.0 : 0.0) : 0.0;
+    acc += (i < j ? 2.0 : 1.0) * (e * e);
     F[i + (size_t)j * n] = i < j ? e : (i == j ? 0.5 * e : 0.0);
   }
   red[threadIdx.x] = acc;
@@ -111,7 +112,7 @@ int orth_series_f64(double* Z, int n, int ldz, double* B1, double* B2, double* B
   auto measure = [&](double& e2) -> int {
     hipLaunchKernelGGL(orth_transpose_kernel, tg, dim3(256), 0, s, (const double*)Z, n, ldz, B1, n);
     JAC_CHECK_LAUNCH();
-    int e = gemm<double>(false, false, n, n, n, 1.0, B1, n, Z, ldz, 0.0, B2, n, s, ms);
+    int e = gemm<double>(false, false, n, n, n, 1.0, B1, n, Z, ldz, 0.0, B2, n, s, ms, kGemmCUpper);
     if (e) return e;
     hipLaunchKernelGGL(orth_f0_kernel, dim3(gx, n), dim3(256), 0, s, (const double*)B2, n, B3, part);
     JAC_CHECK_LAUNCH();
@@ -126,13 +127,16 @@ int orth_series_f64(double* Z, int n, int ldz, double* B1, double* B2, double* B
   auto apply = [&]() -> int {
     hipLaunchKernelGGL(orth_transpose_kernel, tg, dim3(256), 0, s, (const double*)B3, n, n, B1, n);
     JAC_CHECK_LAUNCH();
-    int e = gemm<double>(false, false, n, n, n, 1.0, B1, n, B3, n, 0.0, B4, n, s, ms);
+    // F0^T F0 (F0^T lower, F0 upper triangular; only its upper triangle is used), then Z F and
+    // (Z F) F with F upper triangular: the GEMMs skip the zero blocks
+    int e = gemm<double>(false, false, n, n, n, 1.0, B1, n, B3, n, 0.0, B4, n, s, ms,
+                         kGemmALower | kGemmBUpper | kGemmCUpper);
     if (e) return e;
     hipLaunchKernelGGL(orth_f1_kernel, eg, dim3(256), 0, s, (const double*)B2, (const double*)B4, n, B3);
     JAC_CHECK_LAUNCH();
-    e = gemm<double>(false, false, n, n, n, 1.0, Z, ldz, B3, n, 0.0, B1, n, s, ms);
+    e = gemm<double>(false, false, n, n, n, 1.0, Z, ldz, B3, n, 0.0, B1, n, s, ms, kGemmBUpper);
     if (e) return e;
-    e = gemm<double>(false, false, n, n, n, 1.0, B1, n, B3, n, 0.0, B2, n, s, ms);
+    e = gemm<double>(false, false, n, n, n, 1.0, B1, n, B3, n, 0.0, B2, n, s, ms, kGemmBUpper);
     if (e) return e;
     hipLaunchKernelGGL(orth_combine_kernel, eg, dim3(256), 0, s, Z, n, ldz, (const double*)B1, (const double*)B2);
     JAC_CHECK_LAUNCH();
