@@ -57,7 +57,20 @@ gemm_kernel(int m, int n, int k, T alpha, const T* __restrict__ A, int lda, cons
 
   T ra[LA], rb[LB];
   // op(A)[i][kk]: TA ? A[kk + i*lda] : A[i + kk*lda]
+  // A stage wholly inside the matrix and the K range (the same for every thread, so one scalar
+  // branch) is loaded without the per-element checks.
   auto load_a = [&](int kt) {
+    if (i0 + BM <= m && kt + kBK <= ke) {
+#pragma unroll
+      for (int e = 0; e < LA; ++e) {
+        int idx = tid + e * 256;
+        int ii, kk;
+        if (!TA) { ii = idx % BM; kk = idx / BM; } else { kk = idx % kBK; ii = idx / kBK; }
+        int gi = i0 + ii, gk = kt + kk;
+        ra[e] = TA ? A[gk + (size_t)gi * lda] : A[gi + (size_t)gk * lda];
+      }
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < LA; ++e) {
       int idx = tid + e * 256;
@@ -68,6 +81,17 @@ gemm_kernel(int m, int n, int k, T alpha, const T* __restrict__ A, int lda, cons
     }
   };
   auto load_b = [&](int kt) {
+    if (j0 + BN <= n && kt + kBK <= ke) {
+#pragma unroll
+      for (int e = 0; e < LB; ++e) {
+        int idx = tid + e * 256;
+        int jj, kk;
+        if (!TB) { kk = idx % kBK; jj = idx / kBK; } else { jj = idx % BN; kk = idx / BN; }
+        int gj = j0 + jj, gk = kt + kk;
+        rb[e] = TB ? B[gj + (size_t)gk * ldb] : B[gk + (size_t)gj * ldb];
+      }
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < LB; ++e) {
       int idx = tid + e * 256;
