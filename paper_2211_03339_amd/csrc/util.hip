@@ -131,19 +131,36 @@ int copy_convert(const Tin* A, int m, int n, int lda, Tout* B, int ldb, hipStrea
 }
 
 // Ascending order with ties kept in index order: rank(i) = #{j : d_j < d_i or
-// (d_j == d_i and j < i)}.
+// (d_j == d_i and j < i)}.  A workgroup of 256 threads ranks 32 values: the d_j pass through LDS
+// in chunks of 256, each of the 8 32-lane groups counts one eighth of every chunk, and the 8
+// partial counts of a value are summed at the end (integer counts: the order does not matter).
 template <typename T>
-__global__ void rank_kernel(const T* __restrict__ d, int n, int* __restrict__ rank, double* __restrict__ W) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  T di = d[i];
+__global__ void __launch_bounds__(256) rank_kernel(const T* __restrict__ d, int n, int* __restrict__ rank,
+                                                   double* __restrict__ W) {
+  __shared__ T dc[256];
+  __shared__ int part[8][32];
+  const int tid = threadIdx.x, il = tid & 31, js = tid >> 5;
+  const int i = blockIdx.x * 32 + il;
+  const T di = i < n ? d[i] : T(0);
   int r = 0;
-  for (int j = 0; j < n; ++j) {
-    T dj = d[j];
-    r += (dj < di) || (dj == di && j < i);
+  for (int c = 0; c < n; c += 256) {
+    __syncthreads();
+    if (c + tid < n) dc[tid] = d[c + tid];
+    __syncthreads();
+    const int j0 = c + js * 32, cnt = min(32, n - j0);
+    for (int q = 0; q < cnt; ++q) {
+      const T dj = dc[js * 32 + q];
+      r += (dj < di) || (dj == di && j0 + q < i);
+    }
   }
-  rank[i] = r;
-  W[r] = (double)di;
+  part[js][il] = r;
+  __syncthreads();
+  if (js == 0 && i < n) {
+#pragma unroll
+    for (int g = 1; g < 8; ++g) r += part[g][il];
+    rank[i] = r;
+    W[r] = (double)di;
+  }
 }
 
 template <typename T>
@@ -158,7 +175,7 @@ template <typename T>
 int sort_eigs(const T* d, const T* Vw, int n, int ldw, double* W, double* Vout, int ldv, int* rank,
               hipStream_t s) {
   if (n == 0) return 0;
-  hipLaunchKernelGGL((rank_kernel<T>), dim3(cdiv(n, 256)), dim3(256), 0, s, d, n, rank, W);
+  hipLaunchKernelGGL((rank_kernel<T>), dim3(cdiv(n, 32)), dim3(256), 0, s, d, n, rank, W);
   JAC_CHECK_LAUNCH();
   if (Vout) {
     hipLaunchKernelGGL((permute_cols_kernel<T>), dim3(cdiv(n, 256), n), dim3(256), 0, s, Vw, ldw, rank, n,

@@ -152,6 +152,20 @@ def test_empty_and_diagonal():
     assert np.all(host(W) == 0) and st["sweeps"] == 0
 
 
+
+@pytest.mark.parametrize("n", [37, 600])
+def test_output_order_ties_by_index(n):
+    """Eigenvalues leave in ascending order and equal ones in index order (the ranking spans
+    several workgroups and LDS chunks at n = 600): a diagonal input with many repeated values
+    needs no rotation, so W and V are the stable sort of its diagonal and of the identity."""
+    g = np.random.default_rng(600 + n)
+    dvals = g.choice([-1.0, 0.0, 0.5, 2.0], size=n)
+    W, V, st, info = jacobi.syev_jacobi_ex(dev(np.diag(dvals)), precond="none")
+    assert info == 0 and st["sweeps"] == 0
+    order = np.argsort(dvals, kind="stable")
+    np.testing.assert_array_equal(host(W), dvals[order])
+    np.testing.assert_array_equal(np.abs(host(V)), np.eye(n)[:, order])
+
 def test_error_codes():
     A, _ = tm.sym_matrix(8, "uniform", seed=1)
     bad = A.copy()
