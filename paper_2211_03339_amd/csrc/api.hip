@@ -717,11 +717,13 @@ static int syev_impl(const double* A, int n, int lda, const double* Q0, int ldq,
     }
     e = elem_pack<double>(st, T0, n, 0, s);
     if (e) return e;
-    JAC_HIP(hipMemcpyAsync(&hflag, hd.flag, 4, hipMemcpyDeviceToHost, s));
-    JAC_HIP(hipStreamSynchronize(s));
-    if (hflag) {
-      set_error("syev_jacobi: modified Gram-Schmidt met a zero column");
-      return 3;
+    if (!mgs_done) {   // (after an early step 2 the flag was read already and nothing since sets it)
+      JAC_HIP(hipMemcpyAsync(&hflag, hd.flag, 4, hipMemcpyDeviceToHost, s));
+      JAC_HIP(hipStreamSynchronize(s));
+      if (hflag) {
+        set_error("syev_jacobi: modified Gram-Schmidt met a zero column");
+        return 3;
+      }
     }
     tm.mark(4);
   }
