@@ -1206,11 +1206,12 @@ static int td_vectors(const double* d, const double* e, int n, const double* w, 
 }
 
 // Step 1d: Y (n x n, ld n) <- H_0 ... H_{n-3} Y, in FP64 on the matrix cores: per block of kBtNb
-// reflectors its Gram Ub^T Ub and triangular factor Tb, then Y -= Ub (Tb (Ub^T Y)).
-// Step 1d, first part: the Gram matrix and triangular factor of every reflector block (they
-// depend on the reflectors only).
-static int td_bt_factors(const double* U, const double* Ut, int nbp, const float* tau, int n, double* Gb,
-                         double* Tf, hipStream_t s, bool no_split) {
+// reflectors its Gram Ub^T Ub and triangular factor Tb, then Y -= Ub (Tb Ub^T) Y.
+// Step 1d, first part (it depends on the reflectors only): the Gram matrix and triangular factor
+// of every reflector block, then the rows of Ut (Ub^T) replaced by Tb Ub^T, so that the second
+// part needs two products per block instead of three.  Wb (kBtNb x n) is scratch.
+static int td_bt_factors(const double* U, double* Ut, int nbp, const float* tau, int n, double* Gb, double* Tf,
+                         double* Wb, hipStream_t s, bool no_split) {
   const int nref = n > 2 ? n - 2 : 0;
   if (nref == 0) return 0;
   const int nblk = tcdiv(nref, kBtNb);
@@ -1225,23 +1226,28 @@ static int td_bt_factors(const double* U, const double* Ut, int nbp, const float
   JAC_HIP(hipFuncSetAttribute((const void*)bt_tfactor_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tsh));
   hipLaunchKernelGGL(bt_tfactor_kernel, dim3(nblk), dim3(256), tsh, s, Gb, tau, nref, Tf);
   JAC_CHECK_LAUNCH();
+  for (int b = 0; b < nblk; ++b) {
+    const int k0 = b * kBtNb, r0 = k0 + 1, m = n - r0;
+    double* Utb = Ut + k0 + (size_t)r0 * nbp;
+    int e1 = gemm<double>(false, false, kBtNb, m, kBtNb, 1.0, Tf + (size_t)b * kBtNb * kBtNb, kBtNb, Utb, nbp, 0.0, Wb,
+                          kBtNb, s, msplit);
+    if (!e1) e1 = copy_convert<double, double>(Wb, kBtNb, m, kBtNb, Utb, nbp, s);
+    if (e1) return e1;
+  }
   return 0;
 }
 
-// Step 1d, second part: Y <- H_0 ... H_(n-3) Y, block by block from the last.
-static int td_bt_apply(const double* U, const double* Ut, int nbp, int n, const double* Tf, double* Wb, double* W2,
-                       double* Y, hipStream_t s, bool no_split) {
+// Step 1d, second part: Y <- H_0 ... H_{n-3} Y, block by block from the last (Ut holds Tb Ub^T).
+static int td_bt_apply(const double* U, const double* Ut, int nbp, int n, double* W2, double* Y, hipStream_t s,
+                       bool no_split) {
   const int nref = n > 2 ? n - 2 : 0;
   if (nref == 0) return 0;
   const int nblk = tcdiv(nref, kBtNb);
   const int msplit = no_split ? 1 : 0;
   for (int b = nblk - 1; b >= 0; --b) {
     const int k0 = b * kBtNb, r0 = k0 + 1, m = n - r0;
-    int e1 = gemm<double>(false, false, kBtNb, n, m, 1.0, Ut + k0 + (size_t)r0 * nbp, nbp, Y + r0, n, 0.0, Wb, kBtNb,
+    int e1 = gemm<double>(false, false, kBtNb, n, m, 1.0, Ut + k0 + (size_t)r0 * nbp, nbp, Y + r0, n, 0.0, W2, kBtNb,
                           s, msplit);
-    if (e1) return e1;
-    e1 = gemm<double>(false, false, kBtNb, n, kBtNb, 1.0, Tf + (size_t)b * kBtNb * kBtNb, kBtNb, Wb, kBtNb, 0.0, W2,
-                      kBtNb, s, msplit);
     if (e1) return e1;
     e1 = gemm<double>(false, false, m, n, kBtNb, -1.0, U + r0 + (size_t)k0 * n, n, W2, kBtNb, 1.0, Y + r0, n, s,
                       msplit);
@@ -1250,11 +1256,11 @@ static int td_bt_apply(const double* U, const double* Ut, int nbp, int n, const 
   return 0;
 }
 
-static int td_backtransform(const double* U, const double* Ut, int nbp, const float* tau, int n, double* Gb,
+static int td_backtransform(const double* U, double* Ut, int nbp, const float* tau, int n, double* Gb,
                             double* Tf, double* Wb, double* W2, double* Y, hipStream_t s, bool no_split) {
-  int e = td_bt_factors(U, Ut, nbp, tau, n, Gb, Tf, s, no_split);
+  int e = td_bt_factors(U, Ut, nbp, tau, n, Gb, Tf, Wb, s, no_split);
   if (e) return e;
-  return td_bt_apply(U, Ut, nbp, n, Tf, Wb, W2, Y, s, no_split);
+  return td_bt_apply(U, Ut, nbp, n, W2, Y, s, no_split);
 }
 
 // FP32 eigenvectors of A (n x n, FP64 or FP32, lda) through the tridiagonal route.  Z (FP64,
@@ -1298,7 +1304,7 @@ int eig_tridiag_f32(const TA* A, int n, int lda, double* Z, int ldz, double* w_o
     if (!e) e = hip_ok(hipStreamWaitEvent(s2, fork, 0), "hipStreamWaitEvent");
     if (e) { release(); return e; }
   }
-  e = td_bt_factors(k.U, k.Ut, k.nbp, k.tau, n, k.G, k.Tf, s2 ? s2 : s, no_split);
+  e = td_bt_factors(k.U, k.Ut, k.nbp, k.tau, n, k.G, k.Tf, k.Wb, s2 ? s2 : s, no_split);
   if (!e && s2) e = hip_ok(hipEventRecord(join, s2), "hipEventRecord");
   if (!e) e = td_eigvals(k.d, k.e, n, k.bnd, k.w, s);
   if (!e) e = td_vectors<double>(k.d, k.e, n, k.w, k.bnd, k.dp, k.dm, k.nc, k.Y, n, s);
@@ -1308,7 +1314,7 @@ int eig_tridiag_f32(const TA* A, int n, int lda, double* Z, int ldz, double* w_o
     release();
     return e;
   }
-  e = td_bt_apply(k.U, k.Ut, k.nbp, n, k.Tf, k.Wb, k.W2, k.Y, s, no_split);
+  e = td_bt_apply(k.U, k.Ut, k.nbp, n, k.W2, k.Y, s, no_split);
   release();   // (destroying a stream whose work is queued or waited on is allowed; it completes)
   if (e) return e;
   e = copy_convert<double, double>(k.Y, n, n, n, Z, ldz, s);
