@@ -49,16 +49,24 @@ KERNEL_OF = {"tridiag_reduce": ("sytrd_reg_kernel",),
              "update32": ("blk_update16_kernel<float",),
              "elem64": ("elem_step_kernel<double",), "elem32": ("elem_step_kernel<float",)}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_n2048.json")
+# the source file that holds each class's kernels (its digest at counter time gates the figure)
+SOURCE_OF = {"tridiag_reduce": "tridiag.hip", "tridiag_rest": "tridiag.hip", "inner64": "blocked.hip",
+             "update64": "blocked.hip", "inner32": "blocked.hip", "update32": "blocked.hip",
+             "elem64": "elem.hip", "elem32": "elem.hip"}
 
 
 def measured_traffic(cls: str):
     """HBM bytes per launch of a kernel class from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary (copy-kernel scaled), or None when there is none or the kernel source changed since."""
+    summary (copy-kernel scaled), or None when there is none or the source file that holds the
+    class's kernels changed since the counters were taken."""
     import hashlib
     try:
         t = json.load(open(TRAFFIC_FILE))
-        for src, digest in t["sources"].items():
-            if hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != digest:
+        gated = [src for src in t["sources"] if os.path.basename(src) == SOURCE_OF.get(cls)]
+        if not gated:
+            return None
+        for src in gated:
+            if hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != t["sources"][src]:
                 return None
         sel = [v for k, v in t["kernels"].items() if any(p in k for p in KERNEL_OF.get(cls, ()))]
         calls = sum(v["dispatches"] for v in sel)
